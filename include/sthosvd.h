@@ -1,0 +1,223 @@
+/*
+ * sthosvd.h -- C ABI of the MI355X (gfx950) st-HOSVD library.
+ *
+ * Sequentially truncated HOSVD of a dense tensor (Alg. 2 of the a-Tucker
+ * paper, arXiv 2010.10131): for each mode n, form the mode-n Gram matrix
+ * without explicit matricization and take its R_n leading eigenvectors
+ * (EIG branch), or run the ALS factor solver (ALS branch, Alg. 3); then shrink
+ * the working tensor with a matricization-free TTM.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Layout.  Tensors are dense and column-major: the first index varies fastest
+ *   (Sec. II-A, Sec. V).  For dims I_1..I_N the element (i_1..i_N) sits at
+ *   offset sum_k i_k * prod_{m<k} I_m.  For mode n the library views a tensor
+ *   as (L, I_n, M) with L = prod_{m<n} I_m and M = prod_{m>n} I_m; nothing is
+ *   ever transposed or copied into a matricized form.  Factors U^(n) are
+ *   I_n x R_n column-major FP64; the core is R_1 x ... x R_N column-major.
+ *   Modes are 0-based in this API (mode 0 is the paper's mode 1).
+ * Data types.  A tensor is either FP64 or FP32 (sth_dtype).  Factors,
+ *   eigenvalues and Gram matrices are always FP64.
+ * Memory.  Every pointer named "device" is device memory allocated by the
+ *   caller (for instance through PyTorch); the library never allocates,
+ *   frees or retains caller memory.  Host arrays (dims, ranks, pointer
+ *   arrays) are read during the call only.  A plan owns host memory only.
+ * Streams.  sth_stream_t is a hipStream_t (NULL = the null stream).  Entry
+ *   points that launch work are enqueue-only: they return once the kernels are
+ *   queued, without synchronizing, unless stated otherwise.
+ * Errors.  Every call returns sth_status.  Arguments are validated before any
+ *   launch; on error nothing is launched and sth_last_error() returns a
+ *   thread-local description.  No C++ exception crosses this interface.
+ *   Numerical failures detected on the device (NaN/Inf input, eigensolver
+ *   sweep cap) are recorded in the workspace and reported by
+ *   sthosvd_check().
+ */
+#ifndef STHOSVD_H
+#define STHOSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *sth_stream_t; /* a hipStream_t */
+
+typedef enum {
+    STH_OK = 0,
+    STH_ERR_INVALID = 1,     /* bad order, dims, ranks, mode, enum value or NULL pointer */
+    STH_ERR_LAYOUT = 2,      /* misaligned pointer (device pointers must be 16-byte aligned) */
+    STH_ERR_NOMEM = 3,       /* workspace smaller than required, or over the plan's cap */
+    STH_ERR_HIP = 4,         /* a HIP runtime call or kernel launch failed */
+    STH_ERR_NUMERIC = 5,     /* NaN/Inf met, or the eigensolver hit its sweep cap */
+    STH_ERR_UNSUPPORTED = 6  /* a valid request this build does not implement */
+} sth_status;
+
+typedef enum { STH_F64 = 0, STH_F32 = 1 } sth_dtype;
+
+/* Arithmetic of a contraction (Gram, TTT or TTM).  Products are formed as
+ * stated and accumulated in FP32 within a chunk of at most 128 contraction
+ * steps, then in FP64 across chunks (FP64: FP64 throughout).
+ *   STH_PREC_FP64   FP64 products (FP32 data is widened exactly)
+ *   STH_PREC_FP32   FP32 products on the FP32 matrix cores
+ *   STH_PREC_BF16X3 x = hi + mid (two bf16, round to nearest even);
+ *                   x*y ~ hi*hi' + hi*mid' + mid*hi' on the bf16 matrix cores
+ *   STH_PREC_BF16X6 x = hi + mid + lo; the six products of order <= 2^-16
+ * FP64 data accepts only STH_PREC_FP64. */
+typedef enum {
+    STH_PREC_FP64 = 0,
+    STH_PREC_FP32 = 1,
+    STH_PREC_BF16X3 = 2,
+    STH_PREC_BF16X6 = 3
+} sth_prec;
+
+/* Solver for a mode (Alg. 2: method 0 = EIG, otherwise ALS). */
+typedef enum {
+    STH_SOLVER_EIG = 0,   /* Gram + FP64 eigensolver + TTM (Alg. 2 EIG branch) */
+    STH_SOLVER_ALS = 1,   /* Alg. 3 + QR + TTM (Alg. 2 ALS branch) */
+    STH_SOLVER_AUTO = 2   /* per-mode choice by the learned cost model (Sec. IV analogue) */
+} sth_solver;
+
+/* Description of one decomposition.  Zero-initialize and fill. */
+typedef struct {
+    int32_t order;             /* N, 1..8 */
+    const int64_t *dims;       /* host, N entries: I_1..I_N (>= 1) */
+    const int64_t *ranks;      /* host, N entries: 1 <= R_n <= I_n */
+    const int32_t *mode_order; /* host, N entries, a permutation of 0..N-1; NULL = 0,1,..,N-1 */
+    int32_t dtype;             /* sth_dtype of X, the working tensor and the core */
+    int32_t gram_prec;         /* sth_prec of the Gram / TTT contractions */
+    int32_t ttm_prec;          /* sth_prec of the TTM contractions */
+    int32_t solver;            /* sth_solver for every mode */
+    const int32_t *per_mode;   /* host, N entries of sth_solver (EIG/ALS) overriding solver; or NULL */
+    int32_t als_iters;         /* ALS sweeps (Alg. 3 loop count); 0 = 5 */
+    int32_t eig_max_sweeps;    /* Jacobi sweep cap; 0 = 60 */
+    int64_t workspace_cap;     /* bytes; 0 = no cap.  Plans needing more fail with STH_ERR_NOMEM */
+    const float *mlp_weights;  /* host, selector weights (sth_selector_num_params floats); NULL = built in */
+} sth_desc;
+
+typedef struct sth_plan_s sth_plan;
+
+/* Thread-local text of the last error (never NULL). */
+const char *sth_last_error(void);
+
+/* Library version string. */
+const char *sth_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Whole decomposition (Alg. 2).
+ * ------------------------------------------------------------------------- */
+
+/* Validates d, fixes the per-mode shapes (L_n, I_n, M_n, J_n on the current
+ * working tensor), the solver of every mode (the learned selector runs here,
+ * on the host, for STH_SOLVER_AUTO) and the workspace layout.  Host work only.
+ * *plan receives a new plan (free with sthosvd_plan_destroy); *workspace_bytes
+ * the device workspace sthosvd_run needs. */
+sth_status sthosvd_plan(const sth_desc *d, sth_plan **plan, size_t *workspace_bytes);
+
+/* Solver chosen for each mode of a plan (N entries of sth_solver, indexed by
+ * mode, not by step). */
+sth_status sthosvd_plan_solvers(const sth_plan *plan, int32_t *solvers_out);
+
+void sthosvd_plan_destroy(sth_plan *plan);
+
+/* Runs the decomposition of X (device, dims of the plan, plan dtype; read
+ * only).  core: device, prod R_n elements of the plan dtype.  U: host array of
+ * N device pointers, U[n] receives I_n x R_n FP64 (orthonormal columns).
+ * eigvals: NULL, or host array of N device pointers (entries may be NULL);
+ * for an EIG mode eigvals[n] receives the R_n leading eigenvalues of the
+ * mode-n Gram in descending order (FP64); untouched for ALS modes.
+ * als_init: NULL, or host array of N device pointers to I_n x R_n FP64 initial
+ * guesses L_0 for ALS modes (Alg. 3 input); NULL entries use a Gaussian guess
+ * drawn on the device from the counter-based generator seeded by
+ * (seed, mode).  workspace: device, >= the plan's workspace_bytes.
+ * Enqueue-only; the eigenvectors carry the sign convention "largest-magnitude
+ * entry positive". */
+sth_status sthosvd_run(const sth_plan *plan, const void *X, void *core, double *const *U,
+                       double *const *eigvals, const double *const *als_init, uint64_t seed,
+                       void *workspace, size_t workspace_bytes, sth_stream_t stream);
+
+/* Synchronizes the stream and reports numerical failures recorded in the
+ * workspace by the last run on it (STH_ERR_NUMERIC), then clears them. */
+sth_status sthosvd_check(const sth_plan *plan, void *workspace, sth_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Building blocks.  All act on one tensor Y with order/dims as above and
+ * mode n (0-based).
+ * ------------------------------------------------------------------------- */
+
+/* Device workspace (bytes) needed by gram_mode_n / ttt_mode_n for this shape. */
+size_t gram_mode_n_workspace(int32_t order, const int64_t *dims, int32_t n, int32_t other_rows);
+
+/* Mode-n Gram S = Y_(n) Y_(n)^T (Alg. 2 EIG branch; the special case
+ * TTT(Y, Y) of Eq. 3) without matricization.  Y: device, dtype.  S: device,
+ * I_n x I_n FP64, the full symmetric matrix is written.  ws: device scratch
+ * of gram_mode_n_workspace(order, dims, n, 0) bytes. */
+sth_status gram_mode_n(int32_t order, const int64_t *dims, int32_t n, int32_t dtype,
+                       int32_t prec, const void *Y, double *S, void *ws, size_t ws_bytes,
+                       sth_stream_t stream);
+
+/* Mode-n TTT (Eq. 3, read as a contraction over every mode but n):
+ * P = Y_(n) Z_(n)^T where Z has the dims of Y with dims[n] replaced by R.
+ * Y, Z: device, dtype.  P: device, I_n x R FP64.  ws: device scratch of
+ * gram_mode_n_workspace(order, dims, n, R) bytes. */
+sth_status ttt_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R, int32_t dtype,
+                      int32_t prec, const void *Y, const void *Z, double *P, void *ws,
+                      size_t ws_bytes, sth_stream_t stream);
+
+/* Device workspace (bytes) needed by ttm_mode_n for an I_n x R factor. */
+size_t ttm_mode_n_workspace(int64_t I, int64_t R);
+
+/* Mode-n TTM with the transpose of an I_n x R factor (Eq. 2 with the
+ * R x I_n matrix U^T; the core update of Alg. 2):
+ *   Z(a, r, b) = sum_i U(i, r) Y(a, i, b),
+ * Z has the dims of Y with dims[n] replaced by R, in the same column-major
+ * layout.  Y: device, dtype.  U: device, I_n x R FP64.  Z: device, dtype.
+ * ws: device scratch of ttm_mode_n_workspace(I_n, R) bytes.  transpose_u = 1
+ * takes U as R x I_n instead and applies it as is (Z = Y x_n U), which is the
+ * expansion step of the Tucker reconstruction. */
+sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R, int32_t dtype,
+                      int32_t prec, const void *Y, const double *U, int32_t transpose_u, void *Z,
+                      void *ws, size_t ws_bytes, sth_stream_t stream);
+
+/* R leading eigenpairs of a symmetric n x n FP64 matrix S (device), by a
+ * cyclic Jacobi eigensolver in FP64: U (device, n x R FP64, orthonormal,
+ * largest-magnitude entry of each column positive) and lam (device, R
+ * values, descending; may be NULL).  ws: device scratch of
+ * eig_leading_workspace(n) bytes; an exceeded sweep cap is recorded in the
+ * first 8 bytes of ws as a non-zero int64. */
+size_t eig_leading_workspace(int64_t n);
+sth_status eig_leading(int64_t n, int64_t R, const double *S, double *U, double *lam,
+                       int32_t max_sweeps, void *ws, size_t ws_bytes, sth_stream_t stream);
+
+/* Tucker reconstruction X^ = G x_1 U1 x_2 ... x_N UN (Sec. II-B).
+ * G: device, prod ranks, dtype.  U: host array of N device pointers to
+ * I_n x R_n FP64.  Xhat: device, prod dims, dtype.  ws: device scratch of
+ * tucker_reconstruct_workspace(...) bytes. */
+size_t tucker_reconstruct_workspace(int32_t order, const int64_t *dims, const int64_t *ranks,
+                                    int32_t dtype);
+sth_status tucker_reconstruct(int32_t order, const int64_t *dims, const int64_t *ranks,
+                              int32_t dtype, int32_t prec, const void *G, const double *const *U,
+                              void *Xhat, void *ws, size_t ws_bytes, sth_stream_t stream);
+
+/* Relative-error terms of a decomposition (Sec. VI-B metric): writes
+ * out[0] = ||X - X^||_F^2 and out[1] = ||X||_F^2 (device, 2 FP64), both
+ * accumulated in FP64, with X^ the reconstruction of (G, U).  The
+ * reconstruction is formed in ws (tucker_reconstruct_workspace bytes plus
+ * prod dims elements of dtype). */
+size_t tucker_error_workspace(int32_t order, const int64_t *dims, const int64_t *ranks,
+                              int32_t dtype);
+sth_status tucker_error(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype,
+                        int32_t prec, const void *X, const void *G, const double *const *U,
+                        double *out, void *ws, size_t ws_bytes, sth_stream_t stream);
+
+/* FP64 sum of squares of a device array of count elements (Eq. 1 squared):
+ * out (device, 1 FP64). ws: 8 * 1024 bytes. */
+sth_status sth_sumsq(int32_t dtype, const void *x, int64_t count, double *out, void *ws,
+                     size_t ws_bytes, sth_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STHOSVD_H */

@@ -35,10 +35,10 @@ _ip = ctypes.POINTER(ctypes.c_int)
 
 
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP) into oracle/liboracle.so."""
+    """Compile the oracle with gcc (-O3, OpenMP) into oracle/liboracle.so."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-fPIC", "-shared", "-std=c99",
                                _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB

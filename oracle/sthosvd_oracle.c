@@ -144,24 +144,34 @@ void orc_matmul_tn(i64 m, i64 n, i64 k, const double *A, const double *B, double
 
 /* C (m x n) = A B with A (m x k), B (k x n). */
 void orc_matmul_nn(i64 m, i64 n, i64 k, const double *A, const double *B, double *C) {
-#pragma omp parallel for collapse(2) schedule(static)
-    for (i64 j = 0; j < n; ++j)
-        for (i64 i = 0; i < m; ++i) {
-            double s = 0.0;
-            for (i64 p = 0; p < k; ++p) s += A[i + m * p] * B[p + k * j];
-            C[i + m * j] = s;
+    /* each C(i, j) is summed over p in increasing order; the loops are
+     * interchanged only so that columns of A and C are walked contiguously */
+#pragma omp parallel for schedule(static)
+    for (i64 j = 0; j < n; ++j) {
+        double *c = C + m * j;
+        for (i64 i = 0; i < m; ++i) c[i] = 0.0;
+        for (i64 p = 0; p < k; ++p) {
+            const double b = B[p + k * j];
+            const double *a = A + m * p;
+            for (i64 i = 0; i < m; ++i) c[i] += a[i] * b;
         }
+    }
 }
 
 /* C (m x n) = A B^T with A (m x k), B (n x k). */
 void orc_matmul_nt(i64 m, i64 n, i64 k, const double *A, const double *B, double *C) {
-#pragma omp parallel for collapse(2) schedule(static)
-    for (i64 j = 0; j < n; ++j)
-        for (i64 i = 0; i < m; ++i) {
-            double s = 0.0;
-            for (i64 p = 0; p < k; ++p) s += A[i + m * p] * B[j + n * p];
-            C[i + m * j] = s;
+    /* each C(i, j) is summed over p in increasing order (loop interchange as
+     * in orc_matmul_nn) */
+#pragma omp parallel for schedule(static)
+    for (i64 j = 0; j < n; ++j) {
+        double *c = C + m * j;
+        for (i64 i = 0; i < m; ++i) c[i] = 0.0;
+        for (i64 p = 0; p < k; ++p) {
+            const double b = B[j + n * p];
+            const double *a = A + m * p;
+            for (i64 i = 0; i < m; ++i) c[i] += a[i] * b;
         }
+    }
 }
 
 /* Gram S = Yn Yn^T of an I x J matrix (Alg. 2 EIG branch; Gram = TTT(Y, Y)). */

@@ -1,0 +1,584 @@
+// Host side of the C ABI: validation, plans, workspace layout and the
+// mode-wise driver of Alg. 2 (EIG branch: Gram -> FP64 eigensolver -> TTM;
+// ALS branch: Alg. 3 sweeps -> QR -> TTM).  Every numeric step runs in the
+// library's HIP kernels; this file only computes shapes and enqueues work.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/sthosvd.h"
+#include "internal.h"
+#include "selector.h"
+
+using namespace sth;
+
+// ------------------------------------------------------------ errors ----
+
+static thread_local std::string g_err = "no error";
+
+static sth_status fail(sth_status st, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+static sth_status hip_fail(hipError_t e, const char *what) {
+    return fail(STH_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(expr, what)                       \
+    do {                                         \
+        hipError_t _e = (expr);                  \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+extern "C" const char *sth_last_error(void) { return g_err.c_str(); }
+extern "C" const char *sth_version(void) { return "sthosvd-gfx950 0.1"; }
+
+namespace sth {
+int device_cu_count() {
+    static std::mutex mu;
+    static int cache[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache[dev] == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
+            cu = 256;
+        cache[dev] = cu;
+    }
+    return cache[dev];
+}
+}  // namespace sth
+
+// ------------------------------------------------------- validation ----
+
+static const int MAX_ORDER = 8;
+static const int64_t MAX_EIG_N = 512;   // Jacobi kernel limit (one workgroup)
+static const int64_t MAX_ALS_R = 128;   // R x R Cholesky in LDS
+
+static size_t esize(int dtype) { return dtype == STH_F64 ? 8 : 4; }
+static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static sth_status check_shape(int32_t order, const int64_t *dims) {
+    if (order < 1 || order > MAX_ORDER) return fail(STH_ERR_INVALID, "order %d outside 1..%d", order, MAX_ORDER);
+    if (!dims) return fail(STH_ERR_INVALID, "dims is NULL");
+    double numel = 1.0;
+    for (int k = 0; k < order; ++k) {
+        if (dims[k] < 1) return fail(STH_ERR_INVALID, "dims[%d] = %lld < 1", k, (long long)dims[k]);
+        numel *= (double)dims[k];
+    }
+    if (numel > 9.0e15) return fail(STH_ERR_INVALID, "tensor too large");
+    return STH_OK;
+}
+
+static sth_status check_dtype_prec(int32_t dtype, int32_t prec, const char *what) {
+    if (dtype != STH_F64 && dtype != STH_F32) return fail(STH_ERR_INVALID, "dtype %d", dtype);
+    if (prec < STH_PREC_FP64 || prec > STH_PREC_BF16X6) return fail(STH_ERR_INVALID, "%s %d", what, prec);
+    if (dtype == STH_F64 && prec != STH_PREC_FP64)
+        return fail(STH_ERR_INVALID, "FP64 data needs %s = STH_PREC_FP64", what);
+    return STH_OK;
+}
+
+static sth_status check_ptr(const void *p, const char *what, bool allow_null = false) {
+    if (!p) return allow_null ? STH_OK : fail(STH_ERR_INVALID, "%s is NULL", what);
+    if (reinterpret_cast<uintptr_t>(p) & 15) return fail(STH_ERR_LAYOUT, "%s is not 16-byte aligned", what);
+    return STH_OK;
+}
+
+// (L, I, M) of mode n
+static void lim(int order, const int64_t *dims, int n, int64_t &L, int64_t &I, int64_t &M) {
+    L = 1;
+    M = 1;
+    for (int k = 0; k < n; ++k) L *= dims[k];
+    I = dims[n];
+    for (int k = n + 1; k < order; ++k) M *= dims[k];
+}
+
+// -------------------------------------------------------------- plan ----
+
+struct Step {
+    int n;
+    int64_t L, I, M, R;
+    int solver;
+    int src, dst;  // 0 = X, 1 = buffer A, 2 = buffer B, 3 = core
+};
+
+struct Arena {
+    size_t off = 0;
+    size_t take(size_t bytes) {
+        size_t o = off;
+        off += align_up(bytes);
+        return o;
+    }
+};
+
+struct sth_plan_s {
+    int N;
+    std::vector<int64_t> dims, ranks;
+    std::vector<int> order;
+    int dtype, gram_prec, ttm_prec, als_iters, max_sweeps;
+    std::vector<Step> steps;
+    std::vector<int> solver_of_mode;
+    // workspace offsets
+    size_t o_flag, o_bufA, o_bufB, o_bufZ, o_part, o_S, o_eig, o_uq, o_small, o_gemm, o_sum, total;
+    size_t small_bytes;
+};
+
+static int ttm_prec_of(const sth_plan_s &p) { return p.dtype == STH_F64 ? STH_PREC_FP64 : p.ttm_prec; }
+static int gram_prec_of(const sth_plan_s &p) { return p.dtype == STH_F64 ? STH_PREC_FP64 : p.gram_prec; }
+
+// ALS small-matrix scratch (doubles): Q, P, Lk, T1 (I x R each); C, Rc, Rcinv,
+// G2, R1, R1inv, R2, R2inv, Rhat (R x R each); L0 (I x R).
+static size_t als_small_doubles(int64_t I, int64_t R) { return (size_t)(5 * I * R + 9 * R * R); }
+
+extern "C" sth_status sthosvd_plan(const sth_desc *d, sth_plan **plan_out, size_t *ws_out) {
+    if (!d || !plan_out || !ws_out) return fail(STH_ERR_INVALID, "NULL argument");
+    *plan_out = nullptr;
+    sth_status st = check_shape(d->order, d->dims);
+    if (st) return st;
+    if (!d->ranks) return fail(STH_ERR_INVALID, "ranks is NULL");
+    const int N = d->order;
+    for (int k = 0; k < N; ++k)
+        if (d->ranks[k] < 1 || d->ranks[k] > d->dims[k])
+            return fail(STH_ERR_INVALID, "ranks[%d] = %lld outside 1..%lld", k, (long long)d->ranks[k], (long long)d->dims[k]);
+    if ((st = check_dtype_prec(d->dtype, d->gram_prec, "gram_prec"))) return st;
+    if ((st = check_dtype_prec(d->dtype, d->ttm_prec, "ttm_prec"))) return st;
+    std::vector<int> order(N);
+    if (d->mode_order) {
+        std::vector<int> seen(N, 0);
+        for (int k = 0; k < N; ++k) {
+            int m = d->mode_order[k];
+            if (m < 0 || m >= N || seen[m]) return fail(STH_ERR_INVALID, "mode_order is not a permutation");
+            seen[m] = 1;
+            order[k] = m;
+        }
+    } else {
+        for (int k = 0; k < N; ++k) order[k] = k;
+    }
+    if (d->solver < STH_SOLVER_EIG || d->solver > STH_SOLVER_AUTO) return fail(STH_ERR_INVALID, "solver %d", d->solver);
+    if (d->als_iters < 0) return fail(STH_ERR_INVALID, "als_iters < 0");
+    if (d->eig_max_sweeps < 0) return fail(STH_ERR_INVALID, "eig_max_sweeps < 0");
+
+    sth_plan_s *p = new sth_plan_s();
+    p->N = N;
+    p->dims.assign(d->dims, d->dims + N);
+    p->ranks.assign(d->ranks, d->ranks + N);
+    p->order = order;
+    p->dtype = d->dtype;
+    p->gram_prec = d->gram_prec;
+    p->ttm_prec = d->ttm_prec;
+    p->als_iters = d->als_iters ? d->als_iters : 5;
+    p->max_sweeps = d->eig_max_sweeps ? d->eig_max_sweeps : 60;
+    p->solver_of_mode.assign(N, STH_SOLVER_EIG);
+
+    // shapes on the current working tensor, solver choice (Alg. 2 line 3)
+    std::vector<int64_t> cur = p->dims;
+    size_t maxA = 0, maxB = 0, maxZ = 0, maxPart = 0, maxS = 0, maxEig = 0, maxUq = 0, maxSmall = 0, maxGemm = 0;
+    for (int s = 0; s < N; ++s) {
+        Step stp;
+        stp.n = order[s];
+        lim(N, cur.data(), stp.n, stp.L, stp.I, stp.M);
+        stp.R = p->ranks[stp.n];
+        int solver = d->solver;
+        if (d->per_mode) {
+            solver = d->per_mode[stp.n];
+            if (solver != STH_SOLVER_EIG && solver != STH_SOLVER_ALS && solver != STH_SOLVER_AUTO) {
+                delete p;
+                return fail(STH_ERR_INVALID, "per_mode[%d] = %d", stp.n, solver);
+            }
+        }
+        if (solver == STH_SOLVER_AUTO) {
+            solver = selector_choose(stp.I, stp.R, stp.L * stp.M, N, d->mlp_weights);
+        }
+        if (solver == STH_SOLVER_EIG && stp.I > MAX_EIG_N) {
+            delete p;
+            return fail(STH_ERR_UNSUPPORTED, "EIG mode %d: I_n = %lld exceeds the eigensolver limit %lld (use ALS)", stp.n, (long long)stp.I, (long long)MAX_EIG_N);
+        }
+        if (solver == STH_SOLVER_ALS && stp.R > MAX_ALS_R) {
+            delete p;
+            return fail(STH_ERR_UNSUPPORTED, "ALS mode %d: R_n = %lld exceeds %lld", stp.n, (long long)stp.R, (long long)MAX_ALS_R);
+        }
+        stp.solver = solver;
+        p->solver_of_mode[stp.n] = solver;
+        stp.src = (s == 0) ? 0 : ((s - 1) % 2 == 0 ? 1 : 2);
+        stp.dst = (s == N - 1) ? 3 : (s % 2 == 0 ? 1 : 2);
+        const size_t out_elems = (size_t)(stp.L * stp.R * stp.M);
+        if (stp.dst == 1) maxA = std::max(maxA, out_elems);
+        if (stp.dst == 2) maxB = std::max(maxB, out_elems);
+        const int64_t P = stp.L * stp.M;
+        const int tp = ttm_prec_of(*p);
+        if (solver == STH_SOLVER_EIG) {
+            maxPart = std::max(maxPart, gram_ws_bytes(stp.I, stp.I, P, true));
+            maxS = std::max(maxS, (size_t)(stp.I * stp.I) * sizeof(double));
+            maxEig = std::max(maxEig, eig_ws_bytes(stp.I));
+            maxUq = std::max(maxUq, ttm_prep_bytes(stp.I, stp.R, tp));
+        } else {
+            maxZ = std::max(maxZ, out_elems);
+            maxPart = std::max(maxPart, gram_ws_bytes(stp.I, stp.R, P, false));
+            maxUq = std::max(maxUq, std::max(ttm_prep_bytes(stp.I, stp.R, tp), ttm_prep_bytes(stp.R, stp.R, tp)));
+            maxSmall = std::max(maxSmall, als_small_doubles(stp.I, stp.R) * sizeof(double));
+            const int I = (int)stp.I, R = (int)stp.R;
+            maxGemm = std::max({maxGemm, gemm_ws_bytes(R, R, I), gemm_ws_bytes(I, R, R), gemm_ws_bytes(R, R, R)});
+        }
+        cur[stp.n] = stp.R;
+        p->steps.push_back(stp);
+    }
+    Arena a;
+    p->o_flag = a.take(256);
+    p->o_bufA = a.take(maxA * esize(p->dtype));
+    p->o_bufB = a.take(maxB * esize(p->dtype));
+    p->o_bufZ = a.take(maxZ * esize(p->dtype));
+    p->o_part = a.take(maxPart);
+    p->o_S = a.take(maxS);
+    p->o_eig = a.take(maxEig);
+    p->o_uq = a.take(maxUq);
+    p->o_small = a.take(maxSmall);
+    p->o_gemm = a.take(maxGemm);
+    p->o_sum = a.take(SUMSQ_BLOCKS * sizeof(double));
+    p->total = a.off;
+    if (d->workspace_cap > 0 && p->total > (size_t)d->workspace_cap) {
+        size_t need = p->total;
+        delete p;
+        return fail(STH_ERR_NOMEM, "workspace %zu bytes exceeds the cap %lld", need, (long long)d->workspace_cap);
+    }
+    *plan_out = p;
+    *ws_out = p->total;
+    return STH_OK;
+}
+
+extern "C" sth_status sthosvd_plan_solvers(const sth_plan *plan, int32_t *out) {
+    if (!plan || !out) return fail(STH_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < plan->N; ++k) out[k] = plan->solver_of_mode[k];
+    return STH_OK;
+}
+
+extern "C" void sthosvd_plan_destroy(sth_plan *plan) { delete plan; }
+
+// ---------------------------------------------------------------- ALS ----
+
+namespace {
+
+struct AlsBufs {
+    double *Q, *P, *Lk, *T1, *L0, *C, *Rc, *Rcinv, *G2, *R1, *R1inv, *R2, *R2inv, *Rhat;
+};
+
+AlsBufs als_bufs(double *base, int64_t I, int64_t R) {
+    AlsBufs b;
+    double *p = base;
+    auto take = [&](int64_t n) { double *r = p; p += n; return r; };
+    b.Q = take(I * R);
+    b.P = take(I * R);
+    b.Lk = take(I * R);
+    b.T1 = take(I * R);
+    b.L0 = take(I * R);
+    b.C = take(R * R);
+    b.Rc = take(R * R);
+    b.Rcinv = take(R * R);
+    b.G2 = take(R * R);
+    b.R1 = take(R * R);
+    b.R1inv = take(R * R);
+    b.R2 = take(R * R);
+    b.R2inv = take(R * R);
+    b.Rhat = take(R * R);
+    return b;
+}
+
+// Cholesky-QR twice of the I x R matrix A (well conditioned): Q = A R^{-1},
+// R = R2 R1 (upper, positive diagonal).  Q may alias nothing in A.
+hipError_t cholqr2(const double *A, int I, int R, double *Q, double *Rfac, AlsBufs &b, void *gws,
+                   int64_t *flag, hipStream_t s) {
+    hipError_t e;
+    if ((e = gemm_f64(1, 0, R, R, I, 1.0, A, I, A, I, 0.0, b.G2, R, gws, s))) return e;
+    if ((e = chol_launch(b.G2, R, R, 0.0, b.R1, b.R1inv, flag, s))) return e;
+    if ((e = gemm_f64(0, 0, I, R, R, 1.0, A, I, b.R1inv, R, 0.0, b.T1, I, gws, s))) return e;
+    if ((e = gemm_f64(1, 0, R, R, I, 1.0, b.T1, I, b.T1, I, 0.0, b.G2, R, gws, s))) return e;
+    if ((e = chol_launch(b.G2, R, R, 0.0, b.R2, b.R2inv, flag, s))) return e;
+    if ((e = gemm_f64(0, 0, I, R, R, 1.0, b.T1, I, b.R2inv, R, 0.0, Q, I, gws, s))) return e;
+    if (Rfac) {
+        if ((e = gemm_f64(0, 0, R, R, R, 1.0, b.R2, R, b.R1, R, 0.0, Rfac, R, gws, s))) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- run ----
+
+extern "C" sth_status sthosvd_run(const sth_plan *p, const void *X, void *core, double *const *U,
+                                  double *const *eigvals, const double *const *als_init,
+                                  uint64_t seed, void *ws, size_t ws_bytes, sth_stream_t stream) {
+    if (!p) return fail(STH_ERR_INVALID, "plan is NULL");
+    sth_status st;
+    if ((st = check_ptr(X, "X"))) return st;
+    if ((st = check_ptr(core, "core"))) return st;
+    if ((st = check_ptr(ws, "workspace"))) return st;
+    if (!U) return fail(STH_ERR_INVALID, "U is NULL");
+    for (int k = 0; k < p->N; ++k) {
+        if ((st = check_ptr(U[k], "U[n]"))) return st;
+        if (eigvals && eigvals[k] && (st = check_ptr(eigvals[k], "eigvals[n]"))) return st;
+        if (als_init && als_init[k] && (st = check_ptr(als_init[k], "als_init[n]"))) return st;
+    }
+    if (ws_bytes < p->total) return fail(STH_ERR_NOMEM, "workspace %zu < required %zu bytes", ws_bytes, p->total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int64_t *flag = (int64_t *)(w + p->o_flag);
+    char *bufA = w + p->o_bufA, *bufB = w + p->o_bufB;
+    void *bufZ = w + p->o_bufZ;
+    double *part = (double *)(w + p->o_part);
+    double *S = (double *)(w + p->o_S);
+    void *eigws = w + p->o_eig;
+    void *uq = w + p->o_uq;
+    void *gws = w + p->o_gemm;
+    const int gp = gram_prec_of(*p), tp = ttm_prec_of(*p);
+
+    for (const Step &stp : p->steps) {
+        const void *src = stp.src == 0 ? X : (stp.src == 1 ? (const void *)bufA : (const void *)bufB);
+        void *dst = stp.dst == 3 ? core : (stp.dst == 1 ? (void *)bufA : (void *)bufB);
+        const int n = stp.n;
+        if (stp.solver == STH_SOLVER_EIG) {
+            // Alg. 2 lines 6-8
+            HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
+            double *lam = eigvals ? eigvals[n] : nullptr;
+            HIPCHK(eig_launch(stp.I, stp.R, S, U[n], lam, 1e-15, p->max_sweeps, eigws, s), "eig");
+            HIPCHK(ttm_prep_u(U[n], stp.I, stp.R, 0, tp, uq, s), "ttm prep");
+            HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
+        } else {
+            // Alg. 2 lines 10-13 with Alg. 3 (L_k re-orthonormalized before each sweep)
+            const int I = (int)stp.I, R = (int)stp.R;
+            AlsBufs b = als_bufs((double *)(w + p->o_small), I, R);
+            const double *L0 = als_init ? als_init[n] : nullptr;
+            if (!L0) {
+                HIPCHK(gaussian_f64(b.L0, (int64_t)I * R, seed, (uint64_t)n, s), "als init");
+                L0 = b.L0;
+            }
+            HIPCHK(cholqr2(L0, I, R, b.Q, nullptr, b, gws, flag, s), "als qr0");
+            for (int k = 0; k < p->als_iters; ++k) {
+                // Z = Y x_n Q^T  (R_k as a tensor)
+                HIPCHK(ttm_prep_u(b.Q, I, R, 0, tp, uq, s), "als prep");
+                HIPCHK(ttm_launch(p->dtype, tp, src, uq, bufZ, stp.L, I, R, stp.M, s), "als ttm");
+                // P = Y_(n) Z_(n)^T  (TTT)
+                HIPCHK(gram_launch(p->dtype, gp, src, bufZ, stp.L, I, R, stp.M, false, part, b.P, s), "als ttt");
+                // C = R_k^T R_k = Q^T P ;  L_{k+1} = P C^{-1}
+                HIPCHK(gemm_f64(1, 0, R, R, I, 1.0, b.Q, I, b.P, I, 0.0, b.C, R, gws, s), "als C");
+                HIPCHK(chol_launch(b.C, R, R, 0.0, b.Rc, b.Rcinv, flag, s), "als chol");
+                HIPCHK(gemm_f64(0, 0, I, R, R, 1.0, b.P, I, b.Rcinv, R, 0.0, b.T1, I, gws, s), "als L1");
+                HIPCHK(gemm_f64(0, 1, I, R, R, 1.0, b.T1, I, b.Rcinv, R, 0.0, b.Lk, I, gws, s), "als L2");
+                const bool last = (k + 1 == p->als_iters);
+                // next basis, or the final Q^ R^ = L
+                HIPCHK(cholqr2(b.Lk, I, R, last ? U[n] : b.Q, last ? b.Rhat : nullptr, b, gws, flag, s), "als qr");
+            }
+            // core update: Y' = R x_n R^  (Z'(a, r, b) = sum_s R^(r, s) Z(a, s, b))
+            HIPCHK(ttm_prep_u(b.Rhat, R, R, 1, tp, uq, s), "als core prep");
+            HIPCHK(ttm_launch(p->dtype, tp, bufZ, uq, dst, stp.L, R, R, stp.M, s), "als core ttm");
+        }
+    }
+    return STH_OK;
+}
+
+extern "C" sth_status sthosvd_check(const sth_plan *p, void *ws, sth_stream_t stream) {
+    if (!p || !ws) return fail(STH_ERR_INVALID, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t flag = 0;
+    int64_t *dflag = (int64_t *)((char *)ws + p->o_flag);
+    HIPCHK(hipStreamSynchronize(s), "sync");
+    HIPCHK(hipMemcpy(&flag, dflag, sizeof(flag), hipMemcpyDeviceToHost), "flag read");
+    int64_t zero = 0;
+    HIPCHK(hipMemcpy(dflag, &zero, sizeof(zero), hipMemcpyHostToDevice), "flag clear");
+    if (flag == 1) return fail(STH_ERR_NUMERIC, "eigensolver hit its sweep cap");
+    if (flag == 2) return fail(STH_ERR_NUMERIC, "Cholesky met a non-positive pivot (rank-deficient ALS basis)");
+    if (flag == 3) return fail(STH_ERR_NUMERIC, "NaN or Inf met");
+    if (flag) return fail(STH_ERR_NUMERIC, "numeric flag %lld", (long long)flag);
+    return STH_OK;
+}
+
+// ------------------------------------------------------ building blocks ----
+
+extern "C" size_t gram_mode_n_workspace(int32_t order, const int64_t *dims, int32_t n, int32_t other_rows) {
+    if (check_shape(order, dims) || n < 0 || n >= order) return 0;
+    int64_t L, I, M;
+    lim(order, dims, n, L, I, M);
+    if (other_rows > 0) return align_up(gram_ws_bytes(I, other_rows, L * M, false));
+    return align_up(gram_ws_bytes(I, I, L * M, true));
+}
+
+extern "C" sth_status gram_mode_n(int32_t order, const int64_t *dims, int32_t n, int32_t dtype,
+                                  int32_t prec, const void *Y, double *S, void *ws, size_t ws_bytes,
+                                  sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (n < 0 || n >= order) return fail(STH_ERR_INVALID, "mode %d outside 0..%d", n, order - 1);
+    if ((st = check_dtype_prec(dtype, prec, "prec"))) return st;
+    if ((st = check_ptr(Y, "Y")) || (st = check_ptr(S, "S")) || (st = check_ptr(ws, "ws"))) return st;
+    int64_t L, I, M;
+    lim(order, dims, n, L, I, M);
+    size_t need = gram_ws_bytes(I, I, L * M, true);
+    if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    HIPCHK(gram_launch(dtype, prec, Y, Y, L, I, I, M, true, (double *)ws, S, (hipStream_t)stream), "gram");
+    return STH_OK;
+}
+
+extern "C" sth_status ttt_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                                 int32_t dtype, int32_t prec, const void *Y, const void *Z, double *P,
+                                 void *ws, size_t ws_bytes, sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (n < 0 || n >= order) return fail(STH_ERR_INVALID, "mode %d outside 0..%d", n, order - 1);
+    if (R < 1) return fail(STH_ERR_INVALID, "R < 1");
+    if ((st = check_dtype_prec(dtype, prec, "prec"))) return st;
+    if ((st = check_ptr(Y, "Y")) || (st = check_ptr(Z, "Z")) || (st = check_ptr(P, "P")) || (st = check_ptr(ws, "ws"))) return st;
+    int64_t L, I, M;
+    lim(order, dims, n, L, I, M);
+    size_t need = gram_ws_bytes(I, R, L * M, false);
+    if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    HIPCHK(gram_launch(dtype, prec, Y, Z, L, I, R, M, false, (double *)ws, P, (hipStream_t)stream), "ttt");
+    return STH_OK;
+}
+
+extern "C" size_t ttm_mode_n_workspace(int64_t I, int64_t R) {
+    if (I < 1 || R < 1) return 0;
+    return align_up(ttm_prep_bytes(I, R, STH_PREC_FP64));  // the largest precision
+}
+
+extern "C" sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                                 int32_t dtype, int32_t prec, const void *Y, const double *U,
+                                 int32_t transpose_u, void *Z, void *ws, size_t ws_bytes,
+                                 sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (n < 0 || n >= order) return fail(STH_ERR_INVALID, "mode %d outside 0..%d", n, order - 1);
+    if (R < 1) return fail(STH_ERR_INVALID, "R < 1");
+    if ((st = check_dtype_prec(dtype, prec, "prec"))) return st;
+    if ((st = check_ptr(Y, "Y")) || (st = check_ptr(U, "U")) || (st = check_ptr(Z, "Z")) || (st = check_ptr(ws, "ws"))) return st;
+    int64_t L, I, M;
+    lim(order, dims, n, L, I, M);
+    size_t need = ttm_prep_bytes(I, R, prec);
+    if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(ttm_prep_u(U, I, R, transpose_u ? 1 : 0, prec, ws, s), "ttm prep");
+    HIPCHK(ttm_launch(dtype, prec, Y, ws, Z, L, I, R, M, s), "ttm");
+    return STH_OK;
+}
+
+extern "C" size_t eig_leading_workspace(int64_t n) { return n >= 1 ? align_up(eig_ws_bytes(n)) : 0; }
+
+extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double *U, double *lam,
+                                  int32_t max_sweeps, void *ws, size_t ws_bytes, sth_stream_t stream) {
+    if (n < 1 || n > MAX_EIG_N) return fail(n < 1 ? STH_ERR_INVALID : STH_ERR_UNSUPPORTED, "n = %lld outside 1..%lld", (long long)n, (long long)MAX_EIG_N);
+    if (R < 1 || R > n) return fail(STH_ERR_INVALID, "R = %lld outside 1..n", (long long)R);
+    sth_status st;
+    if ((st = check_ptr(S, "S")) || (st = check_ptr(U, "U")) || (st = check_ptr(lam, "lam", true)) || (st = check_ptr(ws, "ws"))) return st;
+    if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
+    HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (hipStream_t)stream), "eig");
+    return STH_OK;
+}
+
+// -------------------------------------------------------- reconstruct ----
+
+static void recon_sizes(int32_t order, const int64_t *dims, const int64_t *ranks, size_t &maxA, size_t &maxB) {
+    std::vector<int64_t> cur(ranks, ranks + order);
+    maxA = maxB = 0;
+    for (int n = 0; n < order - 1; ++n) {
+        cur[n] = dims[n];
+        size_t e = 1;
+        for (int k = 0; k < order; ++k) e *= (size_t)cur[k];
+        if (n % 2 == 0) maxA = std::max(maxA, e);
+        else maxB = std::max(maxB, e);
+    }
+}
+
+extern "C" size_t tucker_reconstruct_workspace(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype) {
+    if (check_shape(order, dims) || !ranks) return 0;
+    size_t a, b, uq = 0;
+    recon_sizes(order, dims, ranks, a, b);
+    for (int n = 0; n < order; ++n) uq = std::max(uq, ttm_prep_bytes(ranks[n], dims[n], STH_PREC_FP64));
+    return align_up(a * esize(dtype)) + align_up(b * esize(dtype)) + align_up(uq);
+}
+
+extern "C" sth_status tucker_reconstruct(int32_t order, const int64_t *dims, const int64_t *ranks,
+                                         int32_t dtype, int32_t prec, const void *G,
+                                         const double *const *U, void *Xhat, void *ws, size_t ws_bytes,
+                                         sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (!ranks || !U) return fail(STH_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < order; ++k) {
+        if (ranks[k] < 1 || ranks[k] > dims[k]) return fail(STH_ERR_INVALID, "ranks[%d] out of range", k);
+        if ((st = check_ptr(U[k], "U[n]"))) return st;
+    }
+    if ((st = check_dtype_prec(dtype, prec, "prec"))) return st;
+    if ((st = check_ptr(G, "G")) || (st = check_ptr(Xhat, "Xhat")) || (st = check_ptr(ws, "ws"))) return st;
+    size_t need = tucker_reconstruct_workspace(order, dims, ranks, dtype);
+    if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    size_t a, b;
+    recon_sizes(order, dims, ranks, a, b);
+    char *bufA = (char *)ws, *bufB = bufA + align_up(a * esize(dtype));
+    void *uq = bufB + align_up(b * esize(dtype));
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<int64_t> cur(ranks, ranks + order);
+    const void *src = G;
+    for (int n = 0; n < order; ++n) {
+        int64_t L, I, M;
+        lim(order, cur.data(), n, L, I, M);
+        void *dst = (n == order - 1) ? Xhat : (n % 2 == 0 ? (void *)bufA : (void *)bufB);
+        // expand mode n: Z(a, i, b) = sum_r U(i, r) Y(a, r, b)
+        HIPCHK(ttm_prep_u(U[n], ranks[n], dims[n], 1, prec, uq, s), "recon prep");
+        HIPCHK(ttm_launch(dtype, prec, src, uq, dst, L, ranks[n], dims[n], M, s), "recon ttm");
+        cur[n] = dims[n];
+        src = dst;
+    }
+    return STH_OK;
+}
+
+extern "C" size_t tucker_error_workspace(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype) {
+    if (check_shape(order, dims) || !ranks) return 0;
+    size_t numel = 1;
+    for (int k = 0; k < order; ++k) numel *= (size_t)dims[k];
+    return tucker_reconstruct_workspace(order, dims, ranks, dtype) + align_up(numel * esize(dtype)) +
+           align_up(SUMSQ_BLOCKS * sizeof(double));
+}
+
+extern "C" sth_status tucker_error(int32_t order, const int64_t *dims, const int64_t *ranks,
+                                   int32_t dtype, int32_t prec, const void *X, const void *G,
+                                   const double *const *U, double *out, void *ws, size_t ws_bytes,
+                                   sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (!ranks) return fail(STH_ERR_INVALID, "ranks is NULL");
+    if ((st = check_ptr(X, "X")) || (st = check_ptr(out, "out"))) return st;
+    size_t need = tucker_error_workspace(order, dims, ranks, dtype);
+    if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    size_t rw = tucker_reconstruct_workspace(order, dims, ranks, dtype);
+    size_t numel = 1;
+    for (int k = 0; k < order; ++k) numel *= (size_t)dims[k];
+    char *xh = (char *)ws + rw;
+    double *part = (double *)(xh + align_up(numel * esize(dtype)));
+    if ((st = tucker_reconstruct(order, dims, ranks, dtype, prec, G, U, xh, ws, rw, stream))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(sumsq_launch(dtype, X, xh, (int64_t)numel, out, part, nullptr, s), "diff");
+    HIPCHK(sumsq_launch(dtype, X, nullptr, (int64_t)numel, out + 1, part, nullptr, s), "norm");
+    return STH_OK;
+}
+
+extern "C" sth_status sth_sumsq(int32_t dtype, const void *x, int64_t count, double *out, void *ws,
+                                size_t ws_bytes, sth_stream_t stream) {
+    if (dtype != STH_F64 && dtype != STH_F32) return fail(STH_ERR_INVALID, "dtype %d", dtype);
+    if (count < 0) return fail(STH_ERR_INVALID, "count < 0");
+    sth_status st;
+    if ((st = check_ptr(x, "x")) || (st = check_ptr(out, "out")) || (st = check_ptr(ws, "ws"))) return st;
+    if (ws_bytes < SUMSQ_BLOCKS * sizeof(double)) return fail(STH_ERR_NOMEM, "workspace too small");
+    HIPCHK(sumsq_launch(dtype, x, nullptr, count, out, (double *)ws, nullptr, (hipStream_t)stream), "sumsq");
+    return STH_OK;
+}

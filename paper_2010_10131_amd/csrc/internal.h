@@ -1,0 +1,52 @@
+// Internal interfaces between the host driver and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+namespace sth {
+
+enum { DT_F64 = 0, DT_F32 = 1 };
+constexpr int SUMSQ_BLOCKS = 1024;
+
+inline int prec_nq(int prec) { return prec == 0 ? 4 : (prec == 3 ? 3 : 2); }
+
+int device_cu_count();
+
+// TTM (ttm.hip)
+size_t ttm_prep_bytes(int64_t K, int64_t Rout, int prec);
+hipError_t ttm_prep_u(const double *U, int64_t K, int64_t Rout, int transpose, int prec, void *out,
+                      hipStream_t s);
+hipError_t ttm_launch(int dtype, int prec, const void *Y, const void *Uq, void *Z, int64_t L,
+                      int64_t K, int64_t Rout, int64_t M, hipStream_t s);
+
+// Gram / TTT (gram.hip)
+size_t gram_ws_bytes(int64_t IA, int64_t IB, int64_t P, bool sym);
+hipError_t gram_launch(int dtype, int prec, const void *A, const void *B, int64_t L, int64_t IA,
+                       int64_t IB, int64_t M, bool sym, double *partials, double *S,
+                       hipStream_t s);
+
+// Eigensolver (eig.hip)
+size_t eig_ws_bytes(int64_t n);
+hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
+                      int max_sweeps, void *ws, hipStream_t s);
+
+// Small FP64 LA and reductions (la.hip)
+int gemm_splits(int m, int n, int k);
+size_t gemm_ws_bytes(int m, int n, int k);
+hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const double *A,
+                    int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                    void *ws, hipStream_t s);
+hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, double *R,
+                       double *Rinv, int64_t *flag, hipStream_t s);
+hipError_t sumsq_launch(int dtype, const void *x, const void *y, int64_t count, double *out,
+                        double *part, int64_t *flag, hipStream_t s);
+hipError_t fill_f64(double *p, int64_t n, double v, hipStream_t s);
+hipError_t copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
+hipError_t zero_words(void *p, int64_t nwords, hipStream_t s);
+hipError_t gaussian_f64(double *p, int64_t n, uint64_t seed, uint64_t stream, hipStream_t s);
+
+}  // namespace sth

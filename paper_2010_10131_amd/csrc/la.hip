@@ -1,0 +1,302 @@
+// Small dense FP64 linear algebra for the ALS branch (Alg. 3 and the QR of
+// Alg. 2) and the FP64 norm reductions (Eq. 1).
+//
+//   gemm_f64      C = alpha op(A) op(B) + beta C, 32x32 tiles, optional
+//                 split-K with a fixed-order reduction (deterministic)
+//   chol_kernel   one workgroup: G (+ shift) = R^T R (Cholesky, R upper),
+//                 writes R and R^{-1}; used for the normal equations of
+//                 Alg. 3 and for Cholesky-QR
+//   sumsq / diff  FP64 sums of squares with per-block partials reduced in a
+//                 fixed order
+#include "common.h"
+#include "internal.h"
+
+namespace sth {
+
+constexpr int GT = 32;  // gemm tile
+
+// C_part[z] (m x n, ldc) = op(A) op(B) over k-slice z.
+__global__ __launch_bounds__(256) void gemm_f64_kernel(int ta, int tb, int m, int n, int k,
+                                                       double alpha, const double *__restrict__ A,
+                                                       int64_t lda, const double *__restrict__ B,
+                                                       int64_t ldb, double beta, double *__restrict__ C,
+                                                       int64_t ldc, int kslice, double *__restrict__ part) {
+    __shared__ double sA[GT][GT + 1];  // sA[kk][row]
+    __shared__ double sB[GT][GT + 1];  // sB[kk][col]
+    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    const int row0 = blockIdx.x * GT, col0 = blockIdx.y * GT;
+    const int kz = blockIdx.z;
+    const int kbeg = kz * kslice, kend = min(k, kbeg + kslice);
+    double acc[2][2] = {{0, 0}, {0, 0}};
+    for (int kc = kbeg; kc < kend; kc += GT) {
+        for (int e = threadIdx.x; e < GT * GT; e += 256) {
+            int a = e % GT, b = e / GT;
+            // sA[kk][r]: element op(A)(row0 + r, kc + kk)
+            {
+                int r, kk;
+                if (ta) { kk = a; r = b; } else { r = a; kk = b; }
+                int gr = row0 + r, gk = kc + kk;
+                double v = 0.0;
+                if (gr < m && gk < kend) v = ta ? A[gk + lda * gr] : A[gr + lda * gk];
+                sA[kk][r] = v;
+            }
+            {
+                int cidx, kk;
+                if (tb) { cidx = a; kk = b; } else { kk = a; cidx = b; }
+                int gc = col0 + cidx, gk = kc + kk;
+                double v = 0.0;
+                if (gc < n && gk < kend) v = tb ? B[gc + ldb * gk] : B[gk + ldb * gc];
+                sB[kk][cidx] = v;
+            }
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int kk = 0; kk < GT; ++kk) {
+            double a0 = sA[kk][tx], a1 = sA[kk][tx + 16];
+            double b0 = sB[kk][ty], b1 = sB[kk][ty + 16];
+            acc[0][0] += a0 * b0;
+            acc[1][0] += a1 * b0;
+            acc[0][1] += a0 * b1;
+            acc[1][1] += a1 * b1;
+        }
+        __syncthreads();
+    }
+    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < 2; ++y) {
+            int r = row0 + tx + 16 * x, c = col0 + ty + 16 * y;
+            if (r < m && c < n) {
+                if (part) {
+                    part[(int64_t)kz * m * n + r + (int64_t)m * c] = acc[x][y];
+                } else {
+                    double old = (beta != 0.0) ? C[r + ldc * c] : 0.0;
+                    C[r + ldc * c] = alpha * acc[x][y] + beta * old;
+                }
+            }
+        }
+}
+
+__global__ void gemm_reduce_kernel(int m, int n, int nz, const double *__restrict__ part,
+                                   double alpha, double beta, double *__restrict__ C, int64_t ldc) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)m * n) return;
+    int r = (int)(e % m), c = (int)(e / m);
+    double s = 0.0;
+    for (int z = 0; z < nz; ++z) s += part[(int64_t)z * m * n + e];
+    double old = (beta != 0.0) ? C[r + ldc * c] : 0.0;
+    C[r + ldc * c] = alpha * s + beta * old;
+}
+
+size_t gemm_ws_bytes(int m, int n, int k) {
+    int nz = gemm_splits(m, n, k);
+    return nz > 1 ? (size_t)nz * m * n * sizeof(double) : 0;
+}
+
+int gemm_splits(int m, int n, int k) {
+    int tiles = ((m + GT - 1) / GT) * ((n + GT - 1) / GT);
+    int nz = 1;
+    while (tiles * nz < 64 && k / (nz * 2) >= 128 && nz < 32) nz *= 2;
+    return nz;
+}
+
+hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const double *A,
+                    int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                    void *ws, hipStream_t s) {
+    if (m == 0 || n == 0) return hipSuccess;
+    int nz = gemm_splits(m, n, k);
+    int kslice = (k + nz - 1) / nz;
+    kslice = (kslice + GT - 1) / GT * GT;
+    if (kslice == 0) kslice = GT;
+    nz = std::max(1, (k + kslice - 1) / kslice);
+    dim3 grid((m + GT - 1) / GT, (n + GT - 1) / GT, nz);
+    double *part = nz > 1 ? (double *)ws : nullptr;
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, B,
+                       ldb, beta, C, ldc, kslice, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || nz == 1) return e;
+    int64_t tot = (int64_t)m * n;
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, m,
+                       n, nz, part, alpha, beta, C, ldc);
+    return hipGetLastError();
+}
+
+// One workgroup.  G (n x n, symmetric, ldg) + shift_rel * trace(G) / n * I
+// = R^T R.  Writes R (upper, n x n, may be NULL) and Rinv = R^{-1} (upper,
+// n x n).  A non-positive pivot sets flag[0] = 2 and is replaced by a tiny
+// positive one so that the run continues.
+__global__ __launch_bounds__(1024) void chol_kernel(const double *__restrict__ G, int n, int64_t ldg,
+                                                    double shift_rel, double *__restrict__ Rout,
+                                                    double *__restrict__ Rinv,
+                                                    int64_t *__restrict__ flag) {
+    extern __shared__ double s_l[];  // L (lower), n x n column-major
+    __shared__ double s_tr;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        int i = e % n, j = e / n;
+        s_l[e] = (i >= j) ? G[i + ldg * j] : 0.0;
+    }
+    if (tid == 0) {
+        double t = 0.0;
+        for (int i = 0; i < n; ++i) t += G[i + ldg * i];
+        s_tr = t;
+    }
+    __syncthreads();
+    if (shift_rel != 0.0) {
+        double sh = shift_rel * s_tr / n;
+        for (int i = tid; i < n; i += blockDim.x) s_l[i + n * i] += sh;
+        __syncthreads();
+    }
+    const double tiny = 1e-300 + 1e-30 * fabs(s_tr);
+    for (int k = 0; k < n; ++k) {
+        if (tid == 0) {
+            double d = s_l[k + n * k];
+            if (!(d > 0.0)) {
+                if (flag) flag[0] = 2;
+                d = tiny;
+            }
+            s_l[k + n * k] = sqrt(d);
+        }
+        __syncthreads();
+        const double dk = s_l[k + n * k];
+        for (int i = k + 1 + tid; i < n; i += blockDim.x) s_l[i + n * k] /= dk;
+        __syncthreads();
+        const int w = n - k - 1;
+        for (int e = tid; e < w * w; e += blockDim.x) {
+            int i = k + 1 + e % w, j = k + 1 + e / w;
+            if (i >= j) s_l[i + n * j] -= s_l[i + n * k] * s_l[j + n * k];
+        }
+        __syncthreads();
+    }
+    if (Rout)
+        for (int e = tid; e < n * n; e += blockDim.x) {
+            int i = e % n, j = e / n;  // R(i, j) = L(j, i)
+            Rout[e] = (i <= j) ? s_l[j + n * i] : 0.0;
+        }
+    // Linv column j (lower), one thread per column; Rinv = Linv^T
+    for (int j = tid; j < n; j += blockDim.x) {
+        // x = Linv(:, j): L x = e_j
+        for (int i = 0; i < j; ++i) Rinv[j + (int64_t)n * i] = 0.0;  // Rinv(j, i) = Linv(i, j) = 0, i < j
+        double xj = 1.0 / s_l[j + n * j];
+        Rinv[j + (int64_t)n * j] = xj;
+        for (int i = j + 1; i < n; ++i) {
+            double sacc = 0.0;
+            for (int kk = j; kk < i; ++kk) sacc += s_l[i + n * kk] * Rinv[j + (int64_t)n * kk];
+            Rinv[j + (int64_t)n * i] = -sacc / s_l[i + n * i];
+        }
+    }
+}
+
+hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, double *R,
+                       double *Rinv, int64_t *flag, hipStream_t s) {
+    size_t lds = (size_t)n * n * sizeof(double);
+    if (lds > 64 * 1024)
+        hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), lds, s, G, n, ldg, shift_rel, R, Rinv, flag);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- norms ----
+
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_kernel(const T *__restrict__ x, const T *__restrict__ y,
+                                                    int64_t count, double *__restrict__ part) {
+    double s = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256) {
+        double v = (double)x[e];
+        if (y) v -= (double)y[e];
+        s += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+    __shared__ double sw[4];
+    if ((threadIdx.x & 63) == 0) sw[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = ((sw[0] + sw[1]) + sw[2]) + sw[3];
+}
+
+__global__ void sum_parts_kernel(const double *__restrict__ part, int n, double *__restrict__ out,
+                                 int64_t *__restrict__ flag) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += part[i];
+    *out = s;
+    if (flag && !(fabs(s) <= 1.7e308)) flag[0] = 3;  // NaN or Inf
+}
+
+hipError_t sumsq_launch(int dtype, const void *x, const void *y, int64_t count, double *out,
+                        double *part, int64_t *flag, hipStream_t s) {
+    int nb = (int)std::min<int64_t>(SUMSQ_BLOCKS, std::max<int64_t>(1, (count + 255) / 256));
+    if (dtype == DT_F64)
+        hipLaunchKernelGGL(sumsq_kernel<double>, dim3(nb), dim3(256), 0, s, (const double *)x,
+                           (const double *)y, count, part);
+    else
+        hipLaunchKernelGGL(sumsq_kernel<float>, dim3(nb), dim3(256), 0, s, (const float *)x,
+                           (const float *)y, count, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(1), dim3(64), 0, s, part, nb, out, flag);
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------------- misc ----
+
+__global__ void fill_f64_kernel(double *p, int64_t n, double v) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) p[e] = v;
+}
+
+hipError_t fill_f64(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+__global__ void copy_f64_kernel(const double *src, double *dst, int64_t n) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = src[e];
+}
+
+hipError_t copy_f64(const double *src, double *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(copy_f64_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+__global__ void zero_bytes_kernel(uint32_t *p, int64_t nwords) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < nwords) p[e] = 0u;
+}
+
+hipError_t zero_words(void *p, int64_t nwords, hipStream_t s) {
+    if (nwords <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_bytes_kernel, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, s,
+                       (uint32_t *)p, nwords);
+    return hipGetLastError();
+}
+
+// Gaussian initial guess for ALS from a counter-based generator:
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) on the counter
+// (seed, mode, element), two uniforms -> Box-Muller.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__global__ void gaussian_kernel(double *p, int64_t n, uint64_t seed, uint64_t stream) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    uint64_t base = splitmix64(seed ^ splitmix64(stream + 0x5851F42D4C957F2Dull));
+    uint64_t a = splitmix64(base + 2 * (uint64_t)e);
+    uint64_t b = splitmix64(base + 2 * (uint64_t)e + 1);
+    double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+    double u2 = (b >> 11) * (1.0 / 9007199254740992.0);           // [0, 1)
+    p[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+hipError_t gaussian_f64(double *p, int64_t n, uint64_t seed, uint64_t stream, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gaussian_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, seed, stream);
+    return hipGetLastError();
+}
+
+}  // namespace sth

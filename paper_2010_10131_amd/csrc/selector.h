@@ -1,0 +1,27 @@
+// Learned per-mode solver selector (the Sec. IV analogue): a small MLP cost
+// model evaluated on the host at plan time.
+#pragma once
+#include <stdint.h>
+
+namespace sth {
+
+constexpr int SEL_IN = 10;      // Table I features
+constexpr int SEL_HID = 32;
+constexpr int SEL_OUT = 2;      // predicted log time of EIG and of ALS
+// parameter count: W1 (32x10), b1, W2 (32x32), b2, W3 (2x32), b3, plus the
+// feature normalization (mean, inverse std: 2 x 10) and the output scale
+constexpr int SEL_NPARAM = SEL_HID * SEL_IN + SEL_HID + SEL_HID * SEL_HID + SEL_HID +
+                           SEL_OUT * SEL_HID + SEL_OUT + 2 * SEL_IN;
+
+// Table I features of one mode, log-scaled: I, R, J, I^2, R^2, I R, R^2/I,
+// R^2/J, I/J, R/J.
+void selector_features(int64_t I, int64_t R, int64_t J, float *out10);
+
+// Predicted (log t_EIG, log t_ALS) for one mode with the given weights
+// (NULL = the built-in weights).
+void selector_predict(const float *weights, const float *feat10, float *out2);
+
+// 0 = EIG, 1 = ALS (argmin of the predicted times; EIG on ties).
+int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *weights);
+
+}  // namespace sth

@@ -1,0 +1,302 @@
+// Matricization-free mode-n TTM on the gfx950 matrix cores.
+//
+// Computes, for a column-major tensor viewed as (L, K, M) along mode n
+// (L = product of the dims before n, M = product after), the mode-n product
+// with the transpose of a K x Rout factor V (Eq. 2; the core update of
+// Alg. 2 and the expansion step of the Tucker reconstruction):
+//
+//     Z(a, r, b) = sum_k V(k, r) * Y(a, k, b)          (Z is (L, Rout, M))
+//
+// The loops are split at mode n into "inside" (a), "along" (k) and
+// "outside" (b) as in Sec. V / Fig. 4; the (a, b) pairs are the rows of one
+// GEMM with K-long rows that are strided by L in memory.  Nothing is
+// transposed or copied.
+//
+// Design (MI355X): the kernel is HBM-bound for bf16x3 and for small Rout, so
+// each Y element is read from HBM exactly once, straight into the lane that
+// feeds it to the matrix cores (no LDS round trip for Y):
+//   * a wave owns NT row tiles of 16 rows and RTB r-tiles of 16 columns;
+//   * per 32-wide chunk of k a lane loads the 8 consecutive k of its row
+//     (two 16-byte loads when L = 1, 8 strided loads otherwise), splits them
+//     once into the requested precision and multiplies them against every
+//     r-tile of the factor;
+//   * the factor is pre-split by ttm_prep_u into matrix-core-ready 16-byte
+//     quads and staged once per workgroup in LDS (read from L2 when it does
+//     not fit), so the only HBM traffic is one read of Y and one write of Z;
+//   * the next chunk's loads are issued before the current chunk's
+//     matrix-core work (register double buffering).
+#include "common.h"
+#include "internal.h"
+
+namespace sth {
+
+// V (K x Rout) -> quads [c][rt][q][lane] (16 bytes each), zero padded.
+// transpose = 0: V = U with U (K x Rout) column-major.
+// transpose = 1: V = U^T with U (Rout x K) column-major.
+template <int PREC>
+__global__ void ttm_prep_u_kernel(const double *__restrict__ U, int64_t K, int64_t Rout,
+                                  int transpose, uint4 *__restrict__ out, int nchunks,
+                                  int ntiles) {
+    constexpr int NQ = Frag<PREC>::NQ;
+    int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = (int64_t)nchunks * ntiles * 64;
+    if (gid >= total) return;
+    int lane = (int)(gid % 64);
+    int64_t blk = gid / 64;  // c * ntiles + rt
+    int rt = (int)(blk % ntiles);
+    int c = (int)(blk / ntiles);
+    int g = lane / 16;
+    int64_t r = (int64_t)rt * 16 + lane % 16;
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        int64_t k = (int64_t)c * KC + 8 * g + j;
+        double v = 0.0;
+        if (k < K && r < Rout) v = transpose ? U[r + Rout * k] : U[k + K * r];
+        x[j] = v;
+    }
+    FragQ<PREC> f;
+    make_frag(x, f.f);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) out[(blk * NQ + q) * 64 + lane] = f.q[q];
+}
+
+template <typename T, bool CONTIG>
+__device__ __forceinline__ void ttm_load_chunk(const T *__restrict__ Y, int64_t base, int64_t L,
+                                               int64_t K, int64_t kb, T (&x)[8]) {
+    // kb = first of this lane's 8 consecutive k
+    if (CONTIG && kb + 8 <= K) {
+        const T *src = Y + base + kb;
+        if constexpr (sizeof(T) == 4) {
+            float4 u = *reinterpret_cast<const float4 *>(src);
+            float4 w = *reinterpret_cast<const float4 *>(src + 4);
+            x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w;
+            x[4] = w.x; x[5] = w.y; x[6] = w.z; x[7] = w.w;
+        } else {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                double2 u = *reinterpret_cast<const double2 *>(src + 2 * h);
+                x[2 * h] = u.x;
+                x[2 * h + 1] = u.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int64_t k = kb + j;
+            x[j] = (k < K) ? Y[base + L * k] : (T)0;
+        }
+    }
+}
+
+template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void ttm_kernel(
+    const T *__restrict__ Y, const uint4 *__restrict__ Uq, T *__restrict__ Z, int64_t L, int64_t K,
+    int64_t Rout, int64_t P, int nchunks, int ntiles, int64_t nrowblocks) {
+    constexpr int NQ = Frag<PREC>::NQ;
+    typedef typename Acc<PREC>::type AccT;
+    extern __shared__ uint4 s_u[];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int rb = blockIdx.y;            // r-block: tiles [rb*RTB, rb*RTB + RTB)
+    const int rt0 = rb * RTB;
+    const int rtn = min(RTB, ntiles - rt0);
+
+    if (ULDS) {
+        // stage this r-block's factor quads: [c][rt in block][q][lane]
+        const int per_chunk = RTB * NQ * 64;
+        const int total = nchunks * per_chunk;
+        for (int e = threadIdx.x; e < total; e += 64 * WAVES) {
+            int c = e / per_chunk;
+            int rem = e - c * per_chunk;  // (rtl * NQ + q) * 64 + lane
+            int rtl = rem / (NQ * 64);
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (rtl < rtn) v = Uq[((int64_t)c * ntiles + rt0) * NQ * 64 + rem];
+            s_u[e] = v;
+        }
+        __syncthreads();
+    }
+
+    const int64_t wstride = (int64_t)gridDim.x * WAVES;
+    for (int64_t wb = (int64_t)blockIdx.x * WAVES + wave; wb < nrowblocks; wb += wstride) {
+        const int64_t p0 = wb * (16 * NT);
+        int64_t base[NT];
+        int64_t zoff[NT];
+        bool pvalid[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            int64_t p = p0 + 16 * nt + (lane & 15);
+            pvalid[nt] = p < P;
+            int64_t pc = pvalid[nt] ? p : (P - 1);
+            int64_t a, b;
+            if (CONTIG) {
+                a = 0;
+                b = pc;
+            } else {
+                b = pc / L;
+                a = pc - b * L;
+            }
+            base[nt] = a + L * K * b;
+            zoff[nt] = a + L * Rout * b;
+        }
+        AccT acc[NT][RTB];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt) acc[nt][rt] = AccT{0, 0, 0, 0};
+
+        T nxt[NT][8];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, 8 * g, nxt[nt]);
+
+        for (int c = 0; c < nchunks; ++c) {
+            Frag<PREC> yb[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) make_frag(nxt[nt], yb[nt]);
+            if (c + 1 < nchunks) {
+                const int64_t kb = (int64_t)(c + 1) * KC + 8 * g;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, kb, nxt[nt]);
+            }
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt) {
+                FragQ<PREC> ua;
+                if (ULDS) {
+                    const uint4 *src = s_u + ((c * RTB + rt) * NQ) * 64 + lane;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) ua.q[q] = src[q * 64];
+                } else {
+                    const int rtg = min(rt0 + rt, ntiles - 1);
+                    const uint4 *src = Uq + (((int64_t)c * ntiles + rtg) * NQ) * 64 + lane;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) ua.q[q] = src[q * 64];
+                }
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) mma_frag(ua.f, yb[nt], acc[nt][rt]);
+            }
+        }
+
+        // D[r][p]: lane holds r = 16*rt + 4g + v, p = 16*nt + lane%16
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (!pvalid[nt]) continue;
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt) {
+                const int64_t r0 = (int64_t)(rt0 + rt) * 16 + 4 * g;
+                if (CONTIG && sizeof(T) == 4 && (Rout & 3) == 0 && r0 + 4 <= Rout) {
+                    float4 v = make_float4((float)acc[nt][rt][0], (float)acc[nt][rt][1],
+                                           (float)acc[nt][rt][2], (float)acc[nt][rt][3]);
+                    *reinterpret_cast<float4 *>(Z + zoff[nt] + r0) = v;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int64_t r = r0 + v;
+                        if (r < Rout) Z[zoff[nt] + L * r] = (T)acc[nt][rt][v];
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host ----
+
+size_t ttm_prep_bytes(int64_t K, int64_t Rout, int prec) {
+    int64_t nchunks = (K + KC - 1) / KC;
+    int64_t ntiles = (Rout + 15) / 16;
+    return (size_t)(nchunks * ntiles * 64 * 16 * prec_nq(prec));
+}
+
+hipError_t ttm_prep_u(const double *U, int64_t K, int64_t Rout, int transpose, int prec,
+                      void *out, hipStream_t s) {
+    int nchunks = (int)((K + KC - 1) / KC);
+    int ntiles = (int)((Rout + 15) / 16);
+    int64_t total = (int64_t)nchunks * ntiles * 64;
+    dim3 grid((unsigned)((total + 255) / 256));
+    uint4 *o = (uint4 *)out;
+    switch (prec) {
+        case P_FP64: hipLaunchKernelGGL(ttm_prep_u_kernel<P_FP64>, grid, dim3(256), 0, s, U, K, Rout, transpose, o, nchunks, ntiles); break;
+        case P_FP32: hipLaunchKernelGGL(ttm_prep_u_kernel<P_FP32>, grid, dim3(256), 0, s, U, K, Rout, transpose, o, nchunks, ntiles); break;
+        case P_BF16X3: hipLaunchKernelGGL(ttm_prep_u_kernel<P_BF16X3>, grid, dim3(256), 0, s, U, K, Rout, transpose, o, nchunks, ntiles); break;
+        default: hipLaunchKernelGGL(ttm_prep_u_kernel<P_BF16X6>, grid, dim3(256), 0, s, U, K, Rout, transpose, o, nchunks, ntiles); break;
+    }
+    return hipGetLastError();
+}
+
+namespace {
+
+constexpr int TTM_WAVES = 8;
+constexpr size_t TTM_LDS_MAX = 144 * 1024;
+
+template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS>
+hipError_t launch_ttm_t(const T *Y, const uint4 *Uq, T *Z, int64_t L, int64_t K, int64_t Rout,
+                        int64_t M, hipStream_t s) {
+    const int64_t P = L * M;
+    const int nchunks = (int)((K + KC - 1) / KC);
+    const int ntiles = (int)((Rout + 15) / 16);
+    const int nrb = (ntiles + RTB - 1) / RTB;
+    const int64_t nrowblocks = (P + 16 * NT - 1) / (16 * NT);
+    const size_t lds = ULDS ? (size_t)nchunks * RTB * Frag<PREC>::NQ * 64 * 16 : 0;
+    int64_t wgs = (nrowblocks + TTM_WAVES - 1) / TTM_WAVES;
+    const int per_cu = ULDS ? (int)std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / std::max<size_t>(lds, 1))) : 2;
+    const int64_t cap = (int64_t)device_cu_count() * per_cu;
+    if (ULDS && wgs > cap) wgs = cap;  // persistent: amortize the factor staging
+    if (wgs < 1) wgs = 1;
+    auto kern = ttm_kernel<T, PREC, NT, RTB, CONTIG, ULDS, TTM_WAVES>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)wgs, (unsigned)nrb), dim3(64 * TTM_WAVES), lds, s, Y, Uq,
+                       Z, L, K, Rout, P, nchunks, ntiles, nrowblocks);
+    return hipGetLastError();
+}
+
+template <typename T, int PREC, int RTB>
+hipError_t launch_ttm_r(const T *Y, const uint4 *Uq, T *Z, int64_t L, int64_t K, int64_t Rout,
+                        int64_t M, hipStream_t s) {
+    const int nchunks = (int)((K + KC - 1) / KC);
+    const size_t lds = (size_t)nchunks * RTB * Frag<PREC>::NQ * 64 * 16;
+    const bool contig = (L == 1) && (K % (16 / sizeof(T)) == 0) &&
+                        ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
+    // row tiles per wave: keeps a lane under 256 VGPRs (8 waves per workgroup)
+    constexpr int NT = (PREC == P_FP64) ? (RTB == 1 ? 2 : 1) : (RTB == 1 ? 4 : 2);
+    if (lds <= TTM_LDS_MAX) {
+        if (contig) return launch_ttm_t<T, PREC, NT, RTB, true, true>(Y, Uq, Z, L, K, Rout, M, s);
+        return launch_ttm_t<T, PREC, NT, RTB, false, true>(Y, Uq, Z, L, K, Rout, M, s);
+    }
+    if (contig) return launch_ttm_t<T, PREC, NT, RTB, true, false>(Y, Uq, Z, L, K, Rout, M, s);
+    return launch_ttm_t<T, PREC, NT, RTB, false, false>(Y, Uq, Z, L, K, Rout, M, s);
+}
+
+template <typename T, int PREC>
+hipError_t launch_ttm_p(const T *Y, const uint4 *Uq, T *Z, int64_t L, int64_t K, int64_t Rout,
+                        int64_t M, hipStream_t s) {
+    const int64_t ntiles = (Rout + 15) / 16;
+    if (ntiles <= 1) return launch_ttm_r<T, PREC, 1>(Y, Uq, Z, L, K, Rout, M, s);
+    if (ntiles <= 2) return launch_ttm_r<T, PREC, 2>(Y, Uq, Z, L, K, Rout, M, s);
+    return launch_ttm_r<T, PREC, 4>(Y, Uq, Z, L, K, Rout, M, s);
+}
+
+}  // namespace
+
+hipError_t ttm_launch(int dtype, int prec, const void *Y, const void *Uq, void *Z, int64_t L,
+                      int64_t K, int64_t Rout, int64_t M, hipStream_t s) {
+    if (L * M == 0 || Rout == 0) return hipSuccess;
+    const uint4 *uq = (const uint4 *)Uq;
+    if (dtype == DT_F64) {
+        return launch_ttm_p<double, P_FP64>((const double *)Y, uq, (double *)Z, L, K, Rout, M, s);
+    }
+    const float *y = (const float *)Y;
+    float *z = (float *)Z;
+    switch (prec) {
+        case P_FP64: return launch_ttm_p<float, P_FP64>(y, uq, z, L, K, Rout, M, s);
+        case P_FP32: return launch_ttm_p<float, P_FP32>(y, uq, z, L, K, Rout, M, s);
+        case P_BF16X3: return launch_ttm_p<float, P_BF16X3>(y, uq, z, L, K, Rout, M, s);
+        default: return launch_ttm_p<float, P_BF16X6>(y, uq, z, L, K, Rout, M, s);
+    }
+}
+
+}  // namespace sth
