@@ -130,7 +130,10 @@ class Plan:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.load().sthosvd_plan_destroy(h)
+            try:
+                _lib.load().sthosvd_plan_destroy(h)
+            except Exception:  # interpreter shutdown
+                pass
             self._h = None
 
     def run(self, X: torch.Tensor, G: torch.Tensor, U: List[torch.Tensor],

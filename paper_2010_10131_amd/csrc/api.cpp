@@ -343,6 +343,7 @@ extern "C" sth_status sthosvd_run(const sth_plan *p, const void *X, void *core, 
     void *uq = w + p->o_uq;
     void *gws = w + p->o_gemm;
     const int gp = gram_prec_of(*p), tp = ttm_prec_of(*p);
+    HIPCHK(zero_words(flag, 2, s), "flag clear");
 
     for (const Step &stp : p->steps) {
         const void *src = stp.src == 0 ? X : (stp.src == 1 ? (const void *)bufA : (const void *)bufB);
@@ -352,7 +353,7 @@ extern "C" sth_status sthosvd_run(const sth_plan *p, const void *X, void *core, 
             // Alg. 2 lines 6-8
             HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
             double *lam = eigvals ? eigvals[n] : nullptr;
-            HIPCHK(eig_launch(stp.I, stp.R, S, U[n], lam, 1e-15, p->max_sweeps, eigws, s), "eig");
+            HIPCHK(eig_launch(stp.I, stp.R, S, U[n], lam, 1e-15, p->max_sweeps, eigws, flag, s), "eig");
             HIPCHK(ttm_prep_u(U[n], stp.I, stp.R, 0, tp, uq, s), "ttm prep");
             HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
         } else {
@@ -481,7 +482,8 @@ extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double 
     sth_status st;
     if ((st = check_ptr(S, "S")) || (st = check_ptr(U, "U")) || (st = check_ptr(lam, "lam", true)) || (st = check_ptr(ws, "ws"))) return st;
     if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
-    HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (hipStream_t)stream), "eig");
+    HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (int64_t *)ws,
+                      (hipStream_t)stream), "eig");
     return STH_OK;
 }
 

@@ -6,7 +6,9 @@
 // lane t, group g = t / 16):
 //   A operand: lane t supplies row (t % 16) of A for the k-slice owned by g;
 //   B operand: lane t supplies column (t % 16) of B for the same k-slice;
-//   D:         lane t holds D[4g + v][t % 16], v = 0..3.
+//   D:         lane t holds D[4g + v][t % 16], v = 0..3, for the FP32 and
+//              bf16 instructions, but D[g + 4v][t % 16] for the FP64 one
+//              (measured on gfx950; see drow()).
 // Each lane owns 8 consecutive contraction indices k = 8g .. 8g+7 of a
 // 32-wide chunk.  The 16x16x32 bf16 instruction consumes all 8 at once; the
 // 16x16x4 FP32 / FP64 instructions consume one per instruction (8 of them
@@ -60,6 +62,10 @@ template <> struct Frag<P_BF16X6> {
     bf16x8 hi, mid, lo;
     static constexpr int NQ = 3;
 };
+
+// Row of the 16x16 output tile held by lane group g in accumulator slot v.
+template <int PREC> __device__ __forceinline__ int drow(int g, int v) { return 4 * g + v; }
+template <> __device__ __forceinline__ int drow<P_FP64>(int g, int v) { return g + 4 * v; }
 
 template <int PREC> struct Acc { typedef f32x4 type; };
 template <> struct Acc<P_FP64> { typedef f64x4 type; };

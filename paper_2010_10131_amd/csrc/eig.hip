@@ -18,11 +18,14 @@
 
 namespace sth {
 
-constexpr int EIG_THREADS = 1024;
+constexpr int EIG_THREADS = 256;
 
 __device__ __forceinline__ int rr_player(int x, int r, int ne) {
-    // round-robin position x (0..ne-1) in round r: player 0 fixed
-    return x == 0 ? 0 : ((x - 1 + r) % (ne - 1)) + 1;
+    // round-robin position x (0..ne-1) in round r (0..ne-2): player 0 fixed
+    if (x == 0) return 0;
+    int y = x - 1 + r;
+    if (y >= ne - 1) y -= ne - 1;
+    return y + 1;
 }
 
 template <bool ALDS, bool VLDS>
@@ -46,8 +49,9 @@ __global__ __launch_bounds__(EIG_THREADS) void jacobi_kernel(const double *__res
     const int tid = threadIdx.x;
     const int nn = n * n;
     for (int e = tid; e < nn; e += EIG_THREADS) {
-        A[e] = S[e];
-        V[e] = ((e % n) == (e / n)) ? 1.0 : 0.0;
+        const int i = e % n, j = e / n;
+        A[e] = 0.5 * (S[e] + S[j + n * i]);
+        V[e] = (i == j) ? 1.0 : 0.0;
     }
     const int ne = n + (n & 1);
     const int m = ne / 2;
@@ -55,14 +59,16 @@ __global__ __launch_bounds__(EIG_THREADS) void jacobi_kernel(const double *__res
 
     int sweep = 0;
     bool converged = false;
+    double prev_off2 = -1.0;
     for (;;) {
         // convergence test: off(A)^2 <= tol^2 ||A||_F^2
         double off = 0.0, fro = 0.0;
-        for (int e = tid; e < nn; e += EIG_THREADS) {
-            double v = A[e];
-            fro += v * v;
-            if ((e % n) != (e / n)) off += v * v;
-        }
+        for (int j = 0; j < n; ++j)
+            for (int i = tid; i < n; i += EIG_THREADS) {
+                const double v = A[i + n * j];
+                fro += v * v;
+                if (i != j) off += v * v;
+            }
         for (int o = 32; o > 0; o >>= 1) {
             off += __shfl_xor(off, o);
             fro += __shfl_xor(fro, o);
@@ -80,14 +86,19 @@ __global__ __launch_bounds__(EIG_THREADS) void jacobi_kernel(const double *__res
             }
             int stop = 0;
             if (o2 <= tol * tol * f2 || o2 == 0.0) stop = 1;
+            // roundoff floor: off(A) already at the FP64 noise level of an
+            // n x n rotation sequence and no longer shrinking
+            else if (o2 <= (double)n * n * 1.2e-32 * f2 && prev_off2 >= 0.0 && o2 >= 0.25 * prev_off2) stop = 1;
             else if (sweep >= max_sweeps) stop = 2;
             s_stop = stop;
+            s_red[0][0] = o2;  // broadcast for the stagnation test
         }
         __syncthreads();
         if (s_stop) {
             converged = (s_stop == 1);
             break;
         }
+        prev_off2 = s_red[0][0];
         for (int r = 0; r < ne - 1; ++r) {
             // rotations of this round
             for (int k = tid; k < m; k += EIG_THREADS) {
@@ -116,8 +127,9 @@ __global__ __launch_bounds__(EIG_THREADS) void jacobi_kernel(const double *__res
             __syncthreads();
             // A <- J^T A J, block (I, J) of pairs; V <- V J
             const int nb = m * m;
+            int I = tid % m, J = tid / m;
+            const int dI = EIG_THREADS % m, dJ = EIG_THREADS / m;
             for (int e = tid; e < nb; e += EIG_THREADS) {
-                const int I = e % m, J = e / m;
                 const int pi = s_p[I], qi = s_q[I], pj = s_p[J], qj = s_q[J];
                 const double ci = s_c[I], si = s_s[I], cj = s_c[J], sj = s_s[J];
                 const bool vi = qi < n, vj = qj < n;  // pair contains the dummy player?
@@ -136,16 +148,30 @@ __global__ __launch_bounds__(EIG_THREADS) void jacobi_kernel(const double *__res
                 if (vj) A[pi + n * qj] = d01;
                 if (vi) A[qi + n * pj] = d10;
                 if (vi && vj) A[qi + n * qj] = d11;
+                I += dI;
+                J += dJ;
+                if (I >= m) {
+                    I -= m;
+                    ++J;
+                }
             }
             const int nv = n * m;
+            int row = tid % n, Jv = tid / n;
+            const int dr = EIG_THREADS % n, dJv = EIG_THREADS / n;
             for (int e = tid; e < nv; e += EIG_THREADS) {
-                const int row = e % n, J = e / n;
-                const int pj = s_p[J], qj = s_q[J];
-                if (qj >= n) continue;
-                const double cj = s_c[J], sj = s_s[J];
-                double vp = V[row + n * pj], vq = V[row + n * qj];
-                V[row + n * pj] = cj * vp - sj * vq;
-                V[row + n * qj] = sj * vp + cj * vq;
+                const int pj = s_p[Jv], qj = s_q[Jv];
+                if (qj < n) {
+                    const double cj = s_c[Jv], sj = s_s[Jv];
+                    double vp = V[row + n * pj], vq = V[row + n * qj];
+                    V[row + n * pj] = cj * vp - sj * vq;
+                    V[row + n * qj] = sj * vp + cj * vq;
+                }
+                row += dr;
+                Jv += dJv;
+                if (row >= n) {
+                    row -= n;
+                    ++Jv;
+                }
             }
             __syncthreads();
         }
@@ -186,11 +212,105 @@ __global__ __launch_bounds__(EIG_THREADS) void jacobi_kernel(const double *__res
     }
 }
 
-size_t eig_ws_bytes(int64_t n) { return (size_t)(8 + 2 * n * n * sizeof(double) + 256); }
+// Sign rule on the columns of an n x R matrix: the entry of largest
+// magnitude of each column is made positive (first index on ties).
+__global__ void sign_fix_kernel(double *__restrict__ U, int n, int R) {
+    const int r = blockIdx.x;
+    __shared__ double s_v[256];
+    __shared__ int s_i[256];
+    double best = -1.0;
+    int arg = n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double v = fabs(U[i + (int64_t)n * r]);
+        if (v > best) {
+            best = v;
+            arg = i;
+        }
+    }
+    s_v[threadIdx.x] = best;
+    s_i[threadIdx.x] = arg;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) {
+            double v2 = s_v[threadIdx.x + o];
+            int i2 = s_i[threadIdx.x + o];
+            if (v2 > s_v[threadIdx.x] || (v2 == s_v[threadIdx.x] && i2 < s_i[threadIdx.x])) {
+                s_v[threadIdx.x] = v2;
+                s_i[threadIdx.x] = i2;
+            }
+        }
+        __syncthreads();
+    }
+    const bool neg = U[s_i[0] + (int64_t)n * r] < 0.0;
+    __syncthreads();
+    if (neg)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) U[i + (int64_t)n * r] = -U[i + (int64_t)n * r];
+}
 
-hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
-                      int max_sweeps, void *ws, hipStream_t s) {
-    int64_t *flag = (int64_t *)ws;
+namespace {
+
+constexpr int64_t EIG_DIRECT_MAX = 128;  // Jacobi on the whole matrix up to this order
+constexpr int64_t SI_BLOCK_MAX = 96;     // Rayleigh-Ritz block kept in LDS (A and V)
+constexpr int SI_ITERS = 6;              // subspace iterations before Rayleigh-Ritz
+
+int64_t si_block(int64_t n, int64_t R) {
+    int64_t p = std::max<int64_t>(R + 16, (3 * R + 1) / 2);
+    p = (p + 7) / 8 * 8;
+    return std::min(p, n);
+}
+
+bool use_si(int64_t n, int64_t R) { return n > EIG_DIRECT_MAX && si_block(n, R) <= SI_BLOCK_MAX; }
+
+struct SiWs {
+    double *Q, *Z, *Z2, *G, *Rf, *Rinv, *T, *W, *gws;
+    char *jac;
+};
+
+size_t jacobi_ws(int64_t n) { return (size_t)(256 + 2 * n * n * sizeof(double)); }
+
+SiWs si_layout(char *ws, int64_t n, int64_t p) {
+    SiWs w;
+    double *d = (double *)(ws + 256);
+    w.Q = d; d += n * p;
+    w.Z = d; d += n * p;
+    w.Z2 = d; d += n * p;
+    w.G = d; d += p * p;
+    w.Rf = d; d += p * p;
+    w.Rinv = d; d += p * p;
+    w.T = d; d += p * p;
+    w.W = d; d += p * p;
+    w.gws = d; d += std::max<size_t>(gemm_ws_bytes((int)p, (int)p, (int)n), gemm_ws_bytes((int)n, (int)p, (int)n)) / 8 + 1;
+    w.jac = (char *)d;
+    return w;
+}
+
+size_t si_bytes(int64_t n, int64_t p) {
+    return 256 + (size_t)(3 * n * p + 5 * p * p) * 8 +
+           std::max<size_t>(gemm_ws_bytes((int)p, (int)p, (int)n), gemm_ws_bytes((int)n, (int)p, (int)n)) + 8 +
+           jacobi_ws(p) + 256;
+}
+
+// Cholesky-QR of the n x p matrix A into Q; shift_rel > 0 gives the shifted
+// first pass of the shifted Cholesky-QR3 scheme (stable for condition numbers
+// up to ~1/eps).
+hipError_t cholqr_pass(const double *A, double *Q, int n, int p, double shift_rel, SiWs &w,
+                       int64_t *flag, hipStream_t s) {
+    hipError_t e;
+    if ((e = gemm_f64(1, 0, p, p, n, 1.0, A, n, A, n, 0.0, w.G, p, w.gws, s))) return e;
+    if ((e = chol_launch(w.G, p, p, shift_rel, nullptr, w.Rinv, flag, s))) return e;
+    return gemm_f64(0, 0, n, p, p, 1.0, A, n, w.Rinv, p, 0.0, Q, n, w.gws, s);
+}
+
+hipError_t orth3(double *A, double *Q, int n, int p, SiWs &w, int64_t *flag, hipStream_t s) {
+    hipError_t e;
+    const double shift = 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16;
+    if ((e = cholqr_pass(A, w.Z2, n, p, shift * p, w, flag, s))) return e;   // trace/p * p = trace
+    if ((e = cholqr_pass(w.Z2, A, n, p, 0.0, w, flag, s))) return e;
+    return cholqr_pass(A, Q, n, p, 0.0, w, flag, s);
+}
+
+hipError_t jacobi_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
+                         int max_sweeps, void *ws, int64_t *flag, hipStream_t s) {
     double *Ag = (double *)((char *)ws + 256);
     double *Vg = Ag + n * n;
     const size_t mat = (size_t)n * n * sizeof(double);
@@ -206,6 +326,45 @@ hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *
     } else {
         hipLaunchKernelGGL((jacobi_kernel<false, false>), dim3(1), dim3(EIG_THREADS), 0, s, S, (int)n, (int)R, Ag, Vg, U, lam, tol, max_sweeps, flag);
     }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t eig_ws_bytes(int64_t n) {
+    size_t b = jacobi_ws(n);
+    // subspace iteration for any R that selects it
+    for (int64_t R = 1; R <= n; ++R)
+        if (use_si(n, R)) b = std::max(b, si_bytes(n, si_block(n, R)));
+    return b;
+}
+
+// R leading eigenpairs of the symmetric n x n matrix S.
+//   n <= 128: cyclic Jacobi on S itself (one workgroup, LDS).
+//   n > 128 with a block p = max(R + 16, 1.5 R) <= 96: subspace iteration
+//     Q <- orth(S Q) from a seeded Gaussian block (SI_ITERS times; orth is
+//     shifted Cholesky-QR3), then Rayleigh-Ritz: Jacobi on T = Q^T S Q and
+//     U = Q W(:, :R), with the sign rule applied to U.
+//   otherwise: Jacobi on S with A and V in the workspace (slow; large R only).
+hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
+                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s) {
+    if (!use_si(n, R)) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
+    const int64_t p = si_block(n, R);
+    SiWs w = si_layout((char *)ws, n, p);
+    const int ni = (int)n, pi = (int)p;
+    hipError_t e;
+    if ((e = gaussian_f64(w.Z, n * p, 0x5EED5EEDull, (uint64_t)n * 1000 + p, s))) return e;
+    if ((e = orth3(w.Z, w.Q, ni, pi, w, flag, s))) return e;
+    for (int it = 0; it < SI_ITERS; ++it) {
+        if ((e = gemm_f64(0, 0, ni, pi, ni, 1.0, S, n, w.Q, n, 0.0, w.Z, n, w.gws, s))) return e;
+        if ((e = orth3(w.Z, w.Q, ni, pi, w, flag, s))) return e;
+    }
+    // Rayleigh-Ritz
+    if ((e = gemm_f64(0, 0, ni, pi, ni, 1.0, S, n, w.Q, n, 0.0, w.Z, n, w.gws, s))) return e;
+    if ((e = gemm_f64(1, 0, pi, pi, ni, 1.0, w.Q, n, w.Z, n, 0.0, w.T, p, w.gws, s))) return e;
+    if ((e = jacobi_launch(p, R, w.T, w.W, lam, tol, max_sweeps, w.jac, flag, s))) return e;
+    if ((e = gemm_f64(0, 0, ni, (int)R, pi, 1.0, w.Q, n, w.W, p, 0.0, U, n, w.gws, s))) return e;
+    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)R), dim3(256), 0, s, U, ni, (int)R);
     return hipGetLastError();
 }
 

@@ -219,7 +219,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const T *__restrict__ A, cons
             const int jl = wj * (16 * WT) + 16 * y + (lane & 15);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int il = wi * (16 * WT) + 16 * x + 4 * (lane >> 4) + v;
+                const int il = wi * (16 * WT) + 16 * x + drow<PREC>(lane >> 4, v);
                 double val = F64ACC ? (double)acc[x][y][v] : acc64[x][y][v];
                 dst[il + TB * jl] = val;
             }

@@ -32,7 +32,7 @@ hipError_t gram_launch(int dtype, int prec, const void *A, const void *B, int64_
 // Eigensolver (eig.hip)
 size_t eig_ws_bytes(int64_t n);
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
-                      int max_sweeps, void *ws, hipStream_t s);
+                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s);
 
 // Small FP64 LA and reductions (la.hip)
 int gemm_splits(int m, int n, int k);

@@ -119,18 +119,32 @@ hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const dou
     return hipGetLastError();
 }
 
-// One workgroup.  G (n x n, symmetric, ldg) + shift_rel * trace(G) / n * I
-// = R^T R.  Writes R (upper, n x n, may be NULL) and Rinv = R^{-1} (upper,
-// n x n).  A non-positive pivot sets flag[0] = 2 and is replaced by a tiny
+// One workgroup of 256 threads, n <= 128, everything in LDS.
+// G (n x n, symmetric, ldg) + shift_rel * trace(G) / n * I = L L^T, blocked
+// right-looking Cholesky with 16-column panels: the diagonal block is
+// factored by one wave in registers (row i of the block in lane i, columns
+// broadcast with cross-lane shuffles), the panel below by a row-parallel
+// forward substitution and the trailing matrix by an element-parallel
+// rank-16 update.  L is then inverted in place block column by block column
+// from the last one:  L^{-1}(B, K) = -(sum_{J in (K, B]} L^{-1}(B, J) L(J, K))
+// L(K, K)^{-1}.  Writes R = L^T (upper, may be NULL) and Rinv = L^{-T}
+// (upper).  A non-positive pivot sets flag[0] = 2 and is replaced by a tiny
 // positive one so that the run continues.
-__global__ __launch_bounds__(1024) void chol_kernel(const double *__restrict__ G, int n, int64_t ldg,
-                                                    double shift_rel, double *__restrict__ Rout,
-                                                    double *__restrict__ Rinv,
-                                                    int64_t *__restrict__ flag) {
-    extern __shared__ double s_l[];  // L (lower), n x n column-major
+constexpr int CHOL_THREADS = 256;
+constexpr int CB = 16;
+
+__global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(const double *__restrict__ G, int n,
+                                                            int64_t ldg, double shift_rel,
+                                                            double *__restrict__ Rout,
+                                                            double *__restrict__ Rinv,
+                                                            int64_t *__restrict__ flag) {
+    extern __shared__ double s_l[];  // L, column-major, leading dimension n; then T (n x CB)
+    double *s_tmp = s_l + n * n;
+    __shared__ double s_dinv[CB * CB];
     __shared__ double s_tr;
     const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += blockDim.x) {
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < n * n; e += CHOL_THREADS) {
         int i = e % n, j = e / n;
         s_l[e] = (i >= j) ? G[i + ldg * j] : 0.0;
     }
@@ -141,56 +155,136 @@ __global__ __launch_bounds__(1024) void chol_kernel(const double *__restrict__ G
     }
     __syncthreads();
     if (shift_rel != 0.0) {
-        double sh = shift_rel * s_tr / n;
-        for (int i = tid; i < n; i += blockDim.x) s_l[i + n * i] += sh;
+        const double sh = shift_rel * s_tr / n;
+        for (int i = tid; i < n; i += CHOL_THREADS) s_l[i + n * i] += sh;
         __syncthreads();
     }
     const double tiny = 1e-300 + 1e-30 * fabs(s_tr);
-    for (int k = 0; k < n; ++k) {
-        if (tid == 0) {
-            double d = s_l[k + n * k];
-            if (!(d > 0.0)) {
-                if (flag) flag[0] = 2;
-                d = tiny;
+    bool bad = false;
+    for (int k0 = 0; k0 < n; k0 += CB) {
+        const int kn = min(CB, n - k0);
+        // 1. diagonal block, wave 0, row i in lane i
+        if (wave == 0) {
+            double row[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) row[c] = (lane < kn && c < kn) ? s_l[k0 + lane + n * (k0 + c)] : 0.0;
+#pragma unroll
+            for (int j = 0; j < CB; ++j) {
+                if (j < kn) {
+                    // d = a(j,j) - sum_{c<j} L(j,c)^2, computed in lane j, then broadcast
+                    double sacc = row[j];
+#pragma unroll
+                    for (int c = 0; c < CB; ++c)
+                        if (c < j) sacc -= row[c] * __shfl(row[c], j);
+                    double d = __shfl(sacc, j);
+                    if (!(d > 0.0)) {
+                        bad = true;
+                        d = tiny;
+                    }
+                    d = sqrt(d);
+                    if (lane == j) row[j] = d;
+                    else if (lane > j) row[j] = sacc / d;
+                }
             }
-            s_l[k + n * k] = sqrt(d);
+            if (lane < kn)
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    if (c < kn) s_l[k0 + lane + n * (k0 + c)] = (c <= lane) ? row[c] : 0.0;
         }
         __syncthreads();
-        const double dk = s_l[k + n * k];
-        for (int i = k + 1 + tid; i < n; i += blockDim.x) s_l[i + n * k] /= dk;
+        // 2. panel rows i >= k0 + kn: forward substitution against the block
+        for (int i = k0 + kn + tid; i < n; i += CHOL_THREADS) {
+            double x[CB];
+#pragma unroll
+            for (int c = 0; c < CB; ++c) {
+                if (c < kn) {
+                    double sacc = s_l[i + n * (k0 + c)];
+#pragma unroll
+                    for (int d = 0; d < CB; ++d)
+                        if (d < c) sacc -= x[d] * s_l[k0 + c + n * (k0 + d)];
+                    x[c] = sacc / s_l[k0 + c + n * (k0 + c)];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                if (c < kn) s_l[i + n * (k0 + c)] = x[c];
+        }
         __syncthreads();
-        const int w = n - k - 1;
-        for (int e = tid; e < w * w; e += blockDim.x) {
-            int i = k + 1 + e % w, j = k + 1 + e / w;
-            if (i >= j) s_l[i + n * j] -= s_l[i + n * k] * s_l[j + n * k];
+        // 3. trailing update of the lower part
+        const int t0 = k0 + kn, w = n - t0;
+        for (int e = tid; e < w * w; e += CHOL_THREADS) {
+            const int i = t0 + e % w, j = t0 + e / w;
+            if (i < j) continue;
+            double sacc = 0.0;
+#pragma unroll
+            for (int c = 0; c < CB; ++c)
+                if (c < kn) sacc += s_l[i + n * (k0 + c)] * s_l[j + n * (k0 + c)];
+            s_l[i + n * j] -= sacc;
         }
         __syncthreads();
     }
+    if (bad && flag) flag[0] = 2;
     if (Rout)
-        for (int e = tid; e < n * n; e += blockDim.x) {
+        for (int e = tid; e < n * n; e += CHOL_THREADS) {
             int i = e % n, j = e / n;  // R(i, j) = L(j, i)
             Rout[e] = (i <= j) ? s_l[j + n * i] : 0.0;
         }
-    // Linv column j (lower), one thread per column; Rinv = Linv^T
-    for (int j = tid; j < n; j += blockDim.x) {
-        // x = Linv(:, j): L x = e_j
-        for (int i = 0; i < j; ++i) Rinv[j + (int64_t)n * i] = 0.0;  // Rinv(j, i) = Linv(i, j) = 0, i < j
-        double xj = 1.0 / s_l[j + n * j];
-        Rinv[j + (int64_t)n * j] = xj;
-        for (int i = j + 1; i < n; ++i) {
-            double sacc = 0.0;
-            for (int kk = j; kk < i; ++kk) sacc += s_l[i + n * kk] * Rinv[j + (int64_t)n * kk];
-            Rinv[j + (int64_t)n * i] = -sacc / s_l[i + n * i];
+    __syncthreads();
+    // in-place inverse, block columns from the last one
+    const int nb = (n + CB - 1) / CB;
+    for (int kb = nb - 1; kb >= 0; --kb) {
+        const int k0 = kb * CB, kn = min(CB, n - k0), t0 = k0 + kn;
+        // D^{-1} of the diagonal block (lower), one thread per column
+        if (tid < kn) {
+            const int c = tid;
+            double x[CB];
+#pragma unroll
+            for (int r = 0; r < CB; ++r) {
+                if (r < kn) {
+                    double sacc = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+                    for (int d = 0; d < CB; ++d)
+                        if (d < r) sacc -= s_l[k0 + r + n * (k0 + d)] * x[d];
+                    x[r] = (r < c) ? 0.0 : sacc / s_l[k0 + r + n * (k0 + r)];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < CB; ++r)
+                if (r < kn) s_dinv[r + CB * c] = x[r];
         }
+        // T(i, c) = sum_{j in [t0, i]} Linv(i, j) L(j, k0 + c) for rows i >= t0
+        for (int e = tid; e < (n - t0) * kn; e += CHOL_THREADS) {
+            const int i = t0 + e % (n - t0), c = e / (n - t0);
+            double sacc = 0.0;
+            for (int j = t0; j <= i; ++j) sacc += s_l[i + n * j] * s_l[j + n * (k0 + c)];
+            s_tmp[(i - t0) + (n - t0) * c] = sacc;
+        }
+        __syncthreads();
+        // Linv(i, k0 + c) = -sum_d T(i, d) Dinv(d, c);  diagonal block = Dinv
+        for (int e = tid; e < (n - t0) * kn; e += CHOL_THREADS) {
+            const int i = t0 + e % (n - t0), c = e / (n - t0);
+            double sacc = 0.0;
+            for (int d = c; d < kn; ++d) sacc += s_tmp[(i - t0) + (n - t0) * d] * s_dinv[d + CB * c];
+            s_l[i + n * (k0 + c)] = -sacc;
+        }
+        for (int e = tid; e < kn * kn; e += CHOL_THREADS) {
+            const int r = e % kn, c = e / kn;
+            s_l[k0 + r + n * (k0 + c)] = (r >= c) ? s_dinv[r + CB * c] : 0.0;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += CHOL_THREADS) {
+        int i = e % n, j = e / n;  // Rinv(i, j) = Linv(j, i)
+        Rinv[e] = (i <= j) ? s_l[j + n * i] : 0.0;
     }
 }
 
 hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, double *R,
                        double *Rinv, int64_t *flag, hipStream_t s) {
-    size_t lds = (size_t)n * n * sizeof(double);
+    size_t lds = (size_t)(n * n + n * CB) * sizeof(double);
     if (lds > 64 * 1024)
         hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(1024), lds, s, G, n, ldg, shift_rel, R, Rinv, flag);
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(CHOL_THREADS), lds, s, G, n, ldg, shift_rel, R, Rinv, flag);
     return hipGetLastError();
 }
 

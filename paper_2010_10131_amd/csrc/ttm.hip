@@ -178,21 +178,22 @@ __global__ __launch_bounds__(64 * WAVES) void ttm_kernel(
             }
         }
 
-        // D[r][p]: lane holds r = 16*rt + 4g + v, p = 16*nt + lane%16
+        // D[r][p]: lane holds r = 16*rt + drow(g, v), p = 16*nt + lane%16
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (!pvalid[nt]) continue;
 #pragma unroll
             for (int rt = 0; rt < RTB; ++rt) {
-                const int64_t r0 = (int64_t)(rt0 + rt) * 16 + 4 * g;
-                if (CONTIG && sizeof(T) == 4 && (Rout & 3) == 0 && r0 + 4 <= Rout) {
+                const int64_t rbase = (int64_t)(rt0 + rt) * 16;
+                const int64_t r0 = rbase + 4 * g;
+                if (PREC != P_FP64 && CONTIG && sizeof(T) == 4 && (Rout & 3) == 0 && r0 + 4 <= Rout) {
                     float4 v = make_float4((float)acc[nt][rt][0], (float)acc[nt][rt][1],
                                            (float)acc[nt][rt][2], (float)acc[nt][rt][3]);
                     *reinterpret_cast<float4 *>(Z + zoff[nt] + r0) = v;
                 } else {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        int64_t r = r0 + v;
+                        int64_t r = rbase + drow<PREC>(g, v);
                         if (r < Rout) Z[zoff[nt] + L * r] = (T)acc[nt][rt][v];
                     }
                 }

@@ -1,0 +1,127 @@
+"""Host-side checks of the C ABI: the library loads, exports every function
+include/sthosvd.h declares, and validates plans before any launch.  No
+kernel runs here (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sthosvd.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[\w\s\*]+?\b(\w+)\s*\(", txt, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while", "defined")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2010_10131_amd import _lib
+    return _lib.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_2010_10131_amd import _lib
+    assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
+
+
+def test_version_and_error_string(lib):
+    assert lib.sth_version().startswith(b"sthosvd")
+    assert isinstance(lib.sth_last_error(), bytes)
+
+
+def _plan(**kw):
+    import torch
+    from paper_2010_10131_amd import api
+    args = dict(dims=(16, 12, 10), ranks=(4, 3, 2), dtype=torch.float32, gram_prec="fp32",
+                ttm_prec="fp32")
+    args.update(kw)
+    return api.Plan(**args)
+
+
+def _err(**kw):
+    from paper_2010_10131_amd._lib import SthError
+    with pytest.raises(SthError) as e:
+        _plan(**kw)
+    return e.value.status
+
+
+def test_plan_validation_errors():
+    import torch
+    from paper_2010_10131_amd import _lib
+    INV, NOMEM, UNSUP = _lib.STH_ERR_INVALID, _lib.STH_ERR_NOMEM, _lib.STH_ERR_UNSUPPORTED
+    assert _err(ranks=(4, 13, 2)) == INV           # R > I
+    assert _err(ranks=(4, 0, 2)) == INV            # R < 1
+    assert _err(dims=(16, 0, 10)) == INV           # empty mode
+    assert _err(dims=(2,) * 9, ranks=(1,) * 9) == INV   # order > 8
+    assert _err(mode_order=(0, 0, 1)) == INV       # not a permutation
+    assert _err(dtype=torch.float64) == INV        # FP64 data needs FP64 contractions
+    assert _err(gram_prec=7) == INV
+    assert _err(solver=9) == INV
+    assert _err(per_mode=(0, 5, 0)) == INV
+    assert _err(workspace_cap=1024) == NOMEM       # cap below the need
+    assert _err(dims=(600, 4, 4), ranks=(8, 2, 2)) == UNSUP  # EIG beyond the eigensolver limit
+    assert _err(dims=(600, 300, 4), ranks=(8, 200, 2), per_mode=("als", "als", "eig")) == UNSUP
+
+
+def test_plan_shapes_solvers_and_workspace():
+    import torch
+    p = _plan()
+    assert p.solvers == [0, 0, 0]
+    base = p.workspace_bytes
+    # the ping-pong buffers hold at least the mode-1 and mode-2 outputs
+    assert base >= 4 * (4 * 12 * 10 + 4 * 3 * 10)
+    q = _plan(per_mode=("als", "eig", "als"))
+    assert q.solvers == [1, 0, 1]
+    assert q.workspace_bytes > base                 # ALS needs the R_k tensor and small LA
+    r = _plan(dims=(16, 12, 10), ranks=(16, 12, 10))  # R = I: a rotation
+    assert r.workspace_bytes > 0
+    s = _plan(dims=(16, 12, 10), ranks=(4, 3, 2), mode_order=(2, 0, 1))
+    assert s.solvers == [0, 0, 0]
+    f = _plan(dtype=torch.float64, gram_prec="fp64", ttm_prec="fp64")
+    assert f.workspace_bytes > base                 # FP64 working tensors
+
+
+def test_building_block_workspace_queries(lib):
+    from paper_2010_10131_amd._lib import i64arr
+    dims = i64arr([64, 32, 16])
+    assert lib.gram_mode_n_workspace(3, dims, 1, 0) > 0
+    assert lib.gram_mode_n_workspace(3, dims, 1, 8) > 0
+    assert lib.gram_mode_n_workspace(3, dims, 3, 0) == 0      # bad mode
+    assert lib.ttm_mode_n_workspace(64, 8) >= 2 * 1 * 64 * 16 * 4
+    assert lib.eig_leading_workspace(64) >= 2 * 64 * 64 * 8
+    ranks = i64arr([4, 4, 4])
+    assert lib.tucker_reconstruct_workspace(3, dims, ranks, 1) > 0
+    assert lib.tucker_error_workspace(3, dims, ranks, 1) > lib.tucker_reconstruct_workspace(3, dims, ranks, 1)
+
+
+def test_entry_points_reject_bad_arguments_before_launch(lib):
+    from paper_2010_10131_amd import _lib
+    dims = _lib.i64arr([8, 8, 8])
+    # NULL pointers and misaligned pointers are rejected without touching the device
+    st = lib.gram_mode_n(3, dims, 0, 1, 1, None, None, None, 0, None)
+    assert st == _lib.STH_ERR_INVALID
+    st = lib.gram_mode_n(3, dims, 0, 1, 1, ctypes.c_void_p(0x1004), ctypes.c_void_p(0x2000),
+                         ctypes.c_void_p(0x3000), 1 << 20, None)
+    assert st == _lib.STH_ERR_LAYOUT
+    st = lib.gram_mode_n(3, dims, 5, 1, 1, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                         ctypes.c_void_p(0x3000), 1 << 20, None)
+    assert st == _lib.STH_ERR_INVALID
+    st = lib.gram_mode_n(3, dims, 0, 1, 1, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000),
+                         ctypes.c_void_p(0x3000), 16, None)
+    assert st == _lib.STH_ERR_NOMEM
+    st = lib.eig_leading(600, 4, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), None, 0,
+                         ctypes.c_void_p(0x3000), 1 << 30, None)
+    assert st == _lib.STH_ERR_UNSUPPORTED
+    st = lib.ttm_mode_n(3, dims, 1, 0, 1, 1, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 0,
+                        ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), 1 << 20, None)
+    assert st == _lib.STH_ERR_INVALID
+    assert b"R" in lib.sth_last_error()

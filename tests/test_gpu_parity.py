@@ -1,0 +1,302 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances.  FP64 work is compared at 1e-12 relative or tighter.  For the
+reduced-precision contractions every output is checked against an
+elementwise error bound built from the same contraction on absolute values,
+|got - ref| <= tol * (|A| x |B|), with tol per precision:
+  fp32   products exact to 2^-24, FP32 sums within a chunk of <= 128 terms,
+         FP64 across chunks:           tol = 2^-24 (1 + 2 * min(K, 128))
+  bf16x3 operands carried to 2^-17, the lo*lo cross terms dropped:
+                                        tol = 2^-15 + 2^-24 (1 + 2 * min(K, 128))
+  bf16x6 operands to 2^-25:             tol = 2^-21 + 2^-24 (1 + 2 * min(K, 128))
+where K is the contraction length.  Whole decompositions are compared by
+T1 = | ||G|| - ||G*|| | / ||G*|| and T2 = ||X^ - X^*|| / ||X|| (invariant to
+factor signs and to rotations inside degenerate eigenspaces).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+U24 = 2.0 ** -24
+
+
+def tol_for(prec, K):
+    acc = U24 * (1 + 2 * min(K, 128))
+    return {"fp64": 64 * K * 2.0 ** -53, "fp32": acc, "bf16x3": 2.0 ** -15 + acc,
+            "bf16x6": 2.0 ** -21 + acc}[prec]
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    from paper_2010_10131_amd import api as a
+    return a
+
+
+def randn(shape, seed, dtype="float32"):
+    return np.asfortranarray(np.random.default_rng(seed).standard_normal(shape).astype(dtype))
+
+
+def check_bound(got, ref, bound, tol, what):
+    err = np.abs(got - ref)
+    lim = tol * bound + 1e-300
+    bad = err > lim
+    assert not bad.any(), (f"{what}: {bad.sum()} of {bad.size} outside bound; worst ratio "
+                           f"{(err / lim).max():.3g}")
+
+
+# ------------------------------------------------------------------- TTM ----
+
+TTM_CASES = [
+    # dims, mode, R  (L = 1; L >= 64; small L; M = 1; ragged K / R / rows)
+    ((64, 40, 3), 0, 8),
+    ((37, 50, 9), 0, 5),          # ragged K, odd rows
+    ((100, 33), 0, 17),           # two r-tiles with a ragged one
+    ((64, 64, 64), 1, 16),        # L = 64
+    ((96, 20, 7), 1, 64),         # L = 96, R = 64
+    ((8, 48, 30), 1, 8),          # small L (C5-like mode 2)
+    ((3, 65, 11), 1, 33),         # L = 3, ragged K
+    ((16, 160, 5), 1, 16),        # L = 16 (C3-like mode 2)
+    ((12, 10, 70), 2, 70),        # M = 1, R = K (rotation), three r-blocks... ragged
+    ((5, 7, 130), 2, 130),        # R > 64: several r-blocks
+    ((1, 1, 1), 1, 1),            # degenerate
+    ((200, 3), 1, 2),             # M = 1, tiny K
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("dims,n,R", TTM_CASES)
+def test_ttm_parity(api, dims, n, R, prec):
+    dtype = "float64" if prec == "fp64" else "float32"
+    Y = randn(dims, 100 + sum(dims) + n, dtype)
+    K = dims[n]
+    U = np.asfortranarray(np.random.default_rng(7 + K + R).standard_normal((K, R)))
+    Z = api.to_numpy(api.ttm_mode_n(api.to_device(Y), api.to_device(U), n, prec))
+    ref = oracle.ttm_tensor(Y, U.T, n)
+    bound = oracle.ttm_tensor(np.abs(Y), np.abs(U).T, n)
+    check_bound(Z, ref, bound, tol_for(prec, K), f"ttm {dims} n={n} R={R} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_ttm_transposed_factor_expands(api, prec):
+    dtype = "float64" if prec == "fp64" else "float32"
+    Y = randn((6, 5, 7), 3, dtype)
+    W = np.asfortranarray(np.random.default_rng(4).standard_normal((40, 5)))  # I x R factor
+    Z = api.to_numpy(api.ttm_mode_n(api.to_device(Y), api.to_device(W), 1, prec, transpose_u=True))
+    ref = oracle.ttm_tensor(Y, W, 1)
+    check_bound(Z, ref, oracle.ttm_tensor(np.abs(Y), np.abs(W), 1), tol_for(prec, 5), "ttm^T")
+
+
+# ------------------------------------------------------------ Gram / TTT ----
+
+GRAM_CASES = [
+    ((64, 40, 3), 0),
+    ((37, 50, 9), 0),
+    ((130, 20, 6), 0),            # I > 128: several blocks incl. ragged
+    ((64, 64, 20), 1),            # L = 64
+    ((8, 48, 300), 1),            # small L, many rows
+    ((3, 65, 11), 1),
+    ((16, 100, 40), 2),           # M = 1
+    ((1, 5, 1), 1),
+    ((2, 3, 5000), 0),            # I = 2, long contraction (split-K)
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("dims,n", GRAM_CASES)
+def test_gram_parity(api, dims, n, prec):
+    dtype = "float64" if prec == "fp64" else "float32"
+    Y = randn(dims, 200 + sum(dims) + n, dtype)
+    S = api.to_numpy(api.gram_mode_n(api.to_device(Y), n, prec))
+    Yn = oracle.unfold(Y, n)
+    ref = oracle.gram(Yn)
+    bound = oracle.gram(np.abs(Yn))
+    assert np.array_equal(S, S.T)
+    K = Yn.shape[1]
+    check_bound(S, ref, bound, tol_for(prec, K), f"gram {dims} n={n} {prec}")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("dims,n,R", [((64, 40, 3), 0, 8), ((16, 96, 30), 1, 20),
+                                      ((5, 7, 130), 2, 3), ((200, 9), 0, 150)])
+def test_ttt_parity(api, dims, n, R, prec):
+    dtype = "float64" if prec == "fp64" else "float32"
+    Y = randn(dims, 300 + sum(dims), dtype)
+    zd = list(dims)
+    zd[n] = R
+    Z = randn(tuple(zd), 301 + R, dtype)
+    P = api.to_numpy(api.ttt_mode_n(api.to_device(Y), api.to_device(Z), n, prec))
+    Yn, Zn = oracle.unfold(Y, n), oracle.unfold(Z, n)
+    ref = oracle.ttt(Yn, Zn)
+    check_bound(P, ref, oracle.ttt(np.abs(Yn), np.abs(Zn)), tol_for(prec, Yn.shape[1]), "ttt")
+
+
+# ---------------------------------------------------------------- eigen ----
+
+def spd_with_spectrum(lam, seed):
+    n = len(lam)
+    Q, _ = np.linalg.qr(np.random.default_rng(seed).standard_normal((n, n)))
+    return np.asfortranarray((Q * lam) @ Q.T)
+
+
+@pytest.mark.parametrize("n,R", [(1, 1), (2, 1), (5, 3), (16, 16), (33, 7), (64, 8), (90, 30),
+                                 (100, 10), (128, 64), (160, 16)])
+def test_eig_parity(api, n, R):
+    lam = 2.0 ** (-np.arange(n) / 4.0)          # distinct, gaps >> roundoff
+    S = spd_with_spectrum(lam, n)
+    U, ev, ws = api.eig_leading(api.to_device(S), R)
+    U, ev = api.to_numpy(U), ev.cpu().numpy()
+    assert int(ws[:8].view(dtype=__import__("torch").int64).item()) == 0
+    lo, Vo, _ = oracle.jacobi_eig(S)
+    np.testing.assert_allclose(ev, lo[:R], rtol=0, atol=1e-13 * lo[0] * max(1, n / 16))
+    np.testing.assert_allclose(U, Vo[:, :R], rtol=0, atol=1e-10)
+    np.testing.assert_allclose(U.T @ U, np.eye(R), atol=1e-12)
+
+
+@pytest.mark.parametrize("n,R", [(129, 8), (200, 16), (256, 40), (512, 64), (512, 8)])
+def test_eig_subspace_iteration_parity(api, n, R):
+    """n > 128: subspace iteration + Rayleigh-Ritz.  The spectrum has the
+    structure of a low-rank-plus-noise Gram (a gap after the R leading
+    eigenvalues), so the leading eigenvectors are well determined."""
+    lam = np.concatenate([2.0 ** (-np.arange(R) / 4.0), 1e-7 * np.exp(-np.arange(n - R) / n)])
+    S = spd_with_spectrum(lam, n + R)
+    U, ev, ws = api.eig_leading(api.to_device(S), R)
+    U, ev = api.to_numpy(U), ev.cpu().numpy()
+    assert int(ws[:8].view(dtype=__import__("torch").int64).item()) == 0
+    lo, Vo, _ = oracle.jacobi_eig(S)
+    np.testing.assert_allclose(ev, lo[:R], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(U, Vo[:, :R], rtol=0, atol=1e-9)
+    np.testing.assert_allclose(U.T @ U, np.eye(R), atol=1e-12)
+
+
+def test_eig_degenerate_and_cap(api):
+    import torch
+    S = np.asfortranarray(np.diag([3.0, 1.0, 3.0, 2.0]))
+    U, ev, ws = api.eig_leading(api.to_device(S), 3)
+    np.testing.assert_array_equal(ev.cpu().numpy(), [3.0, 3.0, 2.0])
+    # ties by index: eigenvectors e0, e2, e3
+    np.testing.assert_array_equal(api.to_numpy(U), np.eye(4)[:, [0, 2, 3]])
+    A = randn((12, 12), 5, "float64")
+    S2 = np.asfortranarray(A @ A.T)
+    U, ev, ws = api.eig_leading(api.to_device(S2), 2, max_sweeps=1)
+    torch.cuda.synchronize()
+    assert int(ws[:8].view(dtype=torch.int64).item()) == 1   # sweep cap reported
+
+
+# -------------------------------------------------------- decomposition ----
+
+def t1_t2(api, X, G, U, Go, Uo):
+    Gn = api.to_numpy(G)
+    Un = [api.to_numpy(u) for u in U]
+    Xh = oracle.reconstruct(Gn, Un)
+    Xho = oracle.reconstruct(Go, Uo)
+    t2 = np.linalg.norm(Xh - Xho) / np.linalg.norm(np.asarray(X, dtype=np.float64))
+    t1 = abs(np.linalg.norm(Gn) - np.linalg.norm(Go)) / np.linalg.norm(Go)
+    return t1, t2, Gn, Un
+
+
+def test_c1_fp64_matches_oracle(api):
+    """The small parity workload: 64^3 FP64, ranks 8, 1e-3 noise, EIG, order 1,2,3."""
+    X = wl.make(wl.C1)
+    G, U, ev = api.sthosvd(api.to_device(X), wl.C1.ranks, "fp64", "fp64", return_eigvals=True)
+    Go, Uo, lo = oracle.sthosvd(X, wl.C1.ranks)
+    t1, t2, Gn, Un = t1_t2(api, X, G, U, Go, Uo)
+    assert t1 <= 1e-12 and t2 <= 1e-12, (t1, t2)
+    for n in range(3):
+        np.testing.assert_allclose(Un[n], Uo[n], rtol=0, atol=1e-10)
+        np.testing.assert_allclose(ev[n].cpu().numpy(), lo[n][:8], rtol=1e-12)
+    np.testing.assert_allclose(Gn, Go, rtol=0, atol=1e-10 * np.abs(Go).max())
+
+
+@pytest.mark.parametrize("dims,ranks,order", [
+    ((30, 20), (6, 6), None),                          # N = 2: truncated SVD
+    ((12, 10, 9, 8), (3, 4, 2, 5), (3, 1, 0, 2)),      # 4-way, permuted order
+    ((10, 9, 8, 7, 6), (2, 3, 2, 3, 2), None),         # 5-way
+    ((16, 12, 10), (16, 12, 10), None),                # R = I: rotations
+    ((20, 15, 10), (1, 1, 1), None),                   # R = 1
+    ((1, 17, 5), (1, 4, 2), None),                     # a mode of size 1
+])
+def test_decomposition_fp64_edge_cases(api, dims, ranks, order):
+    X = wl.lowrank_plus_noise(dims, tuple(min(r, d) for r, d in zip(ranks, dims)), "none", 1e-2,
+                              sum(dims), "float64")
+    G, U, _ = api.sthosvd(api.to_device(X), ranks, "fp64", "fp64", mode_order=order)
+    Go, Uo, _ = oracle.sthosvd(X, ranks, order=order)
+    t1, t2, _, _ = t1_t2(api, X, G, U, Go, Uo)
+    assert t1 <= 1e-11 and t2 <= 1e-11, (t1, t2)
+
+
+@pytest.mark.parametrize("variant_dims,ranks,per_mode", [
+    ((24, 20, 18), (4, 5, 3), ("als", "als", "als")),
+    ((24, 20, 18), (4, 5, 3), ("eig", "als", "eig")),
+    ((40, 12, 9, 7), (5, 3, 4, 2), ("als", "eig", "als", "als")),
+])
+def test_als_fp64_matches_oracle(api, variant_dims, ranks, per_mode):
+    """ALS branch (Alg. 3 with L_k re-orthonormalized) against the oracle's
+    re-orthonormalized variant, same initial guesses: same subspaces, so the
+    same X^ and ||G|| (factors may differ by a rotation)."""
+    dims = variant_dims
+    X = wl.lowrank_plus_noise(dims, ranks, "none", 1e-3, 77, "float64")
+    L0 = [wl.gaussian_init(d, r, 9, n) for n, (d, r) in enumerate(zip(dims, ranks))]
+    G, U, _ = api.sthosvd(api.to_device(X), ranks, "fp64", "fp64", per_mode=per_mode,
+                          als_init=L0)
+    meth = [0 if m == "eig" else 1 for m in per_mode]
+    Go, Uo, _ = oracle.sthosvd(X, ranks, methods=meth, L0=L0, als_variant=1)
+    t1, t2, _, Un = t1_t2(api, X, G, U, Go, Uo)
+    assert t1 <= 1e-10 and t2 <= 1e-10, (t1, t2)
+    for n in range(len(dims)):
+        np.testing.assert_allclose(Un[n].T @ Un[n], np.eye(ranks[n]), atol=1e-12)
+        np.testing.assert_allclose(Un[n] @ Un[n].T, Uo[n] @ Uo[n].T, atol=1e-9)
+
+
+def test_als_device_initial_guess_runs(api):
+    X = wl.lowrank_plus_noise((30, 20, 10), (3, 3, 3), "none", 0.0, 3, "float64")
+    G, U, _ = api.sthosvd(api.to_device(X), (3, 3, 3), "fp64", "fp64", solver="als", seed=5)
+    Xh = oracle.reconstruct(api.to_numpy(G), [api.to_numpy(u) for u in U])
+    assert np.linalg.norm(Xh - X) / np.linalg.norm(X) <= 1e-11
+
+
+@pytest.mark.parametrize("gp,tp,t2max", [("fp64", "fp32", 1e-6), ("fp32", "fp32", 1e-5),
+                                         ("bf16x6", "bf16x3", 1e-5), ("bf16x3", "bf16x3", 1e-4)])
+def test_fp32_data_recipes(api, gp, tp, t2max):
+    """FP32 data, 48^3 with ranks 6 and decaying core: every recipe against the FP64 oracle."""
+    X = wl.lowrank_plus_noise((48, 40, 36), (6, 6, 6), "0.9", 1e-4, 31, "float32")
+    G, U, _ = api.sthosvd(api.to_device(X), (6, 6, 6), gp, tp)
+    Go, Uo, _ = oracle.sthosvd(X, (6, 6, 6))
+    t1, t2, _, Un = t1_t2(api, X, G, U, Go, Uo)
+    assert t2 <= t2max and t1 <= t2max, (gp, tp, t1, t2)
+    for u in Un:
+        np.testing.assert_allclose(u.T @ u, np.eye(u.shape[1]), atol=1e-12)
+
+
+# -------------------------------------------------------- reconstruction ----
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_reconstruct_and_error(api, prec):
+    dtype = "float64" if prec == "fp64" else "float32"
+    dims, ranks = (20, 14, 9), (5, 4, 3)
+    G = randn(ranks, 1, dtype)
+    U = [randn((d, r), 2 + d, "float64") for d, r in zip(dims, ranks)]
+    Xh = api.to_numpy(api.tucker_reconstruct(api.to_device(G), [api.to_device(u) for u in U], prec))
+    ref = oracle.reconstruct(G, U)
+    bound = oracle.reconstruct(np.abs(G), [np.abs(u) for u in U])
+    check_bound(Xh, ref, bound, 3 * tol_for(prec, 5), "reconstruct")
+    X = randn(dims, 9, dtype)
+    out = api.tucker_error(api.to_device(X), api.to_device(G), [api.to_device(u) for u in U], prec)
+    e2, x2 = out.cpu().numpy()
+    Xf = X.astype(np.float64)
+    assert abs(x2 - np.sum(Xf * Xf)) <= 1e-12 * np.sum(Xf * Xf)
+    assert abs(e2 - np.sum((Xf - ref) ** 2)) <= 1e-5 * np.sum((Xf - ref) ** 2)
+
+
+def test_sumsq(api):
+    x = randn((1000, 37), 11, "float32")
+    got = float(api.sumsq(api.to_device(x)).item())
+    ref = oracle.sumsq(x)
+    assert abs(got - ref) <= 1e-13 * ref
