@@ -211,6 +211,61 @@ sth_status tucker_error(int32_t order, const int64_t *dims, const int64_t *ranks
                         int32_t prec, const void *X, const void *G, const double *const *U,
                         double *out, void *ws, size_t ws_bytes, sth_stream_t stream);
 
+/* ---------------------------------------------------------------------------
+ * One mode of Alg. 2 (the loop body: EIG branch, lines 6-8, or ALS branch,
+ * lines 10-13 with Alg. 3) on a working tensor Y with the given dims:
+ * Z (device, dims with dims[n] replaced by R, dtype) receives the shrunk
+ * tensor, U (device, dims[n] x R FP64) the factor, eigvals (device, R FP64,
+ * may be NULL; EIG only) the leading eigenvalues.  als_init: NULL or device
+ * dims[n] x R FP64 initial guess (ALS only; NULL = seeded Gaussian).
+ * solver: STH_SOLVER_EIG or STH_SOLVER_ALS.  Used to time both solvers per
+ * mode for the selector's training data (Sec. IV-B).
+ * ------------------------------------------------------------------------- */
+size_t sthosvd_mode_step_workspace(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                                   int32_t dtype, int32_t gram_prec, int32_t ttm_prec,
+                                   int32_t solver, int32_t als_iters);
+sth_status sthosvd_mode_step(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                             int32_t dtype, int32_t gram_prec, int32_t ttm_prec, int32_t solver,
+                             int32_t als_iters, const void *Y, void *Z, double *U, double *eigvals,
+                             const double *als_init, uint64_t seed, void *ws, size_t ws_bytes,
+                             sth_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Learned solver selector (the role of the Sec. IV decision tree, with a
+ * small MLP cost model).  Features are the ten Table I quantities of a mode
+ * (I_n, R_n, J_n, I_n^2, R_n^2, I_n R_n, R_n^2/I_n, R_n^2/J_n, I_n/J_n,
+ * R_n/J_n), log-scaled; the network 10 -> 32 -> 32 -> 2 (tanh hidden layers)
+ * predicts (log t_EIG, log t_ALS) and the selector takes the smaller.
+ * Parameters are packed floats: W1 (32x10 column-major), b1, W2 (32x32), b2,
+ * W3 (2x32), b3, then the feature mean (10) and inverse std (10).
+ * ------------------------------------------------------------------------- */
+int32_t sth_selector_num_params(void);    /* all packed floats */
+int32_t sth_selector_num_trainable(void); /* leading floats that training updates */
+/* Host: the ten log-scaled features of a mode (out10: host, 10 floats). */
+sth_status sth_selector_features(int64_t I, int64_t R, int64_t J, float *out10);
+/* Host inference: out2 (host) = predicted (log t_EIG, log t_ALS); weights
+ * (host) NULL = the built-in weights. */
+sth_status sth_selector_predict(const float *weights, int64_t I, int64_t R, int64_t J, float *out2);
+
+/* Device training kernels.  X: device, 10 x B features (column per sample);
+ * T: device, 2 x B targets; params: device packed floats; ws: device scratch
+ * of sth_mlp_workspace(B) bytes. */
+size_t sth_mlp_workspace(int64_t B);
+/* Y (device, 2 x B) = network(X). */
+sth_status sth_mlp_forward(const float *params, int64_t B, const float *X, float *Y, void *ws,
+                           size_t ws_bytes, sth_stream_t stream);
+/* grad (device, num_params floats; the normalization entries are zero) =
+ * gradient of L = 0.5/B sum (Y - T)^2; loss (device, 1 float, may be NULL)
+ * = L.  Sums over samples run in sample order (deterministic). */
+sth_status sth_mlp_loss_grad(const float *params, int64_t B, const float *X, const float *T,
+                             float *grad, float *loss, void *ws, size_t ws_bytes,
+                             sth_stream_t stream);
+/* One Adam step (Kingma & Ba, 2015) on the first count parameters, step >= 1;
+ * m and v (device, count floats) are the moment estimates, zero at step 1. */
+sth_status sth_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count,
+                        float lr, float beta1, float beta2, float eps, int32_t step,
+                        sth_stream_t stream);
+
 /* FP64 sum of squares of a device array of count elements (Eq. 1 squared):
  * out (device, 1 FP64). ws: 8 * 1024 bytes. */
 sth_status sth_sumsq(int32_t dtype, const void *x, int64_t count, double *out, void *ws,

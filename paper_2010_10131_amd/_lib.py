@@ -74,6 +74,19 @@ SIGNATURES = {
     "tucker_error_workspace": (_sz, [_i32, _i64p, _i64p, _i32]),
     "tucker_error": (ctypes.c_int, [_i32, _i64p, _i64p, _i32, _i32, _vp, _vp, _vpp, _vp, _vp, _sz, _vp]),
     "sth_sumsq": (ctypes.c_int, [_i32, _vp, _i64, _vp, _vp, _sz, _vp]),
+    "sthosvd_mode_step_workspace": (_sz, [_i32, _i64p, _i32, _i64, _i32, _i32, _i32, _i32, _i32]),
+    "sthosvd_mode_step": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _vp, _vp,
+                                         _vp, _vp, _vp, ctypes.c_uint64, _vp, _sz, _vp]),
+    "sth_selector_num_params": (_i32, []),
+    "sth_selector_num_trainable": (_i32, []),
+    "sth_selector_features": (ctypes.c_int, [_i64, _i64, _i64, ctypes.POINTER(ctypes.c_float)]),
+    "sth_selector_predict": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), _i64, _i64, _i64,
+                                            ctypes.POINTER(ctypes.c_float)]),
+    "sth_mlp_workspace": (_sz, [_i64]),
+    "sth_mlp_forward": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _sz, _vp]),
+    "sth_mlp_loss_grad": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "sth_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, _i32, _vp]),
 }
 
 _lib = None

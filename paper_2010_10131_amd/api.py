@@ -18,7 +18,8 @@ from ._lib import PREC, SOLVER, check, i32arr, i64arr, ptrarr
 
 __all__ = [
     "fortran_empty", "to_device", "to_numpy", "Plan", "sthosvd", "gram_mode_n", "ttt_mode_n",
-    "ttm_mode_n", "eig_leading", "tucker_reconstruct", "tucker_error", "sumsq",
+    "ttm_mode_n", "eig_leading", "tucker_reconstruct", "tucker_error", "sumsq", "mode_step",
+    "selector_features", "selector_predict", "mlp_forward", "mlp_loss_grad", "mlp_adam",
 ]
 
 
@@ -297,3 +298,98 @@ def sumsq(x: torch.Tensor) -> torch.Tensor:
                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                       _stream()))
     return out
+
+
+# ---------------------------------------------------------- one mode ----
+
+def mode_step(Y: torch.Tensor, n: int, R: int, solver="eig", gram_prec="fp32", ttm_prec="fp32",
+              als_iters: int = 5, als_init=None, seed: int = 0, out=None, workspace=None):
+    """One mode of Alg. 2 on Y: returns (Z, U, eigvals or None, workspace)."""
+    _need(Y, "Y")
+    L = _lib.load()
+    dims = i64arr(Y.shape)
+    sv = SOLVER[solver] if isinstance(solver, str) else int(solver)
+    dt = _dtype_code(Y)
+    gp, tp = _prec(gram_prec), _prec(ttm_prec)
+    if dt == _lib.STH_F64:
+        gp = tp = PREC["fp64"]
+    nb = L.sthosvd_mode_step_workspace(Y.dim(), dims, n, R, dt, gp, tp, sv, als_iters)
+    if nb == 0:
+        raise _lib.SthError(_lib.STH_ERR_INVALID, L.sth_last_error().decode())
+    oshape = list(Y.shape)
+    oshape[n] = R
+    Z = out if out is not None else fortran_empty(oshape, Y.dtype, Y.device)
+    U = fortran_empty((Y.shape[n], R), torch.float64, Y.device)
+    ev = torch.empty(R, dtype=torch.float64, device=Y.device) if sv == 0 else None
+    ws = workspace if workspace is not None and workspace.numel() >= nb else _ws(nb, Y.device)
+    ai = None
+    if als_init is not None:
+        ai = als_init if isinstance(als_init, torch.Tensor) else to_device(als_init, Y.device)
+    check(L.sthosvd_mode_step(Y.dim(), dims, n, R, dt, gp, tp, sv, als_iters,
+                              ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(Z.data_ptr()),
+                              ctypes.c_void_p(U.data_ptr()),
+                              ctypes.c_void_p(ev.data_ptr()) if ev is not None else None,
+                              ctypes.c_void_p(ai.data_ptr()) if ai is not None else None,
+                              ctypes.c_uint64(seed), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                              _stream()))
+    return Z, U, ev, ws
+
+
+# -------------------------------------------------- learned selector ----
+
+def selector_num_params() -> int:
+    return int(_lib.load().sth_selector_num_params())
+
+
+def selector_num_trainable() -> int:
+    return int(_lib.load().sth_selector_num_trainable())
+
+
+def selector_features(I: int, R: int, J: int) -> np.ndarray:
+    out = np.zeros(10, dtype=np.float32)
+    check(_lib.load().sth_selector_features(I, R, J, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def selector_predict(I: int, R: int, J: int, weights: Optional[np.ndarray] = None) -> np.ndarray:
+    out = np.zeros(2, dtype=np.float32)
+    wp = None
+    if weights is not None:
+        weights = np.ascontiguousarray(weights, dtype=np.float32)
+        wp = weights.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    check(_lib.load().sth_selector_predict(wp, I, R, J, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return out
+
+
+def mlp_forward(params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
+    """Y (2 x B) of the selector network on device features X (10 x B)."""
+    L = _lib.load()
+    B = X.shape[1]
+    Y = torch.empty((B, 2), dtype=torch.float32, device=X.device).t()
+    ws = _ws(L.sth_mlp_workspace(B), X.device)
+    check(L.sth_mlp_forward(ctypes.c_void_p(params.data_ptr()), B, ctypes.c_void_p(X.data_ptr()),
+                            ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                            _stream()))
+    return Y
+
+
+def mlp_loss_grad(params: torch.Tensor, X: torch.Tensor, T: torch.Tensor, workspace=None):
+    """(loss tensor [1], grad tensor [num_params]) of 0.5/B ||Y - T||^2."""
+    L = _lib.load()
+    B = X.shape[1]
+    grad = torch.empty_like(params)
+    loss = torch.empty(4, dtype=torch.float32, device=X.device)
+    nb = L.sth_mlp_workspace(B)
+    ws = workspace if workspace is not None and workspace.numel() >= nb else _ws(nb, X.device)
+    check(L.sth_mlp_loss_grad(ctypes.c_void_p(params.data_ptr()), B, ctypes.c_void_p(X.data_ptr()),
+                              ctypes.c_void_p(T.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                              ctypes.c_void_p(loss.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream()))
+    return loss[:1], grad
+
+
+def mlp_adam(params, grad, m, v, count: int, lr: float, step: int, beta1=0.9, beta2=0.999,
+             eps=1e-8) -> None:
+    check(_lib.load().sth_mlp_adam(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                                   ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), count,
+                                   lr, beta1, beta2, eps, step, _stream()))

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -144,7 +145,13 @@ static int gram_prec_of(const sth_plan_s &p) { return p.dtype == STH_F64 ? STH_P
 // G2, R1, R1inv, R2, R2inv, Rhat (R x R each); L0 (I x R).
 static size_t als_small_doubles(int64_t I, int64_t R) { return (size_t)(5 * I * R + 9 * R * R); }
 
+static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_out, size_t *ws_out);
+
 extern "C" sth_status sthosvd_plan(const sth_desc *d, sth_plan **plan_out, size_t *ws_out) {
+    return make_plan(d, MAX_ORDER, plan_out, ws_out);
+}
+
+static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_out, size_t *ws_out) {
     if (!d || !plan_out || !ws_out) return fail(STH_ERR_INVALID, "NULL argument");
     *plan_out = nullptr;
     sth_status st = check_shape(d->order, d->dims);
@@ -187,7 +194,8 @@ extern "C" sth_status sthosvd_plan(const sth_desc *d, sth_plan **plan_out, size_
     // shapes on the current working tensor, solver choice (Alg. 2 line 3)
     std::vector<int64_t> cur = p->dims;
     size_t maxA = 0, maxB = 0, maxZ = 0, maxPart = 0, maxS = 0, maxEig = 0, maxUq = 0, maxSmall = 0, maxGemm = 0;
-    for (int s = 0; s < N; ++s) {
+    const int nsteps = std::min(N, max_steps);
+    for (int s = 0; s < nsteps; ++s) {
         Step stp;
         stp.n = order[s];
         lim(N, cur.data(), stp.n, stp.L, stp.I, stp.M);
@@ -214,7 +222,7 @@ extern "C" sth_status sthosvd_plan(const sth_desc *d, sth_plan **plan_out, size_
         stp.solver = solver;
         p->solver_of_mode[stp.n] = solver;
         stp.src = (s == 0) ? 0 : ((s - 1) % 2 == 0 ? 1 : 2);
-        stp.dst = (s == N - 1) ? 3 : (s % 2 == 0 ? 1 : 2);
+        stp.dst = (s == nsteps - 1) ? 3 : (s % 2 == 0 ? 1 : 2);
         const size_t out_elems = (size_t)(stp.L * stp.R * stp.M);
         if (stp.dst == 1) maxA = std::max(maxA, out_elems);
         if (stp.dst == 2) maxB = std::max(maxB, out_elems);
@@ -315,6 +323,58 @@ hipError_t cholqr2(const double *A, int I, int R, double *Q, double *Rfac, AlsBu
 
 }  // namespace
 
+// One mode of Alg. 2 on the working tensor src (L, I, M) -> dst (L, R, M).
+static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *src, void *dst,
+                            double *Un, double *lam, const double *L0in, uint64_t seed, char *w,
+                            hipStream_t s) {
+    const sth_plan_s *p = &pl;
+    int64_t *flag = (int64_t *)(w + p->o_flag);
+    void *bufZ = w + p->o_bufZ;
+    double *part = (double *)(w + p->o_part);
+    double *S = (double *)(w + p->o_S);
+    void *eigws = w + p->o_eig;
+    void *uq = w + p->o_uq;
+    void *gws = w + p->o_gemm;
+    const int gp = gram_prec_of(*p), tp = ttm_prec_of(*p);
+    const int n = stp.n;
+    if (stp.solver == STH_SOLVER_EIG) {
+        // Alg. 2 lines 6-8
+        HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
+        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s), "eig");
+        HIPCHK(ttm_prep_u(Un, stp.I, stp.R, 0, tp, uq, s), "ttm prep");
+        HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
+        return STH_OK;
+    }
+    // Alg. 2 lines 10-13 with Alg. 3 (L_k re-orthonormalized before each sweep)
+    const int I = (int)stp.I, R = (int)stp.R;
+    AlsBufs b = als_bufs((double *)(w + p->o_small), I, R);
+    const double *L0 = L0in;
+    if (!L0) {
+        HIPCHK(gaussian_f64(b.L0, (int64_t)I * R, seed, (uint64_t)n, s), "als init");
+        L0 = b.L0;
+    }
+    HIPCHK(cholqr2(L0, I, R, b.Q, nullptr, b, gws, flag, s), "als qr0");
+    for (int k = 0; k < p->als_iters; ++k) {
+        // Z = Y x_n Q^T  (R_k as a tensor)
+        HIPCHK(ttm_prep_u(b.Q, I, R, 0, tp, uq, s), "als prep");
+        HIPCHK(ttm_launch(p->dtype, tp, src, uq, bufZ, stp.L, I, R, stp.M, s), "als ttm");
+        // P = Y_(n) Z_(n)^T  (TTT)
+        HIPCHK(gram_launch(p->dtype, gp, src, bufZ, stp.L, I, R, stp.M, false, part, b.P, s), "als ttt");
+        // C = R_k^T R_k = Q^T P ;  L_{k+1} = P C^{-1}
+        HIPCHK(gemm_f64(1, 0, R, R, I, 1.0, b.Q, I, b.P, I, 0.0, b.C, R, gws, s), "als C");
+        HIPCHK(chol_launch(b.C, R, R, 0.0, b.Rc, b.Rcinv, flag, s), "als chol");
+        HIPCHK(gemm_f64(0, 0, I, R, R, 1.0, b.P, I, b.Rcinv, R, 0.0, b.T1, I, gws, s), "als L1");
+        HIPCHK(gemm_f64(0, 1, I, R, R, 1.0, b.T1, I, b.Rcinv, R, 0.0, b.Lk, I, gws, s), "als L2");
+        const bool last = (k + 1 == p->als_iters);
+        // next basis, or the final Q^ R^ = L
+        HIPCHK(cholqr2(b.Lk, I, R, last ? Un : b.Q, last ? b.Rhat : nullptr, b, gws, flag, s), "als qr");
+    }
+    // core update: Y' = R x_n R^  (Z'(a, r, b) = sum_s R^(r, s) Z(a, s, b))
+    HIPCHK(ttm_prep_u(b.Rhat, R, R, 1, tp, uq, s), "als core prep");
+    HIPCHK(ttm_launch(p->dtype, tp, bufZ, uq, dst, stp.L, R, R, stp.M, s), "als core ttm");
+    return STH_OK;
+}
+
 // ---------------------------------------------------------------- run ----
 
 extern "C" sth_status sthosvd_run(const sth_plan *p, const void *X, void *core, double *const *U,
@@ -336,55 +396,15 @@ extern "C" sth_status sthosvd_run(const sth_plan *p, const void *X, void *core, 
     char *w = (char *)ws;
     int64_t *flag = (int64_t *)(w + p->o_flag);
     char *bufA = w + p->o_bufA, *bufB = w + p->o_bufB;
-    void *bufZ = w + p->o_bufZ;
-    double *part = (double *)(w + p->o_part);
-    double *S = (double *)(w + p->o_S);
-    void *eigws = w + p->o_eig;
-    void *uq = w + p->o_uq;
-    void *gws = w + p->o_gemm;
-    const int gp = gram_prec_of(*p), tp = ttm_prec_of(*p);
     HIPCHK(zero_words(flag, 2, s), "flag clear");
 
     for (const Step &stp : p->steps) {
         const void *src = stp.src == 0 ? X : (stp.src == 1 ? (const void *)bufA : (const void *)bufB);
         void *dst = stp.dst == 3 ? core : (stp.dst == 1 ? (void *)bufA : (void *)bufB);
         const int n = stp.n;
-        if (stp.solver == STH_SOLVER_EIG) {
-            // Alg. 2 lines 6-8
-            HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
-            double *lam = eigvals ? eigvals[n] : nullptr;
-            HIPCHK(eig_launch(stp.I, stp.R, S, U[n], lam, 1e-15, p->max_sweeps, eigws, flag, s), "eig");
-            HIPCHK(ttm_prep_u(U[n], stp.I, stp.R, 0, tp, uq, s), "ttm prep");
-            HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
-        } else {
-            // Alg. 2 lines 10-13 with Alg. 3 (L_k re-orthonormalized before each sweep)
-            const int I = (int)stp.I, R = (int)stp.R;
-            AlsBufs b = als_bufs((double *)(w + p->o_small), I, R);
-            const double *L0 = als_init ? als_init[n] : nullptr;
-            if (!L0) {
-                HIPCHK(gaussian_f64(b.L0, (int64_t)I * R, seed, (uint64_t)n, s), "als init");
-                L0 = b.L0;
-            }
-            HIPCHK(cholqr2(L0, I, R, b.Q, nullptr, b, gws, flag, s), "als qr0");
-            for (int k = 0; k < p->als_iters; ++k) {
-                // Z = Y x_n Q^T  (R_k as a tensor)
-                HIPCHK(ttm_prep_u(b.Q, I, R, 0, tp, uq, s), "als prep");
-                HIPCHK(ttm_launch(p->dtype, tp, src, uq, bufZ, stp.L, I, R, stp.M, s), "als ttm");
-                // P = Y_(n) Z_(n)^T  (TTT)
-                HIPCHK(gram_launch(p->dtype, gp, src, bufZ, stp.L, I, R, stp.M, false, part, b.P, s), "als ttt");
-                // C = R_k^T R_k = Q^T P ;  L_{k+1} = P C^{-1}
-                HIPCHK(gemm_f64(1, 0, R, R, I, 1.0, b.Q, I, b.P, I, 0.0, b.C, R, gws, s), "als C");
-                HIPCHK(chol_launch(b.C, R, R, 0.0, b.Rc, b.Rcinv, flag, s), "als chol");
-                HIPCHK(gemm_f64(0, 0, I, R, R, 1.0, b.P, I, b.Rcinv, R, 0.0, b.T1, I, gws, s), "als L1");
-                HIPCHK(gemm_f64(0, 1, I, R, R, 1.0, b.T1, I, b.Rcinv, R, 0.0, b.Lk, I, gws, s), "als L2");
-                const bool last = (k + 1 == p->als_iters);
-                // next basis, or the final Q^ R^ = L
-                HIPCHK(cholqr2(b.Lk, I, R, last ? U[n] : b.Q, last ? b.Rhat : nullptr, b, gws, flag, s), "als qr");
-            }
-            // core update: Y' = R x_n R^  (Z'(a, r, b) = sum_s R^(r, s) Z(a, s, b))
-            HIPCHK(ttm_prep_u(b.Rhat, R, R, 1, tp, uq, s), "als core prep");
-            HIPCHK(ttm_launch(p->dtype, tp, bufZ, uq, dst, stp.L, R, R, stp.M, s), "als core ttm");
-        }
+        sth_status st2 = exec_step(*p, stp, src, dst, U[n], eigvals ? eigvals[n] : nullptr,
+                                   als_init ? als_init[n] : nullptr, seed, w, s);
+        if (st2) return st2;
     }
     return STH_OK;
 }
@@ -582,5 +602,124 @@ extern "C" sth_status sth_sumsq(int32_t dtype, const void *x, int64_t count, dou
     if ((st = check_ptr(x, "x")) || (st = check_ptr(out, "out")) || (st = check_ptr(ws, "ws"))) return st;
     if (ws_bytes < SUMSQ_BLOCKS * sizeof(double)) return fail(STH_ERR_NOMEM, "workspace too small");
     HIPCHK(sumsq_launch(dtype, x, nullptr, count, out, (double *)ws, nullptr, (hipStream_t)stream), "sumsq");
+    return STH_OK;
+}
+
+// ------------------------------------------------------------ one mode ----
+
+static sth_status mode_step_plan(int32_t order, const int64_t *dims, int32_t n, int64_t R, int32_t dtype,
+                                 int32_t gram_prec, int32_t ttm_prec, int32_t solver, int32_t als_iters,
+                                 sth_plan **pl, size_t *bytes) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (n < 0 || n >= order) return fail(STH_ERR_INVALID, "mode %d outside 0..%d", n, order - 1);
+    if (solver != STH_SOLVER_EIG && solver != STH_SOLVER_ALS) return fail(STH_ERR_INVALID, "solver %d", solver);
+    std::vector<int64_t> ranks(dims, dims + order);
+    ranks[n] = R;
+    std::vector<int32_t> mo;
+    mo.push_back(n);
+    for (int k = 0; k < order; ++k)
+        if (k != n) mo.push_back(k);
+    sth_desc d;
+    memset(&d, 0, sizeof(d));
+    d.order = order;
+    d.dims = dims;
+    d.ranks = ranks.data();
+    d.mode_order = mo.data();
+    d.dtype = dtype;
+    d.gram_prec = gram_prec;
+    d.ttm_prec = ttm_prec;
+    d.solver = solver;
+    d.als_iters = als_iters;
+    return make_plan(&d, 1, pl, bytes);
+}
+
+extern "C" size_t sthosvd_mode_step_workspace(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                                              int32_t dtype, int32_t gram_prec, int32_t ttm_prec,
+                                              int32_t solver, int32_t als_iters) {
+    sth_plan *pl = nullptr;
+    size_t b = 0;
+    if (mode_step_plan(order, dims, n, R, dtype, gram_prec, ttm_prec, solver, als_iters, &pl, &b)) return 0;
+    delete pl;
+    return b;
+}
+
+extern "C" sth_status sthosvd_mode_step(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                                        int32_t dtype, int32_t gram_prec, int32_t ttm_prec,
+                                        int32_t solver, int32_t als_iters, const void *Y, void *Z,
+                                        double *U, double *eigvals, const double *als_init,
+                                        uint64_t seed, void *ws, size_t ws_bytes, sth_stream_t stream) {
+    sth_plan *pl = nullptr;
+    size_t need = 0;
+    sth_status st = mode_step_plan(order, dims, n, R, dtype, gram_prec, ttm_prec, solver, als_iters, &pl, &need);
+    if (st) return st;
+    std::unique_ptr<sth_plan> hold(pl);
+    if ((st = check_ptr(Y, "Y")) || (st = check_ptr(Z, "Z")) || (st = check_ptr(U, "U")) ||
+        (st = check_ptr(ws, "ws")) || (st = check_ptr(eigvals, "eigvals", true)) ||
+        (st = check_ptr(als_init, "als_init", true)))
+        return st;
+    if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    HIPCHK(zero_words(w + pl->o_flag, 2, s), "flag clear");
+    return exec_step(*pl, pl->steps[0], Y, Z, U, eigvals, als_init, seed, w, s);
+}
+
+// ----------------------------------------------------- learned selector ----
+
+extern "C" int32_t sth_selector_num_params(void) { return SEL_NPARAM; }
+extern "C" int32_t sth_selector_num_trainable(void) { return mlp_num_trainable(); }
+
+extern "C" sth_status sth_selector_features(int64_t I, int64_t R, int64_t J, float *out10) {
+    if (I < 1 || R < 1 || J < 1 || !out10) return fail(STH_ERR_INVALID, "bad selector features input");
+    selector_features(I, R, J, out10);
+    return STH_OK;
+}
+
+extern "C" sth_status sth_selector_predict(const float *weights, int64_t I, int64_t R, int64_t J,
+                                           float *out2) {
+    if (I < 1 || R < 1 || J < 1 || !out2) return fail(STH_ERR_INVALID, "bad selector input");
+    float f[SEL_IN];
+    selector_features(I, R, J, f);
+    selector_predict(weights, f, out2);
+    return STH_OK;
+}
+
+extern "C" size_t sth_mlp_workspace(int64_t B) { return B > 0 ? align_up(mlp_ws_bytes(B)) : 0; }
+
+extern "C" sth_status sth_mlp_forward(const float *params, int64_t B, const float *X, float *Y, void *ws,
+                                      size_t ws_bytes, sth_stream_t stream) {
+    sth_status st;
+    if (B < 1) return fail(STH_ERR_INVALID, "B < 1");
+    if ((st = check_ptr(params, "params")) || (st = check_ptr(X, "X")) || (st = check_ptr(Y, "Y")) ||
+        (st = check_ptr(ws, "ws")))
+        return st;
+    if (ws_bytes < mlp_ws_bytes(B)) return fail(STH_ERR_NOMEM, "workspace too small");
+    HIPCHK(mlp_forward_launch(params, B, X, Y, ws, (hipStream_t)stream), "mlp forward");
+    return STH_OK;
+}
+
+extern "C" sth_status sth_mlp_loss_grad(const float *params, int64_t B, const float *X, const float *T,
+                                        float *grad, float *loss, void *ws, size_t ws_bytes,
+                                        sth_stream_t stream) {
+    sth_status st;
+    if (B < 1) return fail(STH_ERR_INVALID, "B < 1");
+    if ((st = check_ptr(params, "params")) || (st = check_ptr(X, "X")) || (st = check_ptr(T, "T")) ||
+        (st = check_ptr(grad, "grad")) || (st = check_ptr(loss, "loss", true)) || (st = check_ptr(ws, "ws")))
+        return st;
+    if (ws_bytes < mlp_ws_bytes(B)) return fail(STH_ERR_NOMEM, "workspace too small");
+    HIPCHK(mlp_loss_grad_launch(params, B, X, T, grad, loss, ws, (hipStream_t)stream), "mlp grad");
+    return STH_OK;
+}
+
+extern "C" sth_status sth_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t count,
+                                   float lr, float beta1, float beta2, float eps, int32_t step,
+                                   sth_stream_t stream) {
+    sth_status st;
+    if (count < 1 || step < 1) return fail(STH_ERR_INVALID, "count < 1 or step < 1");
+    if ((st = check_ptr(params, "params")) || (st = check_ptr(grad, "grad")) || (st = check_ptr(m, "m")) ||
+        (st = check_ptr(v, "v")))
+        return st;
+    HIPCHK(adam_launch(params, grad, m, v, count, lr, beta1, beta2, eps, step, (hipStream_t)stream), "adam");
     return STH_OK;
 }

@@ -49,4 +49,13 @@ hipError_t copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t zero_words(void *p, int64_t nwords, hipStream_t s);
 hipError_t gaussian_f64(double *p, int64_t n, uint64_t seed, uint64_t stream, hipStream_t s);
 
+// Learned selector MLP (mlp.hip)
+size_t mlp_ws_bytes(int64_t B);
+hipError_t mlp_forward_launch(const float *w, int64_t B, const float *X, float *Y, void *ws, hipStream_t s);
+hipError_t mlp_loss_grad_launch(const float *w, int64_t B, const float *X, const float *T, float *grad,
+                                float *loss, void *ws, hipStream_t s);
+hipError_t adam_launch(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+int mlp_num_trainable();
+
 }  // namespace sth
