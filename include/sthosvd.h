@@ -97,6 +97,7 @@ typedef struct {
 } sth_desc;
 
 typedef struct sth_plan_s sth_plan;
+typedef struct sth_batch_plan_s sth_batch_plan;
 
 /* Thread-local text of the last error (never NULL). */
 const char *sth_last_error(void);
@@ -140,6 +141,27 @@ sth_status sthosvd_run(const sth_plan *plan, const void *X, void *core, double *
 /* Synchronizes the stream and reports numerical failures recorded in the
  * workspace by the last run on it (STH_ERR_NUMERIC), then clears them. */
 sth_status sthosvd_check(const sth_plan *plan, void *workspace, sth_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched decomposition: count independent FP32 tensors of one order, EIG
+ * branch in mode order 1..N, every R_n <= 64 (spec batching pattern;
+ * each tensor follows Alg. 2 exactly as a single run would).  One launch per
+ * phase of a mode step covers the whole batch; the run is enqueue-only and
+ * may be captured in a HIP graph.  The plan owns pinned host memory holding
+ * the shape/offset tables (copied into the workspace by every run).
+ * ------------------------------------------------------------------------- */
+sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count, sth_batch_plan **plan,
+                                size_t *workspace_bytes);
+void sthosvd_plan_batched_destroy(sth_batch_plan *plan);
+/* X_dev: device array of count device pointers to the inputs; core_dev:
+ * device array of count device pointers to the cores; U_dev: device array of
+ * count * N device pointers, U_dev[t * N + n] receives tensor t's I_n x R_n
+ * FP64 factor.  workspace: device, >= workspace_bytes of the plan. */
+sth_status sthosvd_run_batched(const sth_batch_plan *plan, const void *const *X_dev,
+                               void *const *core_dev, double *const *U_dev, void *workspace,
+                               size_t workspace_bytes, sth_stream_t stream);
+/* Synchronizes and reports device-side numerical flags of the last batched run. */
+sth_status sthosvd_check_batched(const sth_batch_plan *plan, void *workspace, sth_stream_t stream);
 
 /* ---------------------------------------------------------------------------
  * Building blocks.  All act on one tensor Y with order/dims as above and

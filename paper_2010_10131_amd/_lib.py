@@ -77,6 +77,11 @@ SIGNATURES = {
     "sthosvd_mode_step_workspace": (_sz, [_i32, _i64p, _i32, _i64, _i32, _i32, _i32, _i32, _i32]),
     "sthosvd_mode_step": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _vp, _vp,
                                          _vp, _vp, _vp, ctypes.c_uint64, _vp, _sz, _vp]),
+    "sthosvd_plan_batched": (ctypes.c_int, [ctypes.POINTER(sth_desc), _i32, ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_sz)]),
+    "sthosvd_plan_batched_destroy": (None, [_vp]),
+    "sthosvd_run_batched": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "sthosvd_check_batched": (ctypes.c_int, [_vp, _vp, _vp]),
     "sth_selector_num_params": (_i32, []),
     "sth_selector_num_trainable": (_i32, []),
     "sth_selector_features": (ctypes.c_int, [_i64, _i64, _i64, ctypes.POINTER(ctypes.c_float)]),

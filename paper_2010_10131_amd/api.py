@@ -20,6 +20,7 @@ __all__ = [
     "fortran_empty", "to_device", "to_numpy", "Plan", "sthosvd", "gram_mode_n", "ttt_mode_n",
     "ttm_mode_n", "eig_leading", "tucker_reconstruct", "tucker_error", "sumsq", "mode_step",
     "selector_features", "selector_predict", "mlp_forward", "mlp_loss_grad", "mlp_adam",
+    "BatchPlan",
 ]
 
 
@@ -393,3 +394,63 @@ def mlp_adam(params, grad, m, v, count: int, lr: float, step: int, beta1=0.9, be
     check(_lib.load().sth_mlp_adam(ctypes.c_void_p(params.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
                                    ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), count,
                                    lr, beta1, beta2, eps, step, _stream()))
+
+
+# ----------------------------------------------------------- batched ----
+
+class BatchPlan:
+    """sthosvd_plan_batched over a list of (dims, ranks) of FP32 tensors."""
+
+    def __init__(self, shapes, gram_prec="bf16x6", ttm_prec="bf16x3", eig_max_sweeps: int = 0):
+        L = _lib.load()
+        self.shapes = [([int(x) for x in d], [int(x) for x in r]) for d, r in shapes]
+        self.count = len(self.shapes)
+        self.N = len(self.shapes[0][0])
+        self._keep = []
+        descs = (_lib.sth_desc * self.count)()
+        for t, (d, r) in enumerate(self.shapes):
+            da, ra = i64arr(d), i64arr(r)
+            self._keep += [da, ra]
+            descs[t].order = len(d)
+            descs[t].dims = ctypes.cast(da, ctypes.POINTER(ctypes.c_int64))
+            descs[t].ranks = ctypes.cast(ra, ctypes.POINTER(ctypes.c_int64))
+            descs[t].dtype = _lib.STH_F32
+            descs[t].gram_prec = _prec(gram_prec)
+            descs[t].ttm_prec = _prec(ttm_prec)
+            descs[t].solver = SOLVER["eig"]
+            descs[t].eig_max_sweeps = int(eig_max_sweeps)
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        check(L.sthosvd_plan_batched(descs, self.count, ctypes.byref(h), ctypes.byref(ws)))
+        self._h = h
+        self.workspace_bytes = int(ws.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.load().sthosvd_plan_batched_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+    def outputs(self, device="cuda"):
+        """Allocates (cores, factors, pointer arrays) for a run."""
+        G = [fortran_empty(r, torch.float32, device) for _, r in self.shapes]
+        U = [[fortran_empty((d[n], r[n]), torch.float64, device) for n in range(self.N)]
+             for d, r in self.shapes]
+        cp = torch.tensor([g.data_ptr() for g in G], dtype=torch.int64, device=device)
+        up = torch.tensor([u.data_ptr() for us in U for u in us], dtype=torch.int64, device=device)
+        return G, U, cp, up
+
+    def run(self, Xptrs: torch.Tensor, Cptrs: torch.Tensor, Uptrs: torch.Tensor,
+            workspace: torch.Tensor) -> None:
+        check(_lib.load().sthosvd_run_batched(self._h, ctypes.c_void_p(Xptrs.data_ptr()),
+                                              ctypes.c_void_p(Cptrs.data_ptr()),
+                                              ctypes.c_void_p(Uptrs.data_ptr()),
+                                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                              _stream()))
+
+    def check(self, workspace: torch.Tensor) -> None:
+        check(_lib.load().sthosvd_check_batched(self._h, ctypes.c_void_p(workspace.data_ptr()),
+                                                _stream()))

@@ -68,6 +68,13 @@ int device_cu_count() {
 
 static const int MAX_ORDER = 8;
 static const int64_t MAX_EIG_N = 512;   // Jacobi kernel limit (one workgroup)
+static const int64_t EIG_DIRECT_MAX_HOST = 128;
+static const int64_t SI_BLOCK_MAX_HOST = 96;
+static int64_t si_block_host_api(int64_t n, int64_t R) {
+    int64_t p = std::max<int64_t>(R + 16, (3 * R + 1) / 2);
+    p = (p + 7) / 8 * 8;
+    return std::min(p, n);
+}
 static const int64_t MAX_ALS_R = 128;   // R x R Cholesky in LDS
 
 static size_t esize(int dtype) { return dtype == STH_F64 ? 8 : 4; }
@@ -721,5 +728,251 @@ extern "C" sth_status sth_mlp_adam(float *params, const float *grad, float *m, f
         (st = check_ptr(v, "v")))
         return st;
     HIPCHK(adam_launch(params, grad, m, v, count, lr, beta1, beta2, eps, step, (hipStream_t)stream), "adam");
+    return STH_OK;
+}
+
+// ------------------------------------------------------------- batched ----
+
+struct BatchLaunchT {
+    size_t list_off, pref_off;
+    int len;
+    int64_t total;
+    int cls;
+};
+struct BatchStepT {
+    size_t descs_off;
+    std::vector<BatchLaunchT> gram, reduce, ttm;
+    BatchLaunchT prep;
+    size_t eig_lds;
+    int max_nchunks;
+};
+struct sth_batch_plan_s {
+    int count = 0, N = 0, dtype = 0, gram_prec = 0, ttm_prec = 0, max_sweeps = 60;
+    std::vector<BatchStepT> steps;
+    std::vector<char> blob;                // every table, host copy
+    mutable void *pinned = nullptr;        // pinned copy, allocated by the first run
+    mutable std::mutex mu;
+    size_t table_bytes = 0, tables_off = 0, flag_off = 0, total = 0;
+    ~sth_batch_plan_s() {
+        if (pinned) (void)hipHostFree(pinned);
+    }
+};
+
+extern "C" sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count, sth_batch_plan **out,
+                                           size_t *ws_out) {
+    if (!descs || !out || !ws_out || count < 1) return fail(STH_ERR_INVALID, "bad batched arguments");
+    *out = nullptr;
+    const sth_desc &d0 = descs[0];
+    sth_status st;
+    for (int t = 0; t < count; ++t) {
+        const sth_desc &d = descs[t];
+        if ((st = check_shape(d.order, d.dims))) return st;
+        if (!d.ranks) return fail(STH_ERR_INVALID, "ranks[%d] is NULL", t);
+        if (d.order != d0.order || d.dtype != d0.dtype || d.gram_prec != d0.gram_prec ||
+            d.ttm_prec != d0.ttm_prec)
+            return fail(STH_ERR_INVALID, "batched tensors must share order, dtype and precisions");
+        if (d.mode_order || d.per_mode || d.solver != STH_SOLVER_EIG)
+            return fail(STH_ERR_UNSUPPORTED, "the batched path runs the EIG branch in mode order 1..N");
+        for (int k = 0; k < d.order; ++k)
+            if (d.ranks[k] < 1 || d.ranks[k] > d.dims[k])
+                return fail(STH_ERR_INVALID, "tensor %d: ranks[%d] out of range", t, k);
+    }
+    if (d0.dtype != STH_F32) return fail(STH_ERR_UNSUPPORTED, "the batched path takes FP32 tensors");
+    if ((st = check_dtype_prec(d0.dtype, d0.gram_prec, "gram_prec"))) return st;
+    if ((st = check_dtype_prec(d0.dtype, d0.ttm_prec, "ttm_prec"))) return st;
+    const int N = d0.order;
+    std::unique_ptr<sth_batch_plan_s> p(new sth_batch_plan_s());
+    p->count = count;
+    p->N = N;
+    p->dtype = d0.dtype;
+    p->gram_prec = d0.gram_prec;
+    p->ttm_prec = d0.ttm_prec;
+    p->max_sweeps = d0.eig_max_sweeps ? d0.eig_max_sweeps : 60;
+    const int64_t target = std::max<int64_t>(1, 4 * (int64_t)device_cu_count() / count);
+
+    // per tensor regions and per step descriptors
+    Arena a;
+    p->flag_off = a.take(256);
+    std::vector<std::vector<BatchStep>> sd(N, std::vector<BatchStep>(count));
+    for (int t = 0; t < count; ++t) {
+        const sth_desc &d = descs[t];
+        std::vector<int64_t> cur(d.dims, d.dims + N);
+        size_t maxA = 0, maxB = 0, maxPart = 0, maxS = 0, maxUq = 0, maxEig = 0;
+        for (int s = 0; s < N; ++s) {
+            BatchStep &b = sd[s][t];
+            memset(&b, 0, sizeof(b));
+            lim(N, cur.data(), s, b.L, b.I, b.M);
+            b.R = d.ranks[s];
+            b.tensor = t;
+            const int64_t P = b.L * b.M;
+            const size_t out = (size_t)(b.L * b.R * b.M);
+            if (s < N - 1) (s % 2 == 0 ? maxA : maxB) = std::max(s % 2 == 0 ? maxA : maxB, out);
+            int wt, nbi, nbj, nblocks, nkc;
+            int64_t kper;
+            gram_geometry(b.I, b.I, P, true, target, &wt, &nbi, &nbj, &nblocks, &nkc, &kper);
+            b.wt = wt;
+            b.nbi = nbi;
+            b.nblocks = nblocks;
+            b.nkc = nkc;
+            b.kper = kper;
+            b.gram_wg = (int64_t)nkc * nblocks;
+            maxPart = std::max(maxPart, (size_t)nkc * nblocks * (32 * wt) * (32 * wt) * 8);
+            maxS = std::max(maxS, (size_t)(b.I * b.I) * 8);
+            maxUq = std::max(maxUq, ttm_prep_bytes(b.I, b.R, d0.ttm_prec));
+            if (b.I > EIG_DIRECT_MAX_HOST && si_block_host_api(b.I, b.R) > SI_BLOCK_MAX_HOST)
+                return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n = %lld too large for the batched eigensolver", t, s, (long long)b.R);
+            if (b.R > 64) return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n > 64 in the batched path", t, s);
+            maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.R));
+            b.nchunks = (int)((b.I + 31) / 32);
+            b.ntiles = (int)((b.R + 15) / 16);
+            b.rtb = b.ntiles <= 1 ? 1 : (b.ntiles <= 2 ? 2 : 4);
+            b.contig = (b.L == 1 && b.I % 4 == 0) ? 1 : 0;
+            cur[s] = b.R;
+        }
+        const size_t oA = a.take(maxA * 4), oB = a.take(maxB * 4), oPart = a.take(maxPart), oS = a.take(maxS),
+                     oUq = a.take(maxUq), oEig = a.take(maxEig);
+        for (int s = 0; s < N; ++s) {
+            BatchStep &b = sd[s][t];
+            b.src_off = (s == 0) ? -1 : (int64_t)((s - 1) % 2 == 0 ? oA : oB);
+            b.dst_off = (s == N - 1) ? -1 : (int64_t)(s % 2 == 0 ? oA : oB);
+            b.part_off = (int64_t)oPart;
+            b.S_off = (int64_t)oS;
+            b.uq_off = (int64_t)oUq;
+            b.eig_off = (int64_t)oEig;
+        }
+    }
+    // tables: per step descriptors, then launch lists and prefix sums
+    std::vector<char> blob;
+    auto put = [&](const void *src, size_t bytes) {
+        size_t off = (blob.size() + 15) & ~(size_t)15;
+        blob.resize(off + bytes);
+        memcpy(blob.data() + off, src, bytes);
+        return off;
+    };
+    for (int s = 0; s < N; ++s) {
+        BatchStepT T;
+        T.descs_off = put(sd[s].data(), sizeof(BatchStep) * count);
+        T.eig_lds = 0;
+        T.max_nchunks = 0;
+        for (int t = 0; t < count; ++t) {
+            T.eig_lds = std::max(T.eig_lds, batch_eig_lds(sd[s][t].I, sd[s][t].R));
+            T.max_nchunks = std::max(T.max_nchunks, sd[s][t].nchunks);
+        }
+        auto make = [&](const std::vector<int32_t> &list, const std::vector<int64_t> &units, int cls) {
+            BatchLaunchT L;
+            std::vector<int64_t> pref(list.size() + 1, 0);
+            for (size_t k = 0; k < list.size(); ++k) pref[k + 1] = pref[k] + units[k];
+            L.list_off = put(list.data(), sizeof(int32_t) * std::max<size_t>(1, list.size()));
+            L.pref_off = put(pref.data(), sizeof(int64_t) * pref.size());
+            L.len = (int)list.size();
+            L.total = pref.back();
+            L.cls = cls;
+            return L;
+        };
+        for (int cls : {1, 2, 4}) {
+            std::vector<int32_t> gl;
+            std::vector<int64_t> gw, gb;
+            for (int t = 0; t < count; ++t)
+                if (sd[s][t].wt == cls) {
+                    gl.push_back(t);
+                    gw.push_back(sd[s][t].gram_wg);
+                    gb.push_back(sd[s][t].nblocks);
+                }
+            if (!gl.empty()) {
+                T.gram.push_back(make(gl, gw, cls));
+                T.reduce.push_back(make(gl, gb, cls));
+            }
+            std::vector<int32_t> tl;
+            std::vector<int64_t> tw;
+            for (int t = 0; t < count; ++t)
+                if (sd[s][t].rtb == cls) {
+                    const BatchStep &b = sd[s][t];
+                    const int nt = (cls == 1) ? 4 : 2;
+                    const int64_t rows = (b.L * b.M + 16 * nt - 1) / (16 * nt);
+                    tl.push_back(t);
+                    tw.push_back(std::max<int64_t>(1, (rows + BT_WAVES * 4 - 1) / (BT_WAVES * 4)));
+                }
+            if (!tl.empty()) T.ttm.push_back(make(tl, tw, cls));
+        }
+        std::vector<int32_t> all(count);
+        std::vector<int64_t> pw(count);
+        for (int t = 0; t < count; ++t) {
+            all[t] = t;
+            pw[t] = (int64_t)sd[s][t].nchunks * sd[s][t].ntiles * 64;
+        }
+        T.prep = make(all, pw, 0);
+        p->steps.push_back(T);
+    }
+    p->table_bytes = blob.size();
+    p->tables_off = a.take(p->table_bytes);
+    p->total = a.off;
+    p->blob = std::move(blob);
+    *ws_out = p->total;
+    *out = p.release();
+    return STH_OK;
+}
+
+extern "C" void sthosvd_plan_batched_destroy(sth_batch_plan *plan) { delete plan; }
+
+extern "C" sth_status sthosvd_run_batched(const sth_batch_plan *p, const void *const *X_dev,
+                                          void *const *core_dev, double *const *U_dev, void *ws,
+                                          size_t ws_bytes, sth_stream_t stream) {
+    if (!p) return fail(STH_ERR_INVALID, "plan is NULL");
+    sth_status st;
+    if ((st = check_ptr(X_dev, "X pointer array")) || (st = check_ptr(core_dev, "core pointer array")) ||
+        (st = check_ptr(U_dev, "U pointer array")) || (st = check_ptr(ws, "workspace")))
+        return st;
+    if (ws_bytes < p->total) return fail(STH_ERR_NOMEM, "workspace %zu < required %zu bytes", ws_bytes, p->total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    char *tab = w + p->tables_off;
+    int64_t *flag = (int64_t *)(w + p->flag_off);
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (!p->pinned) {
+            void *h = nullptr;
+            HIPCHK(hipHostMalloc(&h, p->table_bytes, hipHostMallocDefault), "pinned tables");
+            memcpy(h, p->blob.data(), p->table_bytes);
+            p->pinned = h;
+        }
+    }
+    HIPCHK(hipMemcpyAsync(tab, p->pinned, p->table_bytes, hipMemcpyHostToDevice, s), "tables");
+    HIPCHK(zero_words(flag, 2, s), "flag clear");
+    auto res = [&](const BatchLaunchT &L) {
+        BatchLaunch b;
+        b.list = (const int32_t *)(tab + L.list_off);
+        b.pref = (const int64_t *)(tab + L.pref_off);
+        b.len = L.len;
+        b.total = L.total;
+        b.cls = L.cls;
+        return b;
+    };
+    for (int s2 = 0; s2 < p->N; ++s2) {
+        const BatchStepT &T = p->steps[s2];
+        BatchStepPlan sp;
+        sp.count = p->count;
+        sp.eig_lds = T.eig_lds;
+        sp.max_nchunks = T.max_nchunks;
+        for (auto &L : T.gram) sp.gram.push_back(res(L));
+        for (auto &L : T.reduce) sp.reduce.push_back(res(L));
+        for (auto &L : T.ttm) sp.ttm.push_back(res(L));
+        sp.prep = res(T.prep);
+        BatchTables bt;
+        bt.descs = (const BatchStep *)(tab + T.descs_off);
+        HIPCHK(batch_step_launch(bt, sp, p->gram_prec, p->ttm_prec, p->N, s2, w, X_dev, core_dev, U_dev,
+                                 flag, p->max_sweeps, s),
+               "batched step");
+    }
+    return STH_OK;
+}
+
+extern "C" sth_status sthosvd_check_batched(const sth_batch_plan *p, void *ws, sth_stream_t stream) {
+    if (!p || !ws) return fail(STH_ERR_INVALID, "NULL argument");
+    int64_t flag = 0;
+    int64_t *dflag = (int64_t *)((char *)ws + p->flag_off);
+    HIPCHK(hipStreamSynchronize((hipStream_t)stream), "sync");
+    HIPCHK(hipMemcpy(&flag, dflag, sizeof(flag), hipMemcpyDeviceToHost), "flag read");
+    if (flag == 1) return fail(STH_ERR_NUMERIC, "eigensolver hit its sweep cap");
+    if (flag) return fail(STH_ERR_NUMERIC, "numeric flag %lld", (long long)flag);
     return STH_OK;
 }

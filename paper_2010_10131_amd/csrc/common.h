@@ -136,4 +136,21 @@ template <int PREC> union FragQ {
     uint4 q[Frag<PREC>::NQ];
 };
 
+// Counter-based standard normal sample: SplitMix64 (Steele, Lea & Flood,
+// OOPSLA 2014) on (seed, stream, element), two uniforms -> Box-Muller.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ double gaussian_value(uint64_t seed, uint64_t stream, uint64_t e) {
+    const uint64_t base = splitmix64(seed ^ splitmix64(stream + 0x5851F42D4C957F2Dull));
+    const uint64_t a = splitmix64(base + 2 * e);
+    const uint64_t b = splitmix64(base + 2 * e + 1);
+    const double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
+    const double u2 = (b >> 11) * (1.0 / 9007199254740992.0);           // [0, 1)
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
 }  // namespace sth

@@ -1,0 +1,234 @@
+// Device body of the FP64 cyclic Jacobi eigensolver (one workgroup) and the
+// eigensolver constants, shared by the single-matrix and batched kernels.
+#pragma once
+#include "common.h"
+
+namespace sth {
+
+constexpr int64_t EIG_DIRECT_MAX = 128;  // Jacobi on the whole matrix up to this order
+constexpr int64_t SI_BLOCK_MAX = 96;     // Rayleigh-Ritz block kept in LDS
+constexpr int SI_ITERS_DEV = 3;          // subspace iterations before Rayleigh-Ritz
+constexpr int EIG_LDS_AV = 150 * 1024;   // LDS bytes available for Jacobi's A and V
+
+// Subspace-iteration block size for n > EIG_DIRECT_MAX.
+__host__ __device__ inline int64_t si_block_dev(int64_t n, int64_t R) {
+    int64_t p = (R + 16 > (3 * R + 1) / 2) ? R + 16 : (3 * R + 1) / 2;
+    p = (p + 7) / 8 * 8;
+    return p < n ? p : n;
+}
+inline int64_t si_block_host(int64_t n, int64_t R) { return si_block_dev(n, R); }
+
+constexpr int EIG_THREADS = 512;
+constexpr int EIG_BATCH = 4;  // items per thread whose loads are issued before any store
+
+__device__ __forceinline__ int rr_player(int x, int r, int ne) {
+    // round-robin position x (0..ne-1) in round r (0..ne-2): player 0 fixed
+    if (x == 0) return 0;
+    int y = x - 1 + r;
+    if (y >= ne - 1) y -= ne - 1;
+    return y + 1;
+}
+
+template <bool ALDS, bool VLDS>
+__device__ __forceinline__ void jacobi_body(const double *__restrict__ S, int n, int R,
+                                            double *__restrict__ Ag, double *__restrict__ Vg,
+                                            double *__restrict__ U, double *__restrict__ lam,
+                                            double tol, int max_sweeps,
+                                            int64_t *__restrict__ flag) {
+    extern __shared__ double s_e[];
+    __shared__ double s_c[256], s_s[256];
+    __shared__ int s_p[256], s_q[256];
+    __shared__ double s_red[2][EIG_THREADS / 64];
+    __shared__ int s_sel[512];
+    __shared__ double s_sign[512];
+    __shared__ int s_stop;
+
+    double *A = ALDS ? s_e : Ag;
+    double *V = VLDS ? (ALDS ? s_e + n * n : s_e) : Vg;
+    const int tid = threadIdx.x;
+    const int nn = n * n;
+    for (int e = tid; e < nn; e += EIG_THREADS) {
+        const int i = e % n, j = e / n;
+        A[e] = 0.5 * (S[e] + S[j + n * i]);
+        V[e] = (i == j) ? 1.0 : 0.0;
+    }
+    const int ne = n + (n & 1);
+    const int m = ne / 2;
+    __syncthreads();
+
+    int sweep = 0;
+    bool converged = false;
+    double prev_off2 = -1.0;
+    for (;;) {
+        // convergence test: off(A)^2 <= tol^2 ||A||_F^2
+        double off = 0.0, fro = 0.0;
+        for (int j = 0; j < n; ++j)
+            for (int i = tid; i < n; i += EIG_THREADS) {
+                const double v = A[i + n * j];
+                fro += v * v;
+                if (i != j) off += v * v;
+            }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            fro += __shfl_xor(fro, o);
+        }
+        if ((tid & 63) == 0) {
+            s_red[0][tid >> 6] = off;
+            s_red[1][tid >> 6] = fro;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double o2 = 0.0, f2 = 0.0;
+            for (int w = 0; w < EIG_THREADS / 64; ++w) {
+                o2 += s_red[0][w];
+                f2 += s_red[1][w];
+            }
+            int stop = 0;
+            if (o2 <= tol * tol * f2 || o2 == 0.0) stop = 1;
+            // roundoff floor: off(A) already at the FP64 noise level of an
+            // n x n rotation sequence and no longer shrinking
+            else if (o2 <= (double)n * n * 1.2e-32 * f2 && prev_off2 >= 0.0 && o2 >= 0.25 * prev_off2) stop = 1;
+            else if (sweep >= max_sweeps) stop = 2;
+            s_stop = stop;
+            s_red[0][0] = o2;  // broadcast for the stagnation test
+        }
+        __syncthreads();
+        if (s_stop) {
+            converged = (s_stop == 1);
+            break;
+        }
+        prev_off2 = s_red[0][0];
+        for (int r = 0; r < ne - 1; ++r) {
+            // rotations of this round
+            for (int k = tid; k < m; k += EIG_THREADS) {
+                int p = rr_player(k, r, ne), q = rr_player(ne - 1 - k, r, ne);
+                if (p > q) {
+                    int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, s = 0.0;
+                if (q < n) {
+                    double apq = A[p + n * q];
+                    if (apq != 0.0) {
+                        double app = A[p + n * p], aqq = A[q + n * q];
+                        double theta = (aqq - app) / (2.0 * apq);
+                        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                }
+                s_p[k] = p;
+                s_q[k] = q;
+                s_c[k] = c;
+                s_s[k] = s;
+            }
+            __syncthreads();
+            // A <- J^T A J, block (I, J) of pairs; V <- V J.  Each thread takes
+            // EIG_BATCH items at a time and issues all their loads before any
+            // store (the items of a round are disjoint).
+            const int nb = m * m;
+            for (int e0 = tid; e0 < nb; e0 += EIG_BATCH * EIG_THREADS) {
+                int pi[EIG_BATCH], qi[EIG_BATCH], pj[EIG_BATCH], qj[EIG_BATCH];
+                double a[EIG_BATCH][4];
+#pragma unroll
+                for (int u = 0; u < EIG_BATCH; ++u) {
+                    const int e = e0 + u * EIG_THREADS;
+                    const int I = e % m, J = e / m;
+                    pi[u] = -1;
+                    if (e < nb) {
+                        pi[u] = s_p[I];
+                        qi[u] = s_q[I];
+                        pj[u] = s_p[J];
+                        qj[u] = s_q[J];
+                        const bool vi = qi[u] < n, vj = qj[u] < n;
+                        a[u][0] = A[pi[u] + n * pj[u]];
+                        a[u][1] = vj ? A[pi[u] + n * qj[u]] : 0.0;
+                        a[u][2] = vi ? A[qi[u] + n * pj[u]] : 0.0;
+                        a[u][3] = (vi && vj) ? A[qi[u] + n * qj[u]] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EIG_BATCH; ++u) {
+                    if (pi[u] < 0) continue;
+                    const int e = e0 + u * EIG_THREADS;
+                    const int I = e % m, J = e / m;
+                    const double ci = s_c[I], si = s_s[I], cj = s_c[J], sj = s_s[J];
+                    const bool vi = qi[u] < n, vj = qj[u] < n;
+                    // rows: p' = c p - s q, q' = s p + c q; then the same on columns
+                    const double b00 = ci * a[u][0] - si * a[u][2], b01 = ci * a[u][1] - si * a[u][3];
+                    const double b10 = si * a[u][0] + ci * a[u][2], b11 = si * a[u][1] + ci * a[u][3];
+                    A[pi[u] + n * pj[u]] = cj * b00 - sj * b01;
+                    if (vj) A[pi[u] + n * qj[u]] = sj * b00 + cj * b01;
+                    if (vi) A[qi[u] + n * pj[u]] = cj * b10 - sj * b11;
+                    if (vi && vj) A[qi[u] + n * qj[u]] = sj * b10 + cj * b11;
+                }
+            }
+            const int nv = n * m;
+            for (int e0 = tid; e0 < nv; e0 += EIG_BATCH * EIG_THREADS) {
+                int row[EIG_BATCH], pj[EIG_BATCH], qj[EIG_BATCH];
+                double vp[EIG_BATCH], vq[EIG_BATCH];
+#pragma unroll
+                for (int u = 0; u < EIG_BATCH; ++u) {
+                    const int e = e0 + u * EIG_THREADS;
+                    row[u] = -1;
+                    if (e < nv) {
+                        const int J = e / n;
+                        if (s_q[J] < n) {
+                            row[u] = e - J * n;
+                            pj[u] = s_p[J];
+                            qj[u] = s_q[J];
+                            vp[u] = V[row[u] + n * pj[u]];
+                            vq[u] = V[row[u] + n * qj[u]];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EIG_BATCH; ++u) {
+                    if (row[u] < 0) continue;
+                    const int J = (e0 + u * EIG_THREADS) / n;
+                    const double cj = s_c[J], sj = s_s[J];
+                    V[row[u] + n * pj[u]] = cj * vp[u] - sj * vq[u];
+                    V[row[u] + n * qj[u]] = sj * vp[u] + cj * vq[u];
+                }
+            }
+            __syncthreads();
+        }
+        ++sweep;
+    }
+    if (!converged && tid == 0 && flag) flag[0] = 1;
+
+    // descending order of the diagonal, ties by index
+    for (int i = tid; i < n; i += EIG_THREADS) {
+        const double li = A[i + n * i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[j + n * j];
+            rank += (lj > li) || (lj == li && j < i);
+        }
+        if (rank < R) s_sel[rank] = i;
+    }
+    __syncthreads();
+    for (int r = tid; r < R; r += EIG_THREADS) {
+        const int col = s_sel[r];
+        int arg = 0;
+        double best = fabs(V[n * col]);
+        for (int i = 1; i < n; ++i) {
+            double v = fabs(V[i + n * col]);
+            if (v > best) {
+                best = v;
+                arg = i;
+            }
+        }
+        s_sign[r] = V[arg + n * col] < 0 ? -1.0 : 1.0;
+        if (lam) lam[r] = A[col + n * col];
+    }
+    __syncthreads();
+    const int nr = n * R;
+    for (int e = tid; e < nr; e += EIG_THREADS) {
+        const int i = e % n, r = e / n;
+        U[e] = s_sign[r] * V[i + n * s_sel[r]];
+    }
+}
+
+}  // namespace sth

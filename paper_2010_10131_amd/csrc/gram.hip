@@ -25,59 +25,10 @@
 //     blocks and a second kernel reduces them in a fixed order
 //     (deterministic), mirroring the lower triangle for the Gram.
 #include "common.h"
+#include "gram_body.h"
 #include "internal.h"
 
 namespace sth {
-
-constexpr int GRAM_FLUSH = 4;  // chunks of 32 rows accumulated in FP32 before an FP64 flush
-
-// Loads the 8 consecutive rows p0..p0+7 of column i of a (L, I, M) tensor.
-template <typename T>
-__device__ __forceinline__ void gram_load_octet(const T *__restrict__ X, int64_t L, int64_t I,
-                                                int64_t i, int64_t p0, int64_t pend, T (&x)[8]) {
-    if (i >= I) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = (T)0;
-        return;
-    }
-    if (L == 1) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            int64_t p = p0 + j;
-            x[j] = (p < pend) ? X[i + I * p] : (T)0;
-        }
-        return;
-    }
-    int64_t b = p0 / L;
-    int64_t a = p0 - b * L;
-    if (a + 8 <= L && p0 + 8 <= pend) {
-        const T *src = X + a + L * i + L * I * b;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) x[j] = src[j];
-        return;
-    }
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        int64_t p = p0 + j;
-        x[j] = (p < pend) ? X[a + L * i + L * I * b] : (T)0;
-        if (++a == L) {
-            a = 0;
-            ++b;
-        }
-    }
-}
-
-// Unit u of a TB x 32 slab (TB columns i, 4 octets of rows).  Lanes run along
-// i when L = 1 (contiguous in memory), along the octets otherwise.
-__device__ __forceinline__ void gram_unit(int u, int TB, bool lfast, int &il, int &oct) {
-    if (lfast) {
-        il = u % TB;
-        oct = u / TB;
-    } else {
-        oct = u & 3;
-        il = u >> 2;
-    }
-}
 
 template <typename T, int PREC, int WT, bool SYM>
 __global__ __launch_bounds__(256) void gram_kernel(const T *__restrict__ A, const T *__restrict__ B,
@@ -85,145 +36,17 @@ __global__ __launch_bounds__(256) void gram_kernel(const T *__restrict__ A, cons
                                                    int64_t kper, int nkc, int nbi, int nbj,
                                                    int nblocks, int64_t total_wg,
                                                    double *__restrict__ partials) {
-    constexpr int TB = 32 * WT;                 // block edge
-    constexpr int NQ = Frag<PREC>::NQ;
-    constexpr int UNITS = TB * 4;               // octets per slab
-    constexpr int UPT = (UNITS + 255) / 256;    // octets per thread per slab
-    typedef typename Acc<PREC>::type AccT;
-    constexpr bool F64ACC = (PREC == P_FP64);
+    gram_body<T, PREC, WT, SYM>(A, B, L, IA, IB, P, kper, nkc, nbi, nbj, nblocks, total_wg,
+                                xcd_logical_id(total_wg), partials);
+}
 
-    // LDS: slab A then slab B, each [q][il][oct] quads
-    extern __shared__ uint4 s_g[];
-    uint4 *sA = s_g;
-    uint4 *sB = s_g + NQ * TB * 4;
-
-    // XCD-aware mapping: consecutive logical ids (same row range, all blocks)
-    // land on the same XCD.
-    const int64_t per_xcd = (total_wg + 7) / 8;
-    const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (lid >= total_wg) return;
-    const int kc = (int)(lid / nblocks);
-    const int q = (int)(lid - (int64_t)kc * nblocks);
-    int bi, bj;
-    if (SYM) {
-        // lower-triangle enumeration: q -> (bi >= bj)
-        bi = 0;
-        while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
-        bj = q - bi * (bi + 1) / 2;
-    } else {
-        bi = q % nbi;
-        bj = q / nbi;
-    }
-    const bool diag = SYM && (bi == bj);
-    const int64_t i0 = (int64_t)bi * TB, j0 = (int64_t)bj * TB;
-    const int64_t pbeg = (int64_t)kc * kper;
-    const int64_t pend = min(P, pbeg + kper);
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wi = wave >> 1, wj = wave & 1;
-    const bool active = !(diag && wi < wj);
-    const bool lfast = (L == 1);
-
-    AccT acc[WT][WT];
-    f64x4 acc64[WT][WT];
-#pragma unroll
-    for (int x = 0; x < WT; ++x)
-#pragma unroll
-        for (int y = 0; y < WT; ++y) {
-            acc[x][y] = AccT{0, 0, 0, 0};
-            acc64[x][y] = f64x4{0, 0, 0, 0};
-        }
-
-    T ra[UPT][8], rb[UPT][8];
-    auto load_slab = [&](int64_t pc) {
-#pragma unroll
-        for (int s = 0; s < UPT; ++s) {
-            int u = threadIdx.x + 256 * s;
-            int il, oct;
-            gram_unit(u, TB, lfast, il, oct);
-            if (u < UNITS) {
-                gram_load_octet<T>(A, L, IA, i0 + il, pc + 8 * oct, pend, ra[s]);
-                if (!diag) gram_load_octet<T>(B, L, IB, j0 + il, pc + 8 * oct, pend, rb[s]);
-            }
-        }
-    };
-    auto store_slab = [&]() {
-#pragma unroll
-        for (int s = 0; s < UPT; ++s) {
-            int u = threadIdx.x + 256 * s;
-            int il, oct;
-            gram_unit(u, TB, lfast, il, oct);
-            if (u < UNITS) {
-                FragQ<PREC> f;
-                make_frag(ra[s], f.f);
-#pragma unroll
-                for (int qq = 0; qq < NQ; ++qq) sA[(qq * TB + il) * 4 + oct] = f.q[qq];
-                if (!diag) {
-                    make_frag(rb[s], f.f);
-#pragma unroll
-                    for (int qq = 0; qq < NQ; ++qq) sB[(qq * TB + il) * 4 + oct] = f.q[qq];
-                }
-            }
-        }
-    };
-
-    const int nch = (int)((pend - pbeg + KC - 1) / KC);
-    if (nch > 0) load_slab(pbeg);
-    const uint4 *sBr = diag ? sA : sB;
-    for (int c = 0; c < nch; ++c) {
-        __syncthreads();  // previous chunk's reads are done
-        store_slab();
-        __syncthreads();
-        if (c + 1 < nch) load_slab(pbeg + (int64_t)(c + 1) * KC);
-        if (active) {
-            Frag<PREC> fa[WT], fb[WT];
-#pragma unroll
-            for (int x = 0; x < WT; ++x) {
-                FragQ<PREC> t;
-                const int il = wi * (16 * WT) + 16 * x + (lane & 15);
-#pragma unroll
-                for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sA[(qq * TB + il) * 4 + (lane >> 4)];
-                fa[x] = t.f;
-            }
-#pragma unroll
-            for (int y = 0; y < WT; ++y) {
-                FragQ<PREC> t;
-                const int jl = wj * (16 * WT) + 16 * y + (lane & 15);
-#pragma unroll
-                for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sBr[(qq * TB + jl) * 4 + (lane >> 4)];
-                fb[y] = t.f;
-            }
-#pragma unroll
-            for (int x = 0; x < WT; ++x)
-#pragma unroll
-                for (int y = 0; y < WT; ++y) mma_frag(fa[x], fb[y], acc[x][y]);
-            if (!F64ACC && ((c + 1) % GRAM_FLUSH == 0 || c + 1 == nch)) {
-#pragma unroll
-                for (int x = 0; x < WT; ++x)
-#pragma unroll
-                    for (int y = 0; y < WT; ++y) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) acc64[x][y][v] += (double)acc[x][y][v];
-                        acc[x][y] = AccT{0, 0, 0, 0};
-                    }
-            }
-        }
-    }
-    if (!active) return;
-    // partial block (TB x TB, column-major) for (kc, q)
-    double *dst = partials + ((int64_t)kc * nblocks + q) * (int64_t)TB * TB;
-#pragma unroll
-    for (int x = 0; x < WT; ++x)
-#pragma unroll
-        for (int y = 0; y < WT; ++y) {
-            const int jl = wj * (16 * WT) + 16 * y + (lane & 15);
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int il = wi * (16 * WT) + 16 * x + drow<PREC>(lane >> 4, v);
-                double val = F64ACC ? (double)acc[x][y][v] : acc64[x][y][v];
-                dst[il + TB * jl] = val;
-            }
-        }
+template <int PREC, int WT, bool VEC4>
+__global__ __launch_bounds__(256) void gram_l1_kernel(const float *__restrict__ Y, int64_t I,
+                                                      int64_t P, int64_t kper, int nkc, int nblocks,
+                                                      int64_t total_wg,
+                                                      double *__restrict__ partials) {
+    gram_l1_body<PREC, WT, VEC4>(Y, I, P, kper, nkc, nblocks, total_wg, xcd_logical_id(total_wg),
+                                 partials);
 }
 
 // Sums the partial blocks over the row ranges in a fixed order and writes
@@ -262,7 +85,13 @@ struct GramShape {
     int64_t kper;
 };
 
+GramShape gram_shape_t(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target);
+
 GramShape gram_shape(int64_t IA, int64_t IB, int64_t P, bool sym) {
+    return gram_shape_t(IA, IB, P, sym, 2 * (int64_t)device_cu_count());
+}
+
+GramShape gram_shape_t(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target) {
     GramShape g;
     int64_t imax = std::max(IA, IB);
     g.wt = imax > 64 ? 4 : (imax > 32 ? 2 : 1);
@@ -270,9 +99,8 @@ GramShape gram_shape(int64_t IA, int64_t IB, int64_t P, bool sym) {
     g.nbi = (int)((IA + g.tb - 1) / g.tb);
     g.nbj = (int)((IB + g.tb - 1) / g.tb);
     g.nblocks = sym ? g.nbi * (g.nbi + 1) / 2 : g.nbi * g.nbj;
-    // aim at ~2 workgroups per CU overall, rows per workgroup >= 512, and
-    // partial traffic well below the input traffic
-    const int64_t target = 2 * (int64_t)device_cu_count();
+    // aim at `target` workgroups (about 2 per CU for one tensor), rows per
+    // workgroup >= 512, and partial traffic well below the input traffic
     int64_t nkc = std::max<int64_t>(1, target / g.nblocks);
     int64_t maxk = std::max<int64_t>(1, P / 512);
     nkc = std::min(nkc, maxk);
@@ -284,6 +112,24 @@ GramShape gram_shape(int64_t IA, int64_t IB, int64_t P, bool sym) {
     return g;
 }
 
+template <int PREC, int WT>
+hipError_t launch_gram_l1(const float *A, int64_t IA, int64_t M, const GramShape &g,
+                          double *partials, hipStream_t s) {
+    constexpr int TB = 32 * WT;
+    const int64_t total = (int64_t)g.nkc * g.nblocks;
+    const int64_t per_xcd = (total + 7) / 8;
+    const size_t lds = (size_t)2 * 2 * Frag<PREC>::NQ * 4 * TB * 16;
+    const bool vec = (IA % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+    auto kern = vec ? gram_l1_kernel<PREC, WT, true> : gram_l1_kernel<PREC, WT, false>;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3((unsigned)(per_xcd * 8)), dim3(256), lds, s, A, IA, M, g.kper,
+                       g.nkc, g.nblocks, total, partials);
+    return hipGetLastError();
+}
+
 template <typename T, int PREC, int WT, bool SYM>
 hipError_t launch_gram_t(const T *A, const T *B, int64_t L, int64_t IA, int64_t IB, int64_t M,
                          const GramShape &g, double *partials, double *S, hipStream_t s) {
@@ -291,6 +137,15 @@ hipError_t launch_gram_t(const T *A, const T *B, int64_t L, int64_t IA, int64_t 
     const int64_t P = L * M;
     const int64_t total = (int64_t)g.nkc * g.nblocks;
     const int64_t per_xcd = (total + 7) / 8;
+    if constexpr (SYM && sizeof(T) == 4) {
+        if (L == 1 && WT >= 2) {
+            hipError_t e = launch_gram_l1<PREC, WT>(A, IA, M, g, partials, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((gram_reduce_kernel<TB, SYM>), dim3((TB * TB + 255) / 256, g.nblocks),
+                               dim3(256), 0, s, partials, g.nkc, g.nbi, g.nblocks, IA, IB, S);
+            return hipGetLastError();
+        }
+    }
     const size_t lds = (size_t)2 * Frag<PREC>::NQ * TB * 4 * 16;
     auto kern = gram_kernel<T, PREC, WT, SYM>;
     if (lds > 64 * 1024) {
@@ -332,6 +187,17 @@ hipError_t launch_gram_d(int dtype, int prec, const void *A, const void *B, int6
 }
 
 }  // namespace
+
+void gram_geometry(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int *wt, int *nbi,
+                   int *nbj, int *nblocks, int *nkc, int64_t *kper) {
+    GramShape g = gram_shape_t(IA, IB, P, sym, target);
+    *wt = g.wt;
+    *nbi = g.nbi;
+    *nbj = g.nbj;
+    *nblocks = g.nblocks;
+    *nkc = g.nkc;
+    *kper = g.kper;
+}
 
 size_t gram_ws_bytes(int64_t IA, int64_t IB, int64_t P, bool sym) {
     GramShape g = gram_shape(IA, IB, P, sym);

@@ -1,0 +1,427 @@
+// Device bodies of the Gram / TTT kernels (one workgroup each), shared by the
+// single-tensor kernels and the batched ones.
+#pragma once
+#include "common.h"
+
+namespace sth {
+
+constexpr int GRAM_FLUSH = 4;  // chunks of 32 rows accumulated in FP32 before an FP64 flush
+
+// Loads the 8 consecutive rows p0..p0+7 of column i of a (L, I, M) tensor.
+template <typename T>
+__device__ __forceinline__ void gram_load_octet(const T *__restrict__ X, int64_t L, int64_t I,
+                                                int64_t i, int64_t p0, int64_t pend, T (&x)[8]) {
+    if (i >= I) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = (T)0;
+        return;
+    }
+    if (L == 1) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int64_t p = p0 + j;
+            x[j] = (p < pend) ? X[i + I * p] : (T)0;
+        }
+        return;
+    }
+    int64_t b = p0 / L;
+    int64_t a = p0 - b * L;
+    if (a + 8 <= L && p0 + 8 <= pend) {
+        const T *src = X + a + L * i + L * I * b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) x[j] = src[j];
+        return;
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        int64_t p = p0 + j;
+        x[j] = (p < pend) ? X[a + L * i + L * I * b] : (T)0;
+        if (++a == L) {
+            a = 0;
+            ++b;
+        }
+    }
+}
+
+// Unit u of a TB x 32 slab (TB columns i, 4 octets of rows).  Lanes run along
+// i when L = 1 (contiguous in memory), along the octets otherwise.
+__device__ __forceinline__ void gram_unit(int u, int TB, bool lfast, int &il, int &oct) {
+    if (lfast) {
+        il = u % TB;
+        oct = u / TB;
+    } else {
+        oct = u & 3;
+        il = u >> 2;
+    }
+}
+
+// XCD-aware mapping of a launch of total_wg workgroups: consecutive logical
+// ids (same row range, all blocks) land on the same XCD.
+__device__ __forceinline__ int64_t xcd_logical_id(int64_t total_wg) {
+    const int64_t per_xcd = (total_wg + 7) / 8;
+    return (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+}
+
+// One workgroup of the Gram/TTT: logical id lid = row range * nblocks + block.
+template <typename T, int PREC, int WT, bool SYM>
+__device__ __forceinline__ void gram_body(const T *__restrict__ A, const T *__restrict__ B,
+                                          int64_t L, int64_t IA, int64_t IB, int64_t P,
+                                          int64_t kper, int nkc, int nbi, int nbj, int nblocks,
+                                          int64_t total_wg, int64_t lid,
+                                          double *__restrict__ partials) {
+    constexpr int TB = 32 * WT;                 // block edge
+    constexpr int NQ = Frag<PREC>::NQ;
+    constexpr int UNITS = TB * 4;               // octets per slab
+    constexpr int UPT = (UNITS + 255) / 256;    // octets per thread per slab
+    typedef typename Acc<PREC>::type AccT;
+    constexpr bool F64ACC = (PREC == P_FP64);
+
+    // LDS: slab A then slab B, each [q][il][oct] quads
+    extern __shared__ uint4 s_g[];
+    uint4 *sA = s_g;
+    uint4 *sB = s_g + NQ * TB * 4;
+
+    if (lid >= total_wg) return;
+    const int kc = (int)(lid / nblocks);
+    const int q = (int)(lid - (int64_t)kc * nblocks);
+    int bi, bj;
+    if (SYM) {
+        // lower-triangle enumeration: q -> (bi >= bj)
+        bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
+        bj = q - bi * (bi + 1) / 2;
+    } else {
+        bi = q % nbi;
+        bj = q / nbi;
+    }
+    const bool diag = SYM && (bi == bj);
+    const int64_t i0 = (int64_t)bi * TB, j0 = (int64_t)bj * TB;
+    const int64_t pbeg = (int64_t)kc * kper;
+    const int64_t pend = min(P, pbeg + kper);
+
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const bool active = !(diag && wi < wj);
+    const bool lfast = (L == 1);
+
+    AccT acc[WT][WT];
+    f64x4 acc64[WT][WT];
+#pragma unroll
+    for (int x = 0; x < WT; ++x)
+#pragma unroll
+        for (int y = 0; y < WT; ++y) {
+            acc[x][y] = AccT{0, 0, 0, 0};
+            acc64[x][y] = f64x4{0, 0, 0, 0};
+        }
+
+    T ra[UPT][8], rb[UPT][8];
+    auto load_slab = [&](int64_t pc) {
+#pragma unroll
+        for (int s = 0; s < UPT; ++s) {
+            int u = threadIdx.x + 256 * s;
+            int il, oct;
+            gram_unit(u, TB, lfast, il, oct);
+            if (u < UNITS) {
+                gram_load_octet<T>(A, L, IA, i0 + il, pc + 8 * oct, pend, ra[s]);
+                if (!diag) gram_load_octet<T>(B, L, IB, j0 + il, pc + 8 * oct, pend, rb[s]);
+            }
+        }
+    };
+    auto store_slab = [&]() {
+#pragma unroll
+        for (int s = 0; s < UPT; ++s) {
+            int u = threadIdx.x + 256 * s;
+            int il, oct;
+            gram_unit(u, TB, lfast, il, oct);
+            if (u < UNITS) {
+                FragQ<PREC> f;
+                make_frag(ra[s], f.f);
+#pragma unroll
+                for (int qq = 0; qq < NQ; ++qq) sA[(qq * TB + il) * 4 + oct] = f.q[qq];
+                if (!diag) {
+                    make_frag(rb[s], f.f);
+#pragma unroll
+                    for (int qq = 0; qq < NQ; ++qq) sB[(qq * TB + il) * 4 + oct] = f.q[qq];
+                }
+            }
+        }
+    };
+
+    const int nch = (int)((pend - pbeg + KC - 1) / KC);
+    if (nch > 0) load_slab(pbeg);
+    const uint4 *sBr = diag ? sA : sB;
+    for (int c = 0; c < nch; ++c) {
+        __syncthreads();  // previous chunk's reads are done
+        store_slab();
+        __syncthreads();
+        if (c + 1 < nch) load_slab(pbeg + (int64_t)(c + 1) * KC);
+        if (active) {
+            Frag<PREC> fa[WT], fb[WT];
+#pragma unroll
+            for (int x = 0; x < WT; ++x) {
+                FragQ<PREC> t;
+                const int il = wi * (16 * WT) + 16 * x + (lane & 15);
+#pragma unroll
+                for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sA[(qq * TB + il) * 4 + (lane >> 4)];
+                fa[x] = t.f;
+            }
+#pragma unroll
+            for (int y = 0; y < WT; ++y) {
+                FragQ<PREC> t;
+                const int jl = wj * (16 * WT) + 16 * y + (lane & 15);
+#pragma unroll
+                for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sBr[(qq * TB + jl) * 4 + (lane >> 4)];
+                fb[y] = t.f;
+            }
+#pragma unroll
+            for (int x = 0; x < WT; ++x)
+#pragma unroll
+                for (int y = 0; y < WT; ++y) mma_frag(fa[x], fb[y], acc[x][y]);
+            if (!F64ACC && ((c + 1) % GRAM_FLUSH == 0 || c + 1 == nch)) {
+#pragma unroll
+                for (int x = 0; x < WT; ++x)
+#pragma unroll
+                    for (int y = 0; y < WT; ++y) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc64[x][y][v] += (double)acc[x][y][v];
+                        acc[x][y] = AccT{0, 0, 0, 0};
+                    }
+            }
+        }
+    }
+    if (!active) return;
+    // partial block (TB x TB, column-major) for (kc, q)
+    double *dst = partials + ((int64_t)kc * nblocks + q) * (int64_t)TB * TB;
+#pragma unroll
+    for (int x = 0; x < WT; ++x)
+#pragma unroll
+        for (int y = 0; y < WT; ++y) {
+            const int jl = wj * (16 * WT) + 16 * y + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int il = wi * (16 * WT) + 16 * x + drow<PREC>(lane >> 4, v);
+                double val = F64ACC ? (double)acc[x][y][v] : acc64[x][y][v];
+                dst[il + TB * jl] = val;
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// First-mode (L = 1) variant for FP32 data.  Each row p of the contraction
+// is a contiguous run of I floats, so a slab of TB columns x 32 rows is read
+// with 16-byte loads along i (lanes 0..TB/4-1 cover one row).  A thread
+// holds 4 columns x LPT rows; the rows it holds are mapped to LPT
+// consecutive fragment slots of one lane group:
+//   row pc + ph + PH*s  ->  group g = ph % 4, slot j = LPT*(ph / 4) + s,
+// the same bijection for A and B, which is all the matrix cores need.
+// LDS holds two slabs per operand (double buffering, one barrier per chunk)
+// and the loads run two chunks ahead of the matrix cores.
+template <int PREC>
+__device__ __forceinline__ void l1_store(uint8_t *slab, int TB, int g, int row, int slot0,
+                                         const float *v, int nv) {
+    // slab: base of one operand buffer, quads [qq][g][row]
+    if constexpr (PREC == P_BF16X3 || PREC == P_BF16X6) {
+        constexpr int NP = (PREC == P_BF16X3) ? 2 : 3;
+        __bf16 part[NP][4];
+        for (int k = 0; k < nv; ++k) {
+            float x = v[k];
+            __bf16 h = to_bf16(x);
+            float r1 = x - from_bf16(h);
+            __bf16 m = to_bf16(r1);
+            part[0][k] = h;
+            part[1][k] = m;
+            if constexpr (NP == 3) part[2][k] = to_bf16(r1 - from_bf16(m));
+        }
+#pragma unroll
+        for (int qq = 0; qq < NP; ++qq) {
+            uint8_t *q = slab + ((size_t)((qq * 4 + g) * TB + row)) * 16 + 2 * slot0;
+            if (nv == 4) {
+                uint2 w;
+                __builtin_memcpy(&w, part[qq], 8);
+                *reinterpret_cast<uint2 *>(q) = w;
+            } else {
+                uint32_t w;
+                __builtin_memcpy(&w, part[qq], 4);
+                *reinterpret_cast<uint32_t *>(q) = w;
+            }
+        }
+    } else if constexpr (PREC == P_FP32) {
+        // slot j -> quad j / 4, element j % 4
+        const int qq = slot0 / 4, e = slot0 % 4;
+        float *q = reinterpret_cast<float *>(slab + ((size_t)((qq * 4 + g) * TB + row)) * 16) + e;
+        for (int k = 0; k < nv; ++k) q[k] = v[k];
+    } else {
+        // FP64: slot j -> quad j / 2, element j % 2
+        for (int k = 0; k < nv; ++k) {
+            const int j = slot0 + k;
+            double *q = reinterpret_cast<double *>(slab + ((size_t)(((j / 2) * 4 + g) * TB + row)) * 16) + (j % 2);
+            *q = (double)v[k];
+        }
+    }
+}
+
+template <int PREC, int WT, bool VEC4>
+__device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_t I, int64_t P,
+                                             int64_t kper, int nkc, int nblocks, int64_t total_wg,
+                                             int64_t lid, double *__restrict__ partials) {
+    constexpr int TB = 32 * WT;
+    constexpr int NQ = Frag<PREC>::NQ;
+    constexpr int IQ = TB / 4;          // 16-byte column quads per row
+    constexpr int PH = 256 / IQ;        // rows covered by one pass of the workgroup
+    constexpr int LPT = KC / PH;        // rows (loads) per thread per chunk
+    constexpr int SLAB = NQ * 4 * TB * 16;  // bytes of one operand buffer
+    typedef typename Acc<PREC>::type AccT;
+    constexpr bool F64ACC = (PREC == P_FP64);
+    extern __shared__ uint4 s_g[];
+    uint8_t *lds = reinterpret_cast<uint8_t *>(s_g);  // [buf][operand][SLAB]
+
+    if (lid >= total_wg) return;
+    const int kc = (int)(lid / nblocks);
+    const int q = (int)(lid - (int64_t)kc * nblocks);
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
+    const int bj = q - bi * (bi + 1) / 2;
+    const bool diag = (bi == bj);
+    const int64_t i0 = (int64_t)bi * TB, j0 = (int64_t)bj * TB;
+    const int64_t pbeg = (int64_t)kc * kper;
+    const int64_t pend = min(P, pbeg + kper);
+    const int nch = (int)((pend - pbeg + KC - 1) / KC);
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wi = wave >> 1, wj = wave & 1;
+    const bool active = !(diag && wi < wj);
+    const int iq = tid % IQ, ph = tid / IQ;
+    const int g_st = ph % 4, slot0 = LPT * (ph / 4);
+
+    auto load = [&](int64_t pc, int64_t c0, float4 (&r)[LPT]) {
+        const int64_t col = c0 + 4 * iq;
+#pragma unroll
+        for (int s = 0; s < LPT; ++s) {
+            const int64_t p = pc + ph + PH * s;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (p < pend) {
+                const float *src = Y + I * p + col;
+                if (VEC4 && col + 4 <= I) {
+                    v = *reinterpret_cast<const float4 *>(src);
+                } else {
+                    if (col + 0 < I) v.x = src[0];
+                    if (col + 1 < I) v.y = src[1];
+                    if (col + 2 < I) v.z = src[2];
+                    if (col + 3 < I) v.w = src[3];
+                }
+            }
+            r[s] = v;
+        }
+    };
+    auto store = [&](int buf, int op, const float4 (&r)[LPT]) {
+        uint8_t *slab = lds + (size_t)(buf * 2 + op) * SLAB;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            float v[LPT];
+#pragma unroll
+            for (int s = 0; s < LPT; ++s) v[s] = (&r[s].x)[c];
+            l1_store<PREC>(slab, TB, g_st, 4 * iq + c, slot0, v, LPT);
+        }
+    };
+
+    AccT acc[WT][WT];
+    f64x4 acc64[WT][WT];
+#pragma unroll
+    for (int x = 0; x < WT; ++x)
+#pragma unroll
+        for (int y = 0; y < WT; ++y) {
+            acc[x][y] = AccT{0, 0, 0, 0};
+            acc64[x][y] = f64x4{0, 0, 0, 0};
+        }
+
+    auto compute = [&](int buf, int c) {
+        if (!active) return;
+        const uint4 *sA = reinterpret_cast<const uint4 *>(lds + (size_t)(buf * 2 + 0) * SLAB);
+        const uint4 *sB = reinterpret_cast<const uint4 *>(lds + (size_t)(buf * 2 + (diag ? 0 : 1)) * SLAB);
+        const int g = lane >> 4;
+        Frag<PREC> fa[WT], fb[WT];
+#pragma unroll
+        for (int x = 0; x < WT; ++x) {
+            FragQ<PREC> t;
+            const int row = wi * (16 * WT) + 16 * x + (lane & 15);
+#pragma unroll
+            for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sA[(qq * 4 + g) * TB + row];
+            fa[x] = t.f;
+        }
+#pragma unroll
+        for (int y = 0; y < WT; ++y) {
+            FragQ<PREC> t;
+            const int row = wj * (16 * WT) + 16 * y + (lane & 15);
+#pragma unroll
+            for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sB[(qq * 4 + g) * TB + row];
+            fb[y] = t.f;
+        }
+#pragma unroll
+        for (int x = 0; x < WT; ++x)
+#pragma unroll
+            for (int y = 0; y < WT; ++y) mma_frag(fa[x], fb[y], acc[x][y]);
+        if (!F64ACC && ((c + 1) % GRAM_FLUSH == 0 || c + 1 == nch)) {
+#pragma unroll
+            for (int x = 0; x < WT; ++x)
+#pragma unroll
+                for (int y = 0; y < WT; ++y) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc64[x][y][v] += (double)acc[x][y][v];
+                    acc[x][y] = AccT{0, 0, 0, 0};
+                }
+        }
+    };
+
+    float4 ra0[LPT], rb0[LPT], ra1[LPT], rb1[LPT];
+    if (nch > 0) {
+        load(pbeg, i0, ra0);
+        if (!diag) load(pbeg, j0, rb0);
+        if (nch > 1) {
+            load(pbeg + KC, i0, ra1);
+            if (!diag) load(pbeg + KC, j0, rb1);
+        }
+        store(0, 0, ra0);
+        if (!diag) store(0, 1, rb0);
+    }
+    __syncthreads();
+    for (int c = 0; c < nch; c += 2) {
+        // chunk c in buffer 0; chunk c+1 in flight in ra1/rb1
+        if (c + 2 < nch) {
+            load(pbeg + (int64_t)(c + 2) * KC, i0, ra0);
+            if (!diag) load(pbeg + (int64_t)(c + 2) * KC, j0, rb0);
+        }
+        compute(0, c);
+        if (c + 1 < nch) {
+            store(1, 0, ra1);
+            if (!diag) store(1, 1, rb1);
+        }
+        __syncthreads();
+        if (c + 1 >= nch) break;
+        // chunk c+1 in buffer 1; chunk c+2 in flight in ra0/rb0
+        if (c + 3 < nch) {
+            load(pbeg + (int64_t)(c + 3) * KC, i0, ra1);
+            if (!diag) load(pbeg + (int64_t)(c + 3) * KC, j0, rb1);
+        }
+        compute(1, c + 1);
+        if (c + 2 < nch) {
+            store(0, 0, ra0);
+            if (!diag) store(0, 1, rb0);
+        }
+        __syncthreads();
+    }
+    if (!active) return;
+    double *dst = partials + ((int64_t)kc * nblocks + q) * (int64_t)TB * TB;
+#pragma unroll
+    for (int x = 0; x < WT; ++x)
+#pragma unroll
+        for (int y = 0; y < WT; ++y) {
+            const int jl = wj * (16 * WT) + 16 * y + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int il = wi * (16 * WT) + 16 * x + drow<PREC>(lane >> 4, v);
+                dst[il + TB * jl] = F64ACC ? (double)acc[x][y][v] : acc64[x][y][v];
+            }
+        }
+}
+
+}  // namespace sth

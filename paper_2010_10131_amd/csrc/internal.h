@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <vector>
 
 namespace sth {
 
@@ -48,6 +49,46 @@ hipError_t fill_f64(double *p, int64_t n, double v, hipStream_t s);
 hipError_t copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t zero_words(void *p, int64_t nwords, hipStream_t s);
 hipError_t gaussian_f64(double *p, int64_t n, uint64_t seed, uint64_t stream, hipStream_t s);
+
+// Gram geometry with a target number of workgroups (gram.hip)
+void gram_geometry(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int *wt, int *nbi,
+                   int *nbj, int *nblocks, int *nkc, int64_t *kper);
+
+// Batched path (batch.hip).  One descriptor per tensor per mode step.
+constexpr int BT_WAVES = 8;
+struct BatchStep {
+    int64_t L, I, M, R;
+    int64_t src_off, dst_off;  // byte offsets into the workspace; -1 = caller's X / core
+    int64_t part_off, S_off, uq_off, eig_off;
+    int64_t kper, gram_wg;
+    int32_t nkc, nbi, nblocks, wt;
+    int32_t nchunks, ntiles, rtb, contig;
+    int32_t tensor, pad;
+};
+struct BatchLaunch {
+    const int32_t *list;  // device: indices into the step's descriptors
+    const int64_t *pref;  // device: prefix sums of the work units (len + 1)
+    int len;
+    int64_t total;
+    int cls;  // tile class (Gram: WT; TTM: r-tiles per workgroup)
+};
+struct BatchTables {
+    const BatchStep *descs;  // device
+};
+struct BatchStepPlan {
+    int count;
+    size_t eig_lds;
+    int max_nchunks;
+    std::vector<BatchLaunch> gram, reduce, ttm;
+    BatchLaunch prep;
+};
+size_t batch_gram_lds(int prec, int wt);
+size_t batch_eig_lds(int64_t n, int64_t R);
+size_t batch_eig_scratch(int64_t n, int64_t R);
+hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int gram_prec,
+                             int ttm_prec, int order, int mode, char *ws, const void *const *Xp,
+                             void *const *Cp, double *const *Up, int64_t *flag, int max_sweeps,
+                             hipStream_t s);
 
 // Learned selector MLP (mlp.hip)
 size_t mlp_ws_bytes(int64_t B);

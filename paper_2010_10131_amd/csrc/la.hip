@@ -8,6 +8,7 @@
 //                 Alg. 3 and for Cholesky-QR
 //   sumsq / diff  FP64 sums of squares with per-block partials reduced in a
 //                 fixed order
+#include "chol_body.h"
 #include "common.h"
 #include "internal.h"
 
@@ -94,7 +95,7 @@ size_t gemm_ws_bytes(int m, int n, int k) {
 int gemm_splits(int m, int n, int k) {
     int tiles = ((m + GT - 1) / GT) * ((n + GT - 1) / GT);
     int nz = 1;
-    while (tiles * nz < 64 && k / (nz * 2) >= 128 && nz < 32) nz *= 2;
+    while (tiles * nz < 256 && k / (nz * 2) >= 64 && nz < 32) nz *= 2;
     return nz;
 }
 
@@ -119,164 +120,14 @@ hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const dou
     return hipGetLastError();
 }
 
-// One workgroup of 256 threads, n <= 128, everything in LDS.
-// G (n x n, symmetric, ldg) + shift_rel * trace(G) / n * I = L L^T, blocked
-// right-looking Cholesky with 16-column panels: the diagonal block is
-// factored by one wave in registers (row i of the block in lane i, columns
-// broadcast with cross-lane shuffles), the panel below by a row-parallel
-// forward substitution and the trailing matrix by an element-parallel
-// rank-16 update.  L is then inverted in place block column by block column
-// from the last one:  L^{-1}(B, K) = -(sum_{J in (K, B]} L^{-1}(B, J) L(J, K))
-// L(K, K)^{-1}.  Writes R = L^T (upper, may be NULL) and Rinv = L^{-T}
-// (upper).  A non-positive pivot sets flag[0] = 2 and is replaced by a tiny
-// positive one so that the run continues.
 constexpr int CHOL_THREADS = 256;
-constexpr int CB = 16;
 
 __global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(const double *__restrict__ G, int n,
                                                             int64_t ldg, double shift_rel,
                                                             double *__restrict__ Rout,
                                                             double *__restrict__ Rinv,
                                                             int64_t *__restrict__ flag) {
-    extern __shared__ double s_l[];  // L, column-major, leading dimension n; then T (n x CB)
-    double *s_tmp = s_l + n * n;
-    __shared__ double s_dinv[CB * CB];
-    __shared__ double s_tr;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < n * n; e += CHOL_THREADS) {
-        int i = e % n, j = e / n;
-        s_l[e] = (i >= j) ? G[i + ldg * j] : 0.0;
-    }
-    if (tid == 0) {
-        double t = 0.0;
-        for (int i = 0; i < n; ++i) t += G[i + ldg * i];
-        s_tr = t;
-    }
-    __syncthreads();
-    if (shift_rel != 0.0) {
-        const double sh = shift_rel * s_tr / n;
-        for (int i = tid; i < n; i += CHOL_THREADS) s_l[i + n * i] += sh;
-        __syncthreads();
-    }
-    const double tiny = 1e-300 + 1e-30 * fabs(s_tr);
-    bool bad = false;
-    for (int k0 = 0; k0 < n; k0 += CB) {
-        const int kn = min(CB, n - k0);
-        // 1. diagonal block, wave 0, row i in lane i
-        if (wave == 0) {
-            double row[CB];
-#pragma unroll
-            for (int c = 0; c < CB; ++c) row[c] = (lane < kn && c < kn) ? s_l[k0 + lane + n * (k0 + c)] : 0.0;
-#pragma unroll
-            for (int j = 0; j < CB; ++j) {
-                if (j < kn) {
-                    // d = a(j,j) - sum_{c<j} L(j,c)^2, computed in lane j, then broadcast
-                    double sacc = row[j];
-#pragma unroll
-                    for (int c = 0; c < CB; ++c)
-                        if (c < j) sacc -= row[c] * __shfl(row[c], j);
-                    double d = __shfl(sacc, j);
-                    if (!(d > 0.0)) {
-                        bad = true;
-                        d = tiny;
-                    }
-                    d = sqrt(d);
-                    if (lane == j) row[j] = d;
-                    else if (lane > j) row[j] = sacc / d;
-                }
-            }
-            if (lane < kn)
-#pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    if (c < kn) s_l[k0 + lane + n * (k0 + c)] = (c <= lane) ? row[c] : 0.0;
-        }
-        __syncthreads();
-        // 2. panel rows i >= k0 + kn: forward substitution against the block
-        for (int i = k0 + kn + tid; i < n; i += CHOL_THREADS) {
-            double x[CB];
-#pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                if (c < kn) {
-                    double sacc = s_l[i + n * (k0 + c)];
-#pragma unroll
-                    for (int d = 0; d < CB; ++d)
-                        if (d < c) sacc -= x[d] * s_l[k0 + c + n * (k0 + d)];
-                    x[c] = sacc / s_l[k0 + c + n * (k0 + c)];
-                }
-            }
-#pragma unroll
-            for (int c = 0; c < CB; ++c)
-                if (c < kn) s_l[i + n * (k0 + c)] = x[c];
-        }
-        __syncthreads();
-        // 3. trailing update of the lower part
-        const int t0 = k0 + kn, w = n - t0;
-        for (int e = tid; e < w * w; e += CHOL_THREADS) {
-            const int i = t0 + e % w, j = t0 + e / w;
-            if (i < j) continue;
-            double sacc = 0.0;
-#pragma unroll
-            for (int c = 0; c < CB; ++c)
-                if (c < kn) sacc += s_l[i + n * (k0 + c)] * s_l[j + n * (k0 + c)];
-            s_l[i + n * j] -= sacc;
-        }
-        __syncthreads();
-    }
-    if (bad && flag) flag[0] = 2;
-    if (Rout)
-        for (int e = tid; e < n * n; e += CHOL_THREADS) {
-            int i = e % n, j = e / n;  // R(i, j) = L(j, i)
-            Rout[e] = (i <= j) ? s_l[j + n * i] : 0.0;
-        }
-    __syncthreads();
-    // in-place inverse, block columns from the last one
-    const int nb = (n + CB - 1) / CB;
-    for (int kb = nb - 1; kb >= 0; --kb) {
-        const int k0 = kb * CB, kn = min(CB, n - k0), t0 = k0 + kn;
-        // D^{-1} of the diagonal block (lower), one thread per column
-        if (tid < kn) {
-            const int c = tid;
-            double x[CB];
-#pragma unroll
-            for (int r = 0; r < CB; ++r) {
-                if (r < kn) {
-                    double sacc = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-                    for (int d = 0; d < CB; ++d)
-                        if (d < r) sacc -= s_l[k0 + r + n * (k0 + d)] * x[d];
-                    x[r] = (r < c) ? 0.0 : sacc / s_l[k0 + r + n * (k0 + r)];
-                }
-            }
-#pragma unroll
-            for (int r = 0; r < CB; ++r)
-                if (r < kn) s_dinv[r + CB * c] = x[r];
-        }
-        // T(i, c) = sum_{j in [t0, i]} Linv(i, j) L(j, k0 + c) for rows i >= t0
-        for (int e = tid; e < (n - t0) * kn; e += CHOL_THREADS) {
-            const int i = t0 + e % (n - t0), c = e / (n - t0);
-            double sacc = 0.0;
-            for (int j = t0; j <= i; ++j) sacc += s_l[i + n * j] * s_l[j + n * (k0 + c)];
-            s_tmp[(i - t0) + (n - t0) * c] = sacc;
-        }
-        __syncthreads();
-        // Linv(i, k0 + c) = -sum_d T(i, d) Dinv(d, c);  diagonal block = Dinv
-        for (int e = tid; e < (n - t0) * kn; e += CHOL_THREADS) {
-            const int i = t0 + e % (n - t0), c = e / (n - t0);
-            double sacc = 0.0;
-            for (int d = c; d < kn; ++d) sacc += s_tmp[(i - t0) + (n - t0) * d] * s_dinv[d + CB * c];
-            s_l[i + n * (k0 + c)] = -sacc;
-        }
-        for (int e = tid; e < kn * kn; e += CHOL_THREADS) {
-            const int r = e % kn, c = e / kn;
-            s_l[k0 + r + n * (k0 + c)] = (r >= c) ? s_dinv[r + CB * c] : 0.0;
-        }
-        __syncthreads();
-    }
-    for (int e = tid; e < n * n; e += CHOL_THREADS) {
-        int i = e % n, j = e / n;  // Rinv(i, j) = Linv(j, i)
-        Rinv[e] = (i <= j) ? s_l[j + n * i] : 0.0;
-    }
+    chol_body<CHOL_THREADS>(G, n, ldg, shift_rel, Rout, Rinv, flag);
 }
 
 hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, double *R,
@@ -366,25 +217,11 @@ hipError_t zero_words(void *p, int64_t nwords, hipStream_t s) {
     return hipGetLastError();
 }
 
-// Gaussian initial guess for ALS from a counter-based generator:
-// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) on the counter
-// (seed, mode, element), two uniforms -> Box-Muller.
-__device__ inline uint64_t splitmix64(uint64_t z) {
-    z += 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
+// Gaussian initial guess (ALS L_0, subspace-iteration start block).
 __global__ void gaussian_kernel(double *p, int64_t n, uint64_t seed, uint64_t stream) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
-    uint64_t base = splitmix64(seed ^ splitmix64(stream + 0x5851F42D4C957F2Dull));
-    uint64_t a = splitmix64(base + 2 * (uint64_t)e);
-    uint64_t b = splitmix64(base + 2 * (uint64_t)e + 1);
-    double u1 = ((a >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0, 1]
-    double u2 = (b >> 11) * (1.0 / 9007199254740992.0);           // [0, 1)
-    p[e] = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+    p[e] = gaussian_value(seed, stream, (uint64_t)e);
 }
 
 hipError_t gaussian_f64(double *p, int64_t n, uint64_t seed, uint64_t stream, hipStream_t s) {

@@ -1,0 +1,151 @@
+// Device body of the TTM kernel (one workgroup), shared by the single-tensor
+// kernel and the batched one.
+#pragma once
+#include "common.h"
+
+namespace sth {
+
+template <typename T, bool CONTIG>
+__device__ __forceinline__ void ttm_load_chunk(const T *__restrict__ Y, int64_t base, int64_t L,
+                                               int64_t K, int64_t kb, T (&x)[8]) {
+    // kb = first of this lane's 8 consecutive k
+    if (CONTIG && kb + 8 <= K) {
+        const T *src = Y + base + kb;
+        if constexpr (sizeof(T) == 4) {
+            float4 u = *reinterpret_cast<const float4 *>(src);
+            float4 w = *reinterpret_cast<const float4 *>(src + 4);
+            x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w;
+            x[4] = w.x; x[5] = w.y; x[6] = w.z; x[7] = w.w;
+        } else {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                double2 u = *reinterpret_cast<const double2 *>(src + 2 * h);
+                x[2 * h] = u.x;
+                x[2 * h + 1] = u.y;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            int64_t k = kb + j;
+            x[j] = (k < K) ? Y[base + L * k] : (T)0;
+        }
+    }
+}
+
+// Body of the TTM for one workgroup: wg of nwg workgroups sharing the row
+// blocks of this tensor, r-block rb.  Also used by the batched kernels.
+template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES>
+__device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *__restrict__ Uq,
+                                         T *__restrict__ Z, int64_t L, int64_t K, int64_t Rout,
+                                         int64_t P, int nchunks, int ntiles, int64_t nrowblocks,
+                                         int64_t wg, int64_t nwg, int rb) {
+    constexpr int NQ = Frag<PREC>::NQ;
+    typedef typename Acc<PREC>::type AccT;
+    extern __shared__ uint4 s_u[];
+
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int rt0 = rb * RTB;
+    const int rtn = min(RTB, ntiles - rt0);
+
+    if (ULDS) {
+        // stage this r-block's factor quads: [c][rt in block][q][lane]
+        const int per_chunk = RTB * NQ * 64;
+        const int total = nchunks * per_chunk;
+        for (int e = threadIdx.x; e < total; e += 64 * WAVES) {
+            int c = e / per_chunk;
+            int rem = e - c * per_chunk;  // (rtl * NQ + q) * 64 + lane
+            int rtl = rem / (NQ * 64);
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (rtl < rtn) v = Uq[((int64_t)c * ntiles + rt0) * NQ * 64 + rem];
+            s_u[e] = v;
+        }
+        __syncthreads();
+    }
+
+    const int64_t wstride = nwg * WAVES;
+    for (int64_t wb = wg * WAVES + wave; wb < nrowblocks; wb += wstride) {
+        const int64_t p0 = wb * (16 * NT);
+        int64_t base[NT];
+        int64_t zoff[NT];
+        bool pvalid[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            int64_t p = p0 + 16 * nt + (lane & 15);
+            pvalid[nt] = p < P;
+            int64_t pc = pvalid[nt] ? p : (P - 1);
+            int64_t a, b;
+            if (CONTIG) {
+                a = 0;
+                b = pc;
+            } else {
+                b = pc / L;
+                a = pc - b * L;
+            }
+            base[nt] = a + L * K * b;
+            zoff[nt] = a + L * Rout * b;
+        }
+        AccT acc[NT][RTB];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt) acc[nt][rt] = AccT{0, 0, 0, 0};
+
+        T nxt[NT][8];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, 8 * g, nxt[nt]);
+
+        for (int c = 0; c < nchunks; ++c) {
+            Frag<PREC> yb[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) make_frag(nxt[nt], yb[nt]);
+            if (c + 1 < nchunks) {
+                const int64_t kb = (int64_t)(c + 1) * KC + 8 * g;
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, kb, nxt[nt]);
+            }
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt) {
+                FragQ<PREC> ua;
+                if (ULDS) {
+                    const uint4 *src = s_u + ((c * RTB + rt) * NQ) * 64 + lane;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) ua.q[q] = src[q * 64];
+                } else {
+                    const int rtg = min(rt0 + rt, ntiles - 1);
+                    const uint4 *src = Uq + (((int64_t)c * ntiles + rtg) * NQ) * 64 + lane;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) ua.q[q] = src[q * 64];
+                }
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) mma_frag(ua.f, yb[nt], acc[nt][rt]);
+            }
+        }
+
+        // D[r][p]: lane holds r = 16*rt + drow(g, v), p = 16*nt + lane%16
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if (!pvalid[nt]) continue;
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt) {
+                const int64_t rbase = (int64_t)(rt0 + rt) * 16;
+                const int64_t r0 = rbase + 4 * g;
+                if (PREC != P_FP64 && CONTIG && sizeof(T) == 4 && (Rout & 3) == 0 && r0 + 4 <= Rout) {
+                    float4 v = make_float4((float)acc[nt][rt][0], (float)acc[nt][rt][1],
+                                           (float)acc[nt][rt][2], (float)acc[nt][rt][3]);
+                    *reinterpret_cast<float4 *>(Z + zoff[nt] + r0) = v;
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        int64_t r = rbase + drow<PREC>(g, v);
+                        if (r < Rout) Z[zoff[nt] + L * r] = (T)acc[nt][rt][v];
+                    }
+                }
+            }
+        }
+    }
+}
+
+}  // namespace sth

@@ -125,3 +125,18 @@ def test_entry_points_reject_bad_arguments_before_launch(lib):
                         ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), 1 << 20, None)
     assert st == _lib.STH_ERR_INVALID
     assert b"R" in lib.sth_last_error()
+
+
+def test_batched_plan_validation():
+    import workloads as wl
+    from paper_2010_10131_amd import api
+    from paper_2010_10131_amd._lib import SthError, STH_ERR_UNSUPPORTED, STH_ERR_INVALID
+    sh = wl.batch_shapes(16)
+    p = api.BatchPlan(sh)
+    assert p.count == 16 and p.workspace_bytes > 0
+    with pytest.raises(SthError) as e:
+        api.BatchPlan([((300, 20, 20), (100, 5, 5))])        # R_n > 64
+    assert e.value.status == STH_ERR_UNSUPPORTED
+    with pytest.raises(SthError) as e:
+        api.BatchPlan([((30, 20, 20), (5, 5, 5)), ((30, 20), (5, 5))])  # mixed orders
+    assert e.value.status == STH_ERR_INVALID

@@ -1,0 +1,93 @@
+"""Batched path: every tensor of a batch equals its single-tensor run and the
+FP64 oracle (T1/T2), and a HIP-graph capture of the batched run replays to
+the eager result bit for bit."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+# mixed shapes: first-mode I % 4 != 0, n <= 128 (Jacobi) and n > 128 (subspace
+# iteration), small and large ranks, a mode of size < 32
+SHAPES = [((40, 36, 33), (4, 5, 6)), ((37, 60, 50), (6, 8, 5)), ((130, 40, 35), (16, 6, 5)),
+          ((200, 150, 33), (30, 20, 5)), ((64, 256, 40), (10, 40, 8)), ((96, 96, 96), (12, 12, 12)),
+          ((33, 20, 150), (5, 3, 24)), ((250, 60, 32), (60, 9, 5))]
+
+
+@pytest.fixture(scope="module")
+def api():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    oracle.build()
+    from paper_2010_10131_amd import api as a
+    return a
+
+
+def make_batch(api, shapes, seed=5):
+    import torch
+    xs = [wl.lowrank_plus_noise(d, r, "none", 1e-4, seed + t, "float32") for t, (d, r) in enumerate(shapes)]
+    xd = [api.to_device(x) for x in xs]
+    xp = torch.tensor([x.data_ptr() for x in xd], dtype=torch.int64, device="cuda")
+    return xs, xd, xp
+
+
+def recon(api, G, U):
+    return oracle.reconstruct(api.to_numpy(G), [api.to_numpy(u) for u in U])
+
+
+@pytest.mark.parametrize("gp,tp", [("fp64", "fp32"), ("bf16x6", "bf16x3")])
+def test_batched_equals_single_and_oracle(api, gp, tp):
+    import torch
+    xs, xd, xp = make_batch(api, SHAPES)
+    plan = api.BatchPlan(SHAPES, gp, tp)
+    G, U, cp, up = plan.outputs()
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.run(xp, cp, up, ws)
+    plan.check(ws)
+    for t, (d, r) in enumerate(SHAPES):
+        Xh = recon(api, G[t], U[t])
+        Gs, Us, _ = api.sthosvd(xd[t], r, gp, tp)
+        Xs = recon(api, Gs, Us)
+        Go, Uo, _ = oracle.sthosvd(xs[t], r)
+        Xo = oracle.reconstruct(Go, Uo)
+        xn = np.linalg.norm(xs[t].astype(np.float64))
+        t2_single = np.linalg.norm(Xh - Xs) / xn
+        t2_oracle = np.linalg.norm(Xh - Xo) / xn
+        t1 = abs(np.linalg.norm(api.to_numpy(G[t])) - np.linalg.norm(Go)) / np.linalg.norm(Go)
+        assert t2_single <= 1e-5 and t2_oracle <= 1e-5 and t1 <= 1e-5, (t, d, r, t2_single, t2_oracle, t1)
+        for n in range(3):
+            u = api.to_numpy(U[t][n])
+            np.testing.assert_allclose(u.T @ u, np.eye(r[n]), atol=1e-10)
+
+
+def test_batched_graph_replay_is_deterministic(api):
+    import torch
+    shapes = SHAPES[:5]
+    xs, xd, xp = make_batch(api, shapes, seed=11)
+    plan = api.BatchPlan(shapes, "bf16x6", "bf16x3")
+    G, U, cp, up = plan.outputs()
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.run(xp, cp, up, ws)          # eager reference (also warms up kernels)
+    torch.cuda.synchronize()
+    ref_G = [g.clone() for g in G]
+    ref_U = [[u.clone() for u in us] for us in U]
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            plan.run(xp, cp, up, ws)
+    torch.cuda.current_stream().wait_stream(s)
+    for rep in range(3):
+        for g in G:
+            g.zero_()                 # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for t in range(len(shapes)):
+            assert torch.equal(G[t], ref_G[t]), (rep, t)
+            for n in range(3):
+                assert torch.equal(U[t][n], ref_U[t][n]), (rep, t, n)
