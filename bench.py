@@ -2,7 +2,9 @@
 
 One step = one whole decomposition (Alg. 2: Gram, FP64 eigensolver and TTM
 for each of the 3 modes) of the resident input, through sthosvd_run.
-Prints one JSON line (see the design doc for every field).
+Prints one JSON line: the headline figures, every precision recipe's time and
+error against the FP64 oracle, the mode-1 TTM roofline, the oracle's own time
+on the host cores, and the batched workload.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -44,10 +46,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--ttm-reps", type=int, default=20)
+    ap.add_argument("--batch", type=int, default=256,
+                    help="tensors in the batched measurement (0 skips it)")
+    ap.add_argument("--batch-reps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
-              "sharding is described in DESIGN.md but not built.", file=sys.stderr)
+              "sharding across GPUs is not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -148,6 +153,10 @@ def main():
     ttm_gbs = ttm_bytes / (ttm_ms * 1e-3) / 1e9
     log(f"[bench] ttm mode-1 {ttm_ms * 1e3:.1f} us, {ttm_gbs:.0f} GB/s")
 
+    batched = None
+    if args.batch > 0:
+        batched = bench_batched(args, api, torch, dev, gp, tp)
+
     fp32_ms = results[fp32_name]["ms"]
     out = {
         "metric": "st-HOSVD wall time & TTM HBM GB/s: mixed-precision vs FP32 at equal rel. error",
@@ -174,8 +183,80 @@ def main():
                      "achieved": ttm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ttm_gbs / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out))
+
+
+def bench_batched(args, api, torch, dev, gp, tp):
+    """Many small 3-way tensors (sides 32..256, ranks 10-25 %) decomposed by one
+    batched plan, replayed from a captured HIP graph, against the same tensors
+    run one after another through single-tensor plans."""
+    t0 = time.time()
+    shapes, xs = wl.batch_tensors(args.batch, workers=min(16, os.cpu_count() or 1))
+    log(f"[bench] generated batch of {len(xs)} in {time.time() - t0:.1f}s")
+    xd = [api.to_device(x, dev) for x in xs]
+    nbytes = sum(x.nbytes for x in xs)
+    del xs
+    xp = torch.tensor([x.data_ptr() for x in xd], dtype=torch.int64, device=dev)
+    from paper_2010_10131_amd import autotune
+    t0 = time.time()
+    tiles, tuned_ms, table = autotune.tune_batched(shapes, xp, gp, tp, reps=2, device=dev)
+    default_ms = table[0]["ms"]
+    log(f"[bench] autotuned batch tiles {tiles}: {tuned_ms:.2f} ms (default {default_ms:.2f} ms), "
+        f"{len(table)} candidates in {time.time() - t0:.1f}s")
+    plan = api.BatchPlan(shapes, gp, tp, tiles=tiles)
+    G, U, cp, up = plan.outputs(dev)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    plan.run(xp, cp, up, ws)
+    plan.check(ws)
+    torch.cuda.synchronize()
+
+    graph = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(graph, stream=s):
+            plan.run(xp, cp, up, ws)
+    torch.cuda.current_stream().wait_stream(s)
+    graph.replay()
+    torch.cuda.synchronize()
+    plan.check(ws)
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t) * 1e3 / args.batch_reps
+
+    t = time.perf_counter()
+    for _ in range(args.batch_reps):
+        plan.run(xp, cp, up, ws)
+    torch.cuda.synchronize()
+    eager_ms = (time.perf_counter() - t) * 1e3 / args.batch_reps
+    del graph
+
+    # one tensor at a time through sthosvd_run
+    plans = [api.Plan(d, r, torch.float32, gp, tp, "eig") for d, r in shapes]
+    ws1 = torch.empty(max(p.workspace_bytes for p in plans), dtype=torch.uint8, device=dev)
+
+    def seq():
+        for k, p in enumerate(plans):
+            p.run(xd[k], G[k], U[k], ws1)
+    seq()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(max(1, args.batch_reps // 2)):
+        seq()
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t) * 1e3 / max(1, args.batch_reps // 2)
+    log(f"[bench] batch of {len(shapes)}: graph {graph_ms:.2f} ms, eager {eager_ms:.2f} ms, "
+        f"one-by-one {seq_ms:.2f} ms")
+    return {"workload": f"batch{len(shapes)}_3way_32to256_fp32", "tensors": len(shapes),
+            "input_bytes": nbytes, "graph_ms": graph_ms, "eager_ms": eager_ms,
+            "sequential_ms": seq_ms, "tensors_per_s": len(shapes) / (graph_ms * 1e-3),
+            "speedup_vs_sequential": seq_ms / graph_ms, "recipe": {"gram": gp, "ttm": tp},
+            "tiles": {"gram_wg_per_cu": tiles[0], "gram_wt_max": tiles[1], "ttm_rows_per_wave": tiles[2]},
+            "eager_default_tiles_ms": default_ms, "autotune": table}
 
 
 if __name__ == "__main__":

@@ -144,14 +144,37 @@ sth_status sthosvd_check(const sth_plan *plan, void *workspace, sth_stream_t str
 
 /* ---------------------------------------------------------------------------
  * Batched decomposition: count independent FP32 tensors of one order, EIG
- * branch in mode order 1..N, every R_n <= 64 (spec batching pattern;
- * each tensor follows Alg. 2 exactly as a single run would).  One launch per
- * phase of a mode step covers the whole batch; the run is enqueue-only and
- * may be captured in a HIP graph.  The plan owns pinned host memory holding
- * the shape/offset tables (copied into the workspace by every run).
+ * branch in mode order 1..N, every R_n <= 64 (each tensor follows Alg. 2
+ * exactly as a single run would).  One launch per phase of a mode step
+ * covers the whole batch; the run is enqueue-only and may be captured in a
+ * HIP graph.  The plan owns pinned host memory holding the shape/offset
+ * tables (copied into the workspace by every run).
  * ------------------------------------------------------------------------- */
 sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count, sth_batch_plan **plan,
                                 size_t *workspace_bytes);
+
+/* Tile choices of the batched kernels; a zero field takes its default.  They
+ * change the work split only: the TTM results are bit-identical for every
+ * choice, the Gram's split-K depth changes the order of its FP64 partial
+ * sums (results agree to rounding).
+ *   gram_wg_per_cu    Gram workgroups aimed at per compute unit over the
+ *                     whole batch (split-K depth), 1..64, default 4
+ *   gram_wt_max       largest Gram output tile, in units of 32 rows: 1, 2
+ *                     or 4, default 4
+ *   ttm_rows_per_wave TTM row blocks per wave of a workgroup, 1..64,
+ *                     default 4 */
+typedef struct sth_batch_tiles {
+    int32_t gram_wg_per_cu;
+    int32_t gram_wt_max;
+    int32_t ttm_rows_per_wave;
+    int32_t reserved; /* must be 0 */
+} sth_batch_tiles;
+
+/* sthosvd_plan_batched with explicit tile choices (tiles may be NULL: the
+ * defaults).  STH_ERR_INVALID for an out-of-range field. */
+sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t count,
+                                      const sth_batch_tiles *tiles, sth_batch_plan **plan,
+                                      size_t *workspace_bytes);
 void sthosvd_plan_batched_destroy(sth_batch_plan *plan);
 /* X_dev: device array of count device pointers to the inputs; core_dev:
  * device array of count device pointers to the cores; U_dev: device array of

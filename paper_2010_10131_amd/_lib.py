@@ -27,6 +27,15 @@ class SthError(RuntimeError):
         self.status = status
 
 
+class sth_batch_tiles(ctypes.Structure):
+    _fields_ = [
+        ("gram_wg_per_cu", ctypes.c_int32),
+        ("gram_wt_max", ctypes.c_int32),
+        ("ttm_rows_per_wave", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
 class sth_desc(ctypes.Structure):
     _fields_ = [
         ("order", ctypes.c_int32),
@@ -79,6 +88,9 @@ SIGNATURES = {
                                          _vp, _vp, _vp, ctypes.c_uint64, _vp, _sz, _vp]),
     "sthosvd_plan_batched": (ctypes.c_int, [ctypes.POINTER(sth_desc), _i32, ctypes.POINTER(_vp),
                                             ctypes.POINTER(_sz)]),
+    "sthosvd_plan_batched_tiles": (ctypes.c_int, [ctypes.POINTER(sth_desc), _i32,
+                                                  ctypes.POINTER(sth_batch_tiles), ctypes.POINTER(_vp),
+                                                  ctypes.POINTER(_sz)]),
     "sthosvd_plan_batched_destroy": (None, [_vp]),
     "sthosvd_run_batched": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _sz, _vp]),
     "sthosvd_check_batched": (ctypes.c_int, [_vp, _vp, _vp]),

@@ -401,8 +401,11 @@ def mlp_adam(params, grad, m, v, count: int, lr: float, step: int, beta1=0.9, be
 class BatchPlan:
     """sthosvd_plan_batched over a list of (dims, ranks) of FP32 tensors."""
 
-    def __init__(self, shapes, gram_prec="bf16x6", ttm_prec="bf16x3", eig_max_sweeps: int = 0):
+    def __init__(self, shapes, gram_prec="bf16x6", ttm_prec="bf16x3", eig_max_sweeps: int = 0,
+                 tiles=None):
+        """tiles: None (defaults) or (gram_wg_per_cu, gram_wt_max, ttm_rows_per_wave)."""
         L = _lib.load()
+        self.tiles = tuple(int(v) for v in tiles) if tiles is not None else None
         self.shapes = [([int(x) for x in d], [int(x) for x in r]) for d, r in shapes]
         self.count = len(self.shapes)
         self.N = len(self.shapes[0][0])
@@ -421,7 +424,11 @@ class BatchPlan:
             descs[t].eig_max_sweeps = int(eig_max_sweeps)
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
-        check(L.sthosvd_plan_batched(descs, self.count, ctypes.byref(h), ctypes.byref(ws)))
+        tl = None
+        if self.tiles is not None:
+            tl = _lib.sth_batch_tiles(*self.tiles, 0)
+        check(L.sthosvd_plan_batched_tiles(descs, self.count, ctypes.byref(tl) if tl is not None else None,
+                                           ctypes.byref(h), ctypes.byref(ws)))
         self._h = h
         self.workspace_bytes = int(ws.value)
 

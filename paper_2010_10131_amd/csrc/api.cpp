@@ -760,8 +760,28 @@ struct sth_batch_plan_s {
 
 extern "C" sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count, sth_batch_plan **out,
                                            size_t *ws_out) {
+    return sthosvd_plan_batched_tiles(descs, count, nullptr, out, ws_out);
+}
+
+extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t count,
+                                                 const sth_batch_tiles *tiles, sth_batch_plan **out,
+                                                 size_t *ws_out) {
     if (!descs || !out || !ws_out || count < 1) return fail(STH_ERR_INVALID, "bad batched arguments");
     *out = nullptr;
+    sth_batch_tiles tile = {4, 4, 4, 0};
+    if (tiles) {
+        if (tiles->reserved != 0) return fail(STH_ERR_INVALID, "tiles.reserved must be 0");
+        if (tiles->gram_wg_per_cu < 0 || tiles->gram_wg_per_cu > 64)
+            return fail(STH_ERR_INVALID, "tiles.gram_wg_per_cu = %d out of 0..64", tiles->gram_wg_per_cu);
+        if (tiles->gram_wt_max != 0 && tiles->gram_wt_max != 1 && tiles->gram_wt_max != 2 &&
+            tiles->gram_wt_max != 4)
+            return fail(STH_ERR_INVALID, "tiles.gram_wt_max = %d is not 0, 1, 2 or 4", tiles->gram_wt_max);
+        if (tiles->ttm_rows_per_wave < 0 || tiles->ttm_rows_per_wave > 64)
+            return fail(STH_ERR_INVALID, "tiles.ttm_rows_per_wave = %d out of 0..64", tiles->ttm_rows_per_wave);
+        if (tiles->gram_wg_per_cu) tile.gram_wg_per_cu = tiles->gram_wg_per_cu;
+        if (tiles->gram_wt_max) tile.gram_wt_max = tiles->gram_wt_max;
+        if (tiles->ttm_rows_per_wave) tile.ttm_rows_per_wave = tiles->ttm_rows_per_wave;
+    }
     const sth_desc &d0 = descs[0];
     sth_status st;
     for (int t = 0; t < count; ++t) {
@@ -788,7 +808,7 @@ extern "C" sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count,
     p->gram_prec = d0.gram_prec;
     p->ttm_prec = d0.ttm_prec;
     p->max_sweeps = d0.eig_max_sweeps ? d0.eig_max_sweeps : 60;
-    const int64_t target = std::max<int64_t>(1, 4 * (int64_t)device_cu_count() / count);
+    const int64_t target = std::max<int64_t>(1, (int64_t)tile.gram_wg_per_cu * device_cu_count() / count);
 
     // per tensor regions and per step descriptors
     Arena a;
@@ -809,7 +829,7 @@ extern "C" sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count,
             if (s < N - 1) (s % 2 == 0 ? maxA : maxB) = std::max(s % 2 == 0 ? maxA : maxB, out);
             int wt, nbi, nbj, nblocks, nkc;
             int64_t kper;
-            gram_geometry(b.I, b.I, P, true, target, &wt, &nbi, &nbj, &nblocks, &nkc, &kper);
+            gram_geometry(b.I, b.I, P, true, target, tile.gram_wt_max, &wt, &nbi, &nbj, &nblocks, &nkc, &kper);
             b.wt = wt;
             b.nbi = nbi;
             b.nblocks = nblocks;
@@ -890,7 +910,8 @@ extern "C" sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count,
                     const int nt = (cls == 1) ? 4 : 2;
                     const int64_t rows = (b.L * b.M + 16 * nt - 1) / (16 * nt);
                     tl.push_back(t);
-                    tw.push_back(std::max<int64_t>(1, (rows + BT_WAVES * 4 - 1) / (BT_WAVES * 4)));
+                    const int64_t per_wg = (int64_t)BT_WAVES * tile.ttm_rows_per_wave;
+                    tw.push_back(std::max<int64_t>(1, (rows + per_wg - 1) / per_wg));
                 }
             if (!tl.empty()) T.ttm.push_back(make(tl, tw, cls));
         }

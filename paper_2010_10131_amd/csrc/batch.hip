@@ -24,7 +24,7 @@ namespace sth {
 constexpr int BE_THREADS = 512;  // batched eigen workgroup (matches the Jacobi body)
 // LDS for Jacobi's A and V in the batched kernel, which also holds the
 // Cholesky body's static LDS
-constexpr int BATCH_LDS_AV = 140 * 1024;
+constexpr int BATCH_LDS_AV = 150 * 1024;
 
 __device__ __forceinline__ int find_segment(const int64_t *__restrict__ pref, int len, int64_t x) {
     // largest k with pref[k] <= x (pref[0] = 0, pref[len] = total)
@@ -184,10 +184,10 @@ __global__ __launch_bounds__(BE_THREADS) void batch_eig_kernel(const BatchStep *
     double *U = Up[(int64_t)d.tensor * order + mode];
     double *scr = (double *)(ws + d.eig_off);
     if (n <= EIG_DIRECT_MAX) {
-        if (2 * n * n * 8 <= BATCH_LDS_AV)
-            jacobi_body<true, true>(S, n, R, scr, scr + n * n, U, nullptr, tol, max_sweeps, flag);
+        if (jacobi_small_lds(n, true) <= (size_t)BATCH_LDS_AV)
+            jacobi_small_body<true>(S, n, R, scr, U, nullptr, tol, max_sweeps, flag);
         else
-            jacobi_body<true, false>(S, n, R, scr, scr + n * n, U, nullptr, tol, max_sweeps, flag);
+            jacobi_small_body<false>(S, n, R, scr, U, nullptr, tol, max_sweeps, flag);
         return;
     }
     const int p = (int)si_block_dev(n, R);
@@ -203,10 +203,10 @@ __global__ __launch_bounds__(BE_THREADS) void batch_eig_kernel(const BatchStep *
     }
     wg_gemm(0, 0, n, p, n, S, n, Q, n, Z, n);
     wg_gemm(1, 0, p, p, n, Q, n, Z, n, T, p);
-    if (2 * p * p * 8 <= BATCH_LDS_AV)
-        jacobi_body<true, true>(T, p, R, jac, jac + p * p, W, nullptr, tol, max_sweeps, flag);
+    if (jacobi_small_lds(p, true) <= (size_t)BATCH_LDS_AV)
+        jacobi_small_body<true>(T, p, R, jac, W, nullptr, tol, max_sweeps, flag);
     else
-        jacobi_body<true, false>(T, p, R, jac, jac + p * p, W, nullptr, tol, max_sweeps, flag);
+        jacobi_small_body<false>(T, p, R, jac, W, nullptr, tol, max_sweeps, flag);
     __syncthreads();
     wg_gemm(0, 0, n, R, p, Q, n, W, p, U, n);
     // sign rule on the columns of U
@@ -290,12 +290,12 @@ size_t batch_gram_lds(int prec, int wt) {
 
 size_t batch_eig_lds(int64_t n, int64_t R) {
     auto jac = [](int64_t m) -> size_t {
-        const size_t mat = (size_t)m * m * 8;
-        return (2 * mat <= (size_t)BATCH_LDS_AV) ? 2 * mat : mat;
+        const size_t both = jacobi_small_lds(m, true);
+        return both <= (size_t)BATCH_LDS_AV ? both : jacobi_small_lds(m, false);
     };
     if (n <= EIG_DIRECT_MAX) return jac(n);
     const int64_t p = si_block_host(n, R);
-    return std::max({jac(p), (size_t)(p * p + p * 16) * 8, (size_t)2 * 32 * 33 * 8});
+    return std::max({jac(p), chol_lds_bytes(p), (size_t)2 * 32 * 33 * 8});
 }
 
 size_t batch_eig_scratch(int64_t n, int64_t R) {

@@ -7,7 +7,7 @@
 namespace sth {
 
 // One workgroup of NTH threads, n <= 128, everything in LDS (dynamic LDS of
-// (n * n + n * CB) doubles).
+// chol_lds_bytes(n)).
 // G (n x n, symmetric, ldg) + shift_rel * trace(G) / n * I = L L^T, blocked
 // right-looking Cholesky with 16-column panels: the diagonal block is
 // factored by one wave in registers (row i of the block in lane i, columns
@@ -20,12 +20,17 @@ namespace sth {
 // positive one so that the run continues.
 constexpr int CB = 16;
 
+// Dynamic LDS of chol_body: L (n x n), the panel buffer (n x CB) and the
+// reciprocals of the diagonal of L (n).
+__host__ __device__ inline size_t chol_lds_bytes(int64_t n) { return (size_t)(n * n + n * CB + n) * 8; }
+
 template <int CHOL_THREADS>
 __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, int64_t ldg,
                                           double shift_rel, double *__restrict__ Rout,
                                           double *__restrict__ Rinv, int64_t *__restrict__ flag) {
     extern __shared__ double s_l[];  // L, column-major, leading dimension n; then T (n x CB)
     double *s_tmp = s_l + n * n;
+    double *s_rd = s_tmp + n * CB;    // 1 / L(i, i)
     __shared__ double s_dinv[CB * CB];
     __shared__ double s_tr;
     const int tid = threadIdx.x;
@@ -34,10 +39,13 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
         int i = e % n, j = e / n;
         s_l[e] = (i >= j) ? G[i + ldg * j] : 0.0;
     }
-    if (tid == 0) {
+    __syncthreads();
+    if (wave == 0) {
+        // trace, reduced across one wave from the copy in LDS
         double t = 0.0;
-        for (int i = 0; i < n; ++i) t += G[i + ldg * i];
-        s_tr = t;
+        for (int i = lane; i < n; i += 64) t += s_l[i + n * i];
+        for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+        if (lane == 0) s_tr = t;
     }
     __syncthreads();
     if (shift_rel != 0.0) {
@@ -68,8 +76,13 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
                         d = tiny;
                     }
                     d = sqrt(d);
-                    if (lane == j) row[j] = d;
-                    else if (lane > j) row[j] = sacc / d;
+                    const double rd = 1.0 / d;
+                    if (lane == j) {
+                        row[j] = d;
+                        s_rd[k0 + j] = rd;
+                    } else if (lane > j) {
+                        row[j] = sacc * rd;
+                    }
                 }
             }
             if (lane < kn)
@@ -88,7 +101,7 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
 #pragma unroll
                     for (int d = 0; d < CB; ++d)
                         if (d < c) sacc -= x[d] * s_l[k0 + c + n * (k0 + d)];
-                    x[c] = sacc / s_l[k0 + c + n * (k0 + c)];
+                    x[c] = sacc * s_rd[k0 + c];
                 }
             }
 #pragma unroll
@@ -131,7 +144,7 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
 #pragma unroll
                     for (int d = 0; d < CB; ++d)
                         if (d < r) sacc -= s_l[k0 + r + n * (k0 + d)] * x[d];
-                    x[r] = (r < c) ? 0.0 : sacc / s_l[k0 + r + n * (k0 + r)];
+                    x[r] = (r < c) ? 0.0 : sacc * s_rd[k0 + r];
                 }
             }
 #pragma unroll

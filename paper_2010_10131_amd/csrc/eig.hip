@@ -2,7 +2,7 @@
 // eigenvectors of the mode-n Gram matrix.
 //
 // Two-sided cyclic Jacobi with a parallel (round-robin tournament) ordering,
-// run by one 1024-thread workgroup.  In every round the n/2 disjoint
+// run by one 512-thread workgroup.  In every round the n/2 disjoint
 // rotations are computed first; then A <- J^T A J is applied block-wise
 // (each thread transforms whole 2x2 blocks (pair I, pair J), which are
 // independent within a round) and V <- V J.  After each sweep the
@@ -28,6 +28,16 @@ __global__ __launch_bounds__(EIG_THREADS) void jacobi_kernel(const double *__res
                                                              int max_sweeps,
                                                              int64_t *__restrict__ flag) {
     jacobi_body<ALDS, VLDS>(S, n, R, Ag, Vg, U, lam, tol, max_sweeps, flag);
+}
+
+template <bool VLDS>
+__global__ __launch_bounds__(EIG_THREADS) void jacobi_small_kernel(const double *__restrict__ S, int n,
+                                                                   int R, double *__restrict__ Vg,
+                                                                   double *__restrict__ U,
+                                                                   double *__restrict__ lam, double tol,
+                                                                   int max_sweeps,
+                                                                   int64_t *__restrict__ flag) {
+    jacobi_small_body<VLDS>(S, n, R, Vg, U, lam, tol, max_sweeps, flag);
 }
 
 // Sign rule on the columns of an n x R matrix: the entry of largest
@@ -130,8 +140,19 @@ hipError_t jacobi_launch(int64_t n, int64_t R, const double *S, double *U, doubl
     double *Ag = (double *)((char *)ws + 256);
     double *Vg = Ag + n * n;
     const size_t mat = (size_t)n * n * sizeof(double);
-    const size_t budget = 150 * 1024;
-    if (2 * mat <= budget) {
+    const size_t budget = EIG_LDS_AV;
+    if (n <= 2 * JS_MAXM) {
+        // A in LDS; V too when both fit (V in the workspace otherwise)
+        const bool vl = jacobi_small_lds(n, true) <= budget;
+        const size_t lds = jacobi_small_lds(n, vl);
+        if (vl) {
+            hipFuncSetAttribute((const void *)jacobi_small_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(jacobi_small_kernel<true>, dim3(1), dim3(EIG_THREADS), lds, s, S, (int)n, (int)R, Ag, U, lam, tol, max_sweeps, flag);
+        } else {
+            hipFuncSetAttribute((const void *)jacobi_small_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            hipLaunchKernelGGL(jacobi_small_kernel<false>, dim3(1), dim3(EIG_THREADS), lds, s, S, (int)n, (int)R, Ag, U, lam, tol, max_sweeps, flag);
+        }
+    } else if (2 * mat <= budget) {
         auto k = jacobi_kernel<true, true>;
         hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * mat));
         hipLaunchKernelGGL(k, dim3(1), dim3(EIG_THREADS), 2 * mat, s, S, (int)n, (int)R, Ag, Vg, U, lam, tol, max_sweeps, flag);

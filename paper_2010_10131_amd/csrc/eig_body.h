@@ -29,6 +29,217 @@ __device__ __forceinline__ int rr_player(int x, int r, int ne) {
     return y + 1;
 }
 
+// ------------------------------------------------------------------------
+// Small matrices (n <= 128, at most JS_MAXM pairs per round).  The same
+// parallel round-robin sweep as jacobi_body, with A padded to an even order
+// ne (a zero row and column: the odd player's partner, whose rotation is the
+// identity, so no bound tests in the update) and a fixed work split computed
+// once: a thread owns row-pair I = tid % m of A for a stride of column pairs,
+// and row tid % n of V for a stride of column pairs.  The arithmetic of every
+// rotation and update is the one of jacobi_body.
+constexpr int JS_MAXM = 64;
+constexpr int JS_KA = JS_MAXM / (EIG_THREADS / JS_MAXM);        // A blocks per thread
+constexpr int JS_KV = JS_MAXM / (EIG_THREADS / (2 * JS_MAXM));  // V pairs per thread
+constexpr int JS_CA = 4;  // A blocks whose loads are issued together
+constexpr int JS_CV = 8;  // V pairs whose loads are issued together
+
+// Dynamic LDS of jacobi_small_body: A (ne x ne) and, when v_lds, V (n x ne).
+__host__ __device__ inline size_t jacobi_small_lds(int64_t n, bool v_lds) {
+    const int64_t ne = n + (n & 1);
+    return (size_t)(ne * ne + (v_lds ? n * ne : 0)) * 8;
+}
+// Global V (when not in LDS) needs n * ne doubles.
+__host__ __device__ inline size_t jacobi_small_vg(int64_t n) { return (size_t)(n * (n + (n & 1))) * 8; }
+
+template <bool VLDS>
+__device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, int n, int R,
+                                                  double *__restrict__ Vg, double *__restrict__ U,
+                                                  double *__restrict__ lam, double tol,
+                                                  int max_sweeps, int64_t *__restrict__ flag) {
+    extern __shared__ double s_e[];
+    __shared__ double s_c[JS_MAXM], s_s[JS_MAXM];
+    __shared__ int s_p[JS_MAXM], s_q[JS_MAXM];
+    __shared__ double s_red[2][EIG_THREADS / 64];
+    __shared__ int s_sel[2 * JS_MAXM];
+    __shared__ double s_sign[2 * JS_MAXM];
+    __shared__ int s_stop;
+
+    const int ne = n + (n & 1), m = ne / 2;
+    double *A = s_e;                         // ne x ne, leading dimension ne
+    double *V = VLDS ? s_e + ne * ne : Vg;   // n x ne, leading dimension n
+    const int tid = threadIdx.x;
+    for (int e = tid; e < ne * ne; e += EIG_THREADS) {
+        const int i = e % ne, j = e / ne;
+        A[e] = (i < n && j < n) ? 0.5 * (S[i + n * j] + S[j + n * i]) : 0.0;
+    }
+    for (int e = tid; e < n * ne; e += EIG_THREADS) {
+        const int i = e % n, j = e / n;
+        V[e] = (i == j) ? 1.0 : 0.0;
+    }
+    const int ja = EIG_THREADS / m, Ia = tid % m, ja0 = tid / m;
+    const int jv = EIG_THREADS / n, rv = tid % n, jv0 = tid / n;
+    __syncthreads();
+
+    int sweep = 0;
+    bool converged = false;
+    double prev_off2 = -1.0;
+    for (;;) {
+        double off = 0.0, fro = 0.0;
+        for (int j = 0; j < n; ++j)
+            for (int i = tid; i < n; i += EIG_THREADS) {
+                const double v = A[i + ne * j];
+                fro += v * v;
+                if (i != j) off += v * v;
+            }
+        for (int o = 32; o > 0; o >>= 1) {
+            off += __shfl_xor(off, o);
+            fro += __shfl_xor(fro, o);
+        }
+        if ((tid & 63) == 0) {
+            s_red[0][tid >> 6] = off;
+            s_red[1][tid >> 6] = fro;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double o2 = 0.0, f2 = 0.0;
+            for (int w = 0; w < EIG_THREADS / 64; ++w) {
+                o2 += s_red[0][w];
+                f2 += s_red[1][w];
+            }
+            int stop = 0;
+            if (o2 <= tol * tol * f2 || o2 == 0.0) stop = 1;
+            else if (o2 <= (double)n * n * 1.2e-32 * f2 && prev_off2 >= 0.0 && o2 >= 0.25 * prev_off2) stop = 1;
+            else if (sweep >= max_sweeps) stop = 2;
+            s_stop = stop;
+            s_red[0][0] = o2;
+        }
+        __syncthreads();
+        if (s_stop) {
+            converged = (s_stop == 1);
+            break;
+        }
+        prev_off2 = s_red[0][0];
+        for (int r = 0; r < ne - 1; ++r) {
+            if (tid < m) {
+                int p = rr_player(tid, r, ne), q = rr_player(ne - 1 - tid, r, ne);
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                double c = 1.0, sn = 0.0;
+                const double apq = A[p + ne * q];
+                if (apq != 0.0) {
+                    const double app = A[p + ne * p], aqq = A[q + ne * q];
+                    const double theta = (aqq - app) / (2.0 * apq);
+                    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    sn = t * c;
+                }
+                s_p[tid] = p;
+                s_q[tid] = q;
+                s_c[tid] = c;
+                s_s[tid] = sn;
+            }
+            __syncthreads();
+            if (ja0 < ja) {
+                const int pI = s_p[Ia], qI = s_q[Ia];
+                const double ci = s_c[Ia], si = s_s[Ia];
+#pragma unroll 1
+                for (int k0 = 0; k0 < JS_KA; k0 += JS_CA) {
+                int pj[JS_CA], qj[JS_CA];
+                double a[JS_CA][4];
+#pragma unroll
+                for (int k = 0; k < JS_CA; ++k) {
+                    const int J = ja0 + (k0 + k) * ja;
+                    if (J < m) {
+                        pj[k] = ne * s_p[J];
+                        qj[k] = ne * s_q[J];
+                        a[k][0] = A[pI + pj[k]];
+                        a[k][1] = A[pI + qj[k]];
+                        a[k][2] = A[qI + pj[k]];
+                        a[k][3] = A[qI + qj[k]];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < JS_CA; ++k) {
+                    const int J = ja0 + (k0 + k) * ja;
+                    if (J < m) {
+                        const double cj = s_c[J], sj = s_s[J];
+                        const double b00 = ci * a[k][0] - si * a[k][2], b01 = ci * a[k][1] - si * a[k][3];
+                        const double b10 = si * a[k][0] + ci * a[k][2], b11 = si * a[k][1] + ci * a[k][3];
+                        A[pI + pj[k]] = cj * b00 - sj * b01;
+                        A[pI + qj[k]] = sj * b00 + cj * b01;
+                        A[qI + pj[k]] = cj * b10 - sj * b11;
+                        A[qI + qj[k]] = sj * b10 + cj * b11;
+                    }
+                }
+                }
+            }
+            if (jv0 < jv) {
+#pragma unroll 1
+                for (int k0 = 0; k0 < JS_KV; k0 += JS_CV) {
+                int pj[JS_CV], qj[JS_CV];
+                double vp[JS_CV], vq[JS_CV];
+#pragma unroll
+                for (int k = 0; k < JS_CV; ++k) {
+                    const int J = jv0 + (k0 + k) * jv;
+                    if (J < m) {
+                        pj[k] = rv + n * s_p[J];
+                        qj[k] = rv + n * s_q[J];
+                        vp[k] = V[pj[k]];
+                        vq[k] = V[qj[k]];
+                    }
+                }
+#pragma unroll
+                for (int k = 0; k < JS_CV; ++k) {
+                    const int J = jv0 + (k0 + k) * jv;
+                    if (J < m) {
+                        const double cj = s_c[J], sj = s_s[J];
+                        V[pj[k]] = cj * vp[k] - sj * vq[k];
+                        V[qj[k]] = sj * vp[k] + cj * vq[k];
+                    }
+                }
+                }
+            }
+            __syncthreads();
+        }
+        ++sweep;
+    }
+    if (!converged && tid == 0 && flag) flag[0] = 1;
+
+    // descending order of the diagonal, ties by index
+    for (int i = tid; i < n; i += EIG_THREADS) {
+        const double li = A[i + ne * i];
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[j + ne * j];
+            rank += (lj > li) || (lj == li && j < i);
+        }
+        if (rank < R) s_sel[rank] = i;
+    }
+    __syncthreads();
+    for (int r = tid; r < R; r += EIG_THREADS) {
+        const int col = s_sel[r];
+        int arg = 0;
+        double best = fabs(V[n * col]);
+        for (int i = 1; i < n; ++i) {
+            const double v = fabs(V[i + n * col]);
+            if (v > best) {
+                best = v;
+                arg = i;
+            }
+        }
+        s_sign[r] = V[arg + n * col] < 0 ? -1.0 : 1.0;
+        if (lam) lam[r] = A[col + ne * col];
+    }
+    __syncthreads();
+    for (int e = tid; e < n * R; e += EIG_THREADS) {
+        const int i = e % n, r = e / n;
+        U[e] = s_sign[r] * V[i + n * s_sel[r]];
+    }
+}
+
 template <bool ALDS, bool VLDS>
 __device__ __forceinline__ void jacobi_body(const double *__restrict__ S, int n, int R,
                                             double *__restrict__ Ag, double *__restrict__ Vg,

@@ -85,16 +85,16 @@ struct GramShape {
     int64_t kper;
 };
 
-GramShape gram_shape_t(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target);
+GramShape gram_shape_t(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int wt_max);
 
 GramShape gram_shape(int64_t IA, int64_t IB, int64_t P, bool sym) {
-    return gram_shape_t(IA, IB, P, sym, 2 * (int64_t)device_cu_count());
+    return gram_shape_t(IA, IB, P, sym, 2 * (int64_t)device_cu_count(), 4);
 }
 
-GramShape gram_shape_t(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target) {
+GramShape gram_shape_t(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int wt_max) {
     GramShape g;
     int64_t imax = std::max(IA, IB);
-    g.wt = imax > 64 ? 4 : (imax > 32 ? 2 : 1);
+    g.wt = std::min(wt_max, imax > 64 ? 4 : (imax > 32 ? 2 : 1));
     g.tb = 32 * g.wt;
     g.nbi = (int)((IA + g.tb - 1) / g.tb);
     g.nbj = (int)((IB + g.tb - 1) / g.tb);
@@ -188,9 +188,9 @@ hipError_t launch_gram_d(int dtype, int prec, const void *A, const void *B, int6
 
 }  // namespace
 
-void gram_geometry(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int *wt, int *nbi,
-                   int *nbj, int *nblocks, int *nkc, int64_t *kper) {
-    GramShape g = gram_shape_t(IA, IB, P, sym, target);
+void gram_geometry(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int wt_max, int *wt,
+                   int *nbi, int *nbj, int *nblocks, int *nkc, int64_t *kper) {
+    GramShape g = gram_shape_t(IA, IB, P, sym, target, wt_max);
     *wt = g.wt;
     *nbi = g.nbi;
     *nbj = g.nbj;
@@ -209,7 +209,7 @@ hipError_t gram_launch(int dtype, int prec, const void *A, const void *B, int64_
                        hipStream_t s) {
     const int64_t P = L * M;
     if (P == 0) {
-        return hipMemsetAsync(S, 0, sizeof(double) * IA * IB, s);
+        return fill_f64(S, IA * IB, 0.0, s);  // a kernel, so that the call stays graph-capturable
     }
     GramShape g = gram_shape(IA, IB, P, sym);
     if (sym) return launch_gram_d<true>(dtype, prec, A, A, L, IA, IA, M, g, partials, S, s);

@@ -50,9 +50,10 @@ hipError_t copy_f64(const double *src, double *dst, int64_t n, hipStream_t s);
 hipError_t zero_words(void *p, int64_t nwords, hipStream_t s);
 hipError_t gaussian_f64(double *p, int64_t n, uint64_t seed, uint64_t stream, hipStream_t s);
 
-// Gram geometry with a target number of workgroups (gram.hip)
-void gram_geometry(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int *wt, int *nbi,
-                   int *nbj, int *nblocks, int *nkc, int64_t *kper);
+// Gram geometry with a target number of workgroups and a cap on the tile
+// width in units of 32 (gram.hip)
+void gram_geometry(int64_t IA, int64_t IB, int64_t P, bool sym, int64_t target, int wt_max, int *wt,
+                   int *nbi, int *nbj, int *nblocks, int *nkc, int64_t *kper);
 
 // Batched path (batch.hip).  One descriptor per tensor per mode step.
 constexpr int BT_WAVES = 8;

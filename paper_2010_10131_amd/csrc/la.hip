@@ -132,7 +132,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(const double *__rest
 
 hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, double *R,
                        double *Rinv, int64_t *flag, hipStream_t s) {
-    size_t lds = (size_t)(n * n + n * CB) * sizeof(double);
+    const size_t lds = chol_lds_bytes(n);
     if (lds > 64 * 1024)
         hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(CHOL_THREADS), lds, s, G, n, ldg, shift_rel, R, Rinv, flag);

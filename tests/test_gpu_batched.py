@@ -91,3 +91,44 @@ def test_batched_graph_replay_is_deterministic(api):
             assert torch.equal(G[t], ref_G[t]), (rep, t)
             for n in range(3):
                 assert torch.equal(U[t][n], ref_U[t][n]), (rep, t, n)
+
+
+@pytest.mark.parametrize("tiles", [(2, 1, 1), (16, 2, 8), (64, 4, 64)])
+def test_batched_tiles_agree(api, tiles):
+    """Other tile choices split the work differently; the decomposition agrees
+    with the default one to rounding and stays within the oracle tolerance."""
+    import torch
+    xs, xd, xp = make_batch(api, SHAPES, seed=21)
+    outs = []
+    for t in [None, tiles]:
+        plan = api.BatchPlan(SHAPES, "bf16x6", "bf16x3", tiles=t)
+        G, U, cp, up = plan.outputs()
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+        plan.run(xp, cp, up, ws)
+        plan.check(ws)
+        outs.append((G, U))
+    for t, (d, r) in enumerate(SHAPES):
+        xn = np.linalg.norm(xs[t].astype(np.float64))
+        Xa = recon(api, outs[0][0][t], outs[0][1][t])
+        Xb = recon(api, outs[1][0][t], outs[1][1][t])
+        assert np.linalg.norm(Xa - Xb) / xn <= 1e-6, (t, d, r, tiles)
+
+
+def test_autotuner_picks_a_valid_choice(api):
+    import torch
+    from paper_2010_10131_amd import autotune
+    shapes = SHAPES[:6]
+    xs, xd, xp = make_batch(api, shapes, seed=31)
+    best, ms, table = autotune.tune_batched(shapes, xp, "bf16x6", "bf16x3", reps=1)
+    assert ms > 0 and len(table) >= 12
+    assert min(r["ms"] for r in table) == ms
+    assert (table[0]["gram_wg_per_cu"], table[0]["gram_wt_max"], table[0]["ttm_rows_per_wave"]) == autotune.DEFAULT
+    plan = api.BatchPlan(shapes, "bf16x6", "bf16x3", tiles=best)
+    G, U, cp, up = plan.outputs()
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.run(xp, cp, up, ws)
+    plan.check(ws)
+    for t, (d, r) in enumerate(shapes):
+        Go, Uo, _ = oracle.sthosvd(xs[t], r)
+        xn = np.linalg.norm(xs[t].astype(np.float64))
+        assert np.linalg.norm(recon(api, G[t], U[t]) - oracle.reconstruct(Go, Uo)) / xn <= 1e-5

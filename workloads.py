@@ -132,11 +132,22 @@ def batch_shapes(count=256, seed=BASE_SEED + 3, lo=32, hi=256, rlo=0.10, rhi=0.2
     return shapes
 
 
-def batch_tensors(count=256, seed=BASE_SEED + 3, nu=1e-4, dtype="float32", **kw):
-    """The batched workload: (shapes, tensors); tensor t uses seed + 1000 + t."""
+def batch_tensors(count=256, seed=BASE_SEED + 3, nu=1e-4, dtype="float32", workers=1, **kw):
+    """The batched workload: (shapes, tensors); tensor t uses seed + 1000 + t.
+
+    Each tensor has its own seed, so `workers` > 1 (a thread pool; numpy's
+    generators and BLAS release the GIL) gives the same tensors faster."""
     shapes = batch_shapes(count, seed, **kw)
-    xs = [lowrank_plus_noise(d, r, "none", nu, seed + 1000 + t, dtype)
-          for t, (d, r) in enumerate(shapes)]
+
+    def one(t):
+        d, r = shapes[t]
+        return lowrank_plus_noise(d, r, "none", nu, seed + 1000 + t, dtype)
+
+    if workers <= 1:
+        return shapes, [one(t) for t in range(count)]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=int(workers)) as ex:
+        xs = list(ex.map(one, range(count)))
     return shapes, xs
 
 
