@@ -194,9 +194,8 @@ __global__ __launch_bounds__(BE_THREADS) void batch_eig_kernel(const BatchStep *
     double *Q = scr, *Z = Q + (int64_t)n * p, *Z2 = Z + (int64_t)n * p, *G = Z2 + (int64_t)n * p;
     double *Rinv = G + p * p, *T = Rinv + p * p, *W = T + p * p, *jac = W + p * p;
     for (int e = threadIdx.x; e < n * p; e += BE_THREADS)
-        Z[e] = gaussian_value(0x5EED5EEDull, (uint64_t)n * 1000 + p, (uint64_t)e);
+        Q[e] = gaussian_value(0x5EED5EEDull, (uint64_t)n * 1000 + p, (uint64_t)e);
     __syncthreads();
-    wg_orth(Z, Q, Z2, n, p, 3, G, Rinv, flag);
     for (int it = 0; it < SI_ITERS_DEV; ++it) {
         wg_gemm(0, 0, n, p, n, S, n, Q, n, Z, n);
         wg_orth(Z, Q, Z2, n, p, it + 1 == SI_ITERS_DEV ? 3 : 2, G, Rinv, flag);

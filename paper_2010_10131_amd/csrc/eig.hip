@@ -180,9 +180,9 @@ size_t eig_ws_bytes(int64_t n) {
 //   n <= 128: cyclic Jacobi on S itself (one workgroup, LDS).
 //   n > 128 with a block p = max(R + 16, 1.5 R) <= 96: subspace iteration
 //     Q <- orth(S Q) from a seeded Gaussian block (SI_ITERS = 3 times; orth is
-//     shifted Cholesky-QR, three passes for the first and last basis, two
-//     in between), then Rayleigh-Ritz: Jacobi on T = Q^T S Q and
-//     U = Q W(:, :R), with the sign rule applied to U.
+//     shifted Cholesky-QR, three passes for the last basis, two before), then
+//     Rayleigh-Ritz: Jacobi on T = Q^T S Q and U = Q W(:, :R), with the sign
+//     rule applied to U.
 //   otherwise: Jacobi on S with A and V in the workspace (slow; large R only).
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
                       int max_sweeps, void *ws, int64_t *flag, hipStream_t s) {
@@ -191,8 +191,9 @@ hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *
     SiWs w = si_layout((char *)ws, n, p);
     const int ni = (int)n, pi = (int)p;
     hipError_t e;
-    if ((e = gaussian_f64(w.Z, n * p, 0x5EED5EEDull, (uint64_t)n * 1000 + p, s))) return e;
-    if ((e = orth(w.Z, w.Q, ni, pi, 3, w, flag, s))) return e;
+    // start block: seeded Gaussian, used as it is (its span is all that
+    // matters to the iteration, and an n x p Gaussian is well conditioned)
+    if ((e = gaussian_f64(w.Q, n * p, 0x5EED5EEDull, (uint64_t)n * 1000 + p, s))) return e;
     for (int it = 0; it < SI_ITERS; ++it) {
         if ((e = gemm_f64(0, 0, ni, pi, ni, 1.0, S, n, w.Q, n, 0.0, w.Z, n, w.gws, s))) return e;
         if ((e = orth(w.Z, w.Q, ni, pi, it + 1 == SI_ITERS ? 3 : 2, w, flag, s))) return e;

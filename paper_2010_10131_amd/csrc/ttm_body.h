@@ -35,11 +35,13 @@ __device__ __forceinline__ void ttm_load_chunk(const T *__restrict__ Y, int64_t 
 
 // Body of the TTM for one workgroup: wg of nwg workgroups sharing the row
 // blocks of this tensor, r-block rb.  Also used by the batched kernels.
-template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES>
+// PF = chunks of Y in flight per wave (1 or 2).
+template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES, int PF = 1>
 __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *__restrict__ Uq,
                                          T *__restrict__ Z, int64_t L, int64_t K, int64_t Rout,
                                          int64_t P, int nchunks, int ntiles, int64_t nrowblocks,
                                          int64_t wg, int64_t nwg, int rb) {
+    if (CONTIG) L = 1;  // the contiguous variant is the L = 1 view; a constant for the compiler
     constexpr int NQ = Frag<PREC>::NQ;
     typedef typename Acc<PREC>::type AccT;
     extern __shared__ uint4 s_u[];
@@ -93,19 +95,7 @@ __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *_
 #pragma unroll
             for (int rt = 0; rt < RTB; ++rt) acc[nt][rt] = AccT{0, 0, 0, 0};
 
-        T nxt[NT][8];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, 8 * g, nxt[nt]);
-
-        for (int c = 0; c < nchunks; ++c) {
-            Frag<PREC> yb[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) make_frag(nxt[nt], yb[nt]);
-            if (c + 1 < nchunks) {
-                const int64_t kb = (int64_t)(c + 1) * KC + 8 * g;
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, kb, nxt[nt]);
-            }
+        auto chunk_mma = [&](int c, const Frag<PREC>(&yb)[NT]) {
 #pragma unroll
             for (int rt = 0; rt < RTB; ++rt) {
                 FragQ<PREC> ua;
@@ -122,6 +112,58 @@ __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *_
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) mma_frag(ua.f, yb[nt], acc[nt][rt]);
             }
+        };
+
+        if constexpr (PF == 1) {
+            // one chunk buffer: chunk c + 1 loads while chunk c is multiplied
+            T nxt[NT][8];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, 8 * g, nxt[nt]);
+            for (int c = 0; c < nchunks; ++c) {
+                Frag<PREC> yb[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) make_frag(nxt[nt], yb[nt]);
+                if (c + 1 < nchunks) {
+                    const int64_t kb = (int64_t)(c + 1) * KC + 8 * g;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, kb, nxt[nt]);
+                }
+                chunk_mma(c, yb);
+            }
+        } else {
+        // two chunk buffers: chunk c is consumed from one while chunks c + 1
+        // (already in flight) and c + 2 (issued right after c is split) load
+        T xa[NT][8], xb[NT][8];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, 8 * g, xa[nt]);
+        if (nchunks > 1) {
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, KC + 8 * g, xb[nt]);
+        }
+        for (int c = 0; c < nchunks; c += 2) {
+            {
+                Frag<PREC> yb[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) make_frag(xa[nt], yb[nt]);
+                if (c + 2 < nchunks) {
+                    const int64_t kb = (int64_t)(c + 2) * KC + 8 * g;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, kb, xa[nt]);
+                }
+                chunk_mma(c, yb);
+            }
+            if (c + 1 < nchunks) {
+                Frag<PREC> yb[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) make_frag(xb[nt], yb[nt]);
+                if (c + 3 < nchunks) {
+                    const int64_t kb = (int64_t)(c + 3) * KC + 8 * g;
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) ttm_load_chunk<T, CONTIG>(Y, base[nt], L, K, kb, xb[nt]);
+                }
+                chunk_mma(c + 1, yb);
+            }
+        }
         }
 
         // D[r][p]: lane holds r = 16*rt + drow(g, v), p = 16*nt + lane%16
