@@ -49,6 +49,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256,
                     help="tensors in the batched measurement (0 skips it)")
     ap.add_argument("--batch-reps", type=int, default=5)
+    ap.add_argument("--no-selector", action="store_true",
+                    help="skip the learned-selector measurement (5-way 48^5 workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -157,6 +159,10 @@ def main():
     if args.batch > 0:
         batched = bench_batched(args, api, torch, dev, gp, tp)
 
+    selector = None
+    if not args.no_selector:
+        selector = bench_selector(api, torch, dev, gp, tp)
+
     fp32_ms = results[fp32_name]["ms"]
     out = {
         "metric": "st-HOSVD wall time & TTM HBM GB/s: mixed-precision vs FP32 at equal rel. error",
@@ -184,6 +190,7 @@ def main():
                      "frac": ttm_gbs / HBM_PEAK_GBS, "traffic": None},
         "cpu_baseline": cpu,
         "batched": batched,
+        "selector": selector,
     }
     print(json.dumps(out))
 
@@ -261,3 +268,62 @@ def bench_batched(args, api, torch, dev, gp, tp):
 
 if __name__ == "__main__":
     main()
+
+
+def bench_selector(api, torch, dev, gp, tp, reps=3):
+    """The 48^5 FP32 workload (ranks 8) under the learned per-mode solver
+    choice, against always-EIG, always-ALS and the exhaustive choice (each
+    mode's two steps timed on the working tensor, the faster one kept)."""
+    w = wl.C5
+    t0 = time.time()
+    X = wl.lowrank_plus_noise_device(w.dims, w.ranks, w.decay, w.nu, w.seed, dev)
+    log(f"[bench] generated {w.name} on the device in {time.time() - t0:.1f}s")
+    N = len(w.dims)
+
+    def timed(**kw):
+        plan = api.Plan(w.dims, w.ranks, torch.float32, gp, tp, **kw)
+        G = api.fortran_empty(w.ranks, torch.float32, dev)
+        U = [api.fortran_empty((w.dims[n], w.ranks[n]), torch.float64, dev) for n in range(N)]
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        plan.run(X, G, U, ws)
+        plan.check(ws)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            plan.run(X, G, U, ws)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t) * 1e3 / reps
+        plan.check(ws)
+        names = ["eig", "als"]
+        return ms, [names[v] for v in plan.solvers]
+
+    auto_ms, auto_choice = timed(solver="auto")
+    eig_ms, _ = timed(solver="eig")
+    als_ms, _ = timed(solver="als")
+    # exhaustive: both steps of every mode on the working tensor, keep the faster
+    Y = X
+    choice, per_mode = [], []
+    for n in range(N):
+        t_best, z_best = None, None
+        row = {"mode": n}
+        for sv in ("eig", "als"):
+            Z, U, ev, ws = api.mode_step(Y, n, w.ranks[n], sv, gp, tp)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(reps):
+                Z, U, ev, ws = api.mode_step(Y, n, w.ranks[n], sv, gp, tp, out=Z, workspace=ws)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t) * 1e3 / reps
+            row[sv + "_ms"] = ms
+            if t_best is None or ms < t_best:
+                t_best, z_best, best_sv = ms, Z, sv
+        choice.append(best_sv)
+        per_mode.append(row)
+        Y = z_best
+    exh_ms, _ = timed(per_mode=choice)
+    log(f"[bench] selector on {w.name}: auto {auto_choice} {auto_ms:.2f} ms, exhaustive {choice} "
+        f"{exh_ms:.2f} ms, always-eig {eig_ms:.2f} ms, always-als {als_ms:.2f} ms")
+    return {"workload": w.name, "auto_ms": auto_ms, "auto_choice": auto_choice,
+            "exhaustive_ms": exh_ms, "exhaustive_choice": choice, "always_eig_ms": eig_ms,
+            "always_als_ms": als_ms, "regret": auto_ms / exh_ms - 1.0, "per_mode_steps": per_mode,
+            "data": "device-drawn low-rank + 1e-4 noise (same recipe as the host generator)"}

@@ -156,3 +156,35 @@ def gaussian_init(I: int, R: int, seed: int, mode: int) -> np.ndarray:
     seeded by (seed, mode); passed identically to both implementations."""
     rng = np.random.default_rng([int(seed), int(mode), 0xA15])
     return np.asfortranarray(rng.standard_normal((I, R)))
+
+
+def lowrank_plus_noise_device(dims, ranks, decay="none", nu=0.0, seed=BASE_SEED, device="cuda"):
+    """The same recipe as lowrank_plus_noise, drawn on the device with torch's
+    seeded generator (different numbers, same distribution), for inputs of
+    several GB where host generation would dominate.  FP32, column-major."""
+    import torch
+    dims = [int(d) for d in dims]
+    ranks = [int(r) for r in ranks]
+    N = len(dims)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    w = torch.from_numpy(decay_weights(ranks, decay)).to(device=device, dtype=torch.float64)
+    G0 = torch.randn(ranks, generator=g, device=device, dtype=torch.float64) * w
+    Q = []
+    for n in range(N):
+        A = torch.randn(dims[n], ranks[n], generator=g, device=device, dtype=torch.float64)
+        q, r = torch.linalg.qr(A)
+        Q.append(q * torch.sign(torch.diagonal(r)))
+    # T in C order over reversed modes: element (i_N, ..., i_1)
+    T = G0.permute(*range(N - 1, -1, -1)).contiguous()
+    for n in range(N):
+        ax = N - 1 - n
+        T = torch.movedim(torch.tensordot(T, Q[n].t(), dims=([ax], [0])), -1, ax)
+    X0 = T.to(torch.float32).contiguous()
+    del T
+    if nu > 0.0:
+        E = torch.randn(X0.shape, generator=g, device=device, dtype=torch.float32)
+        scale = nu * torch.linalg.vector_norm(X0.double()) / torch.linalg.vector_norm(E.double())
+        X0.add_(E * scale.float())
+        del E
+    return X0.permute(*range(N - 1, -1, -1))
