@@ -146,19 +146,19 @@ hipError_t jacobi_launch(int64_t n, int64_t R, const double *S, double *U, doubl
         const bool vl = jacobi_small_lds(n, true) <= budget;
         const size_t lds = jacobi_small_lds(n, vl);
         if (vl) {
-            hipFuncSetAttribute((const void *)jacobi_small_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (hipError_t ea = hipFuncSetAttribute((const void *)jacobi_small_kernel<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return ea;
             hipLaunchKernelGGL(jacobi_small_kernel<true>, dim3(1), dim3(EIG_THREADS), lds, s, S, (int)n, (int)R, Ag, U, lam, tol, max_sweeps, flag);
         } else {
-            hipFuncSetAttribute((const void *)jacobi_small_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (hipError_t ea = hipFuncSetAttribute((const void *)jacobi_small_kernel<false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return ea;
             hipLaunchKernelGGL(jacobi_small_kernel<false>, dim3(1), dim3(EIG_THREADS), lds, s, S, (int)n, (int)R, Ag, U, lam, tol, max_sweeps, flag);
         }
     } else if (2 * mat <= budget) {
         auto k = jacobi_kernel<true, true>;
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * mat));
+        if (hipError_t ea = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * mat))) return ea;
         hipLaunchKernelGGL(k, dim3(1), dim3(EIG_THREADS), 2 * mat, s, S, (int)n, (int)R, Ag, Vg, U, lam, tol, max_sweeps, flag);
     } else if (mat <= budget) {
         auto k = jacobi_kernel<true, false>;
-        hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mat);
+        if (hipError_t ea = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mat)) return ea;
         hipLaunchKernelGGL(k, dim3(1), dim3(EIG_THREADS), mat, s, S, (int)n, (int)R, Ag, Vg, U, lam, tol, max_sweeps, flag);
     } else {
         hipLaunchKernelGGL((jacobi_kernel<false, false>), dim3(1), dim3(EIG_THREADS), 0, s, S, (int)n, (int)R, Ag, Vg, U, lam, tol, max_sweeps, flag);

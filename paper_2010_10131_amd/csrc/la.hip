@@ -14,53 +14,67 @@
 
 namespace sth {
 
-constexpr int GT = 32;  // gemm tile
+constexpr int GT = 32;   // gemm tile (rows and columns of C)
+constexpr int GK = 128;  // k-extent staged in LDS per step
 
-// C_part[z] (m x n, ldc) = op(A) op(B) over k-slice z.
+// C_part[z] (m x n, ldc) = op(A) op(B) over k-slice z.  The skinny products
+// of the eigensolver and the ALS branch are latency-bound, so every step
+// loads a whole GT x GK panel of each operand with all loads in flight at
+// once (coalesced along the contiguous index of each operand), then runs
+// GK rank-1 updates from LDS: one global round trip per 128 values of k.
 __global__ __launch_bounds__(256) void gemm_f64_kernel(int ta, int tb, int m, int n, int k,
                                                        double alpha, const double *__restrict__ A,
                                                        int64_t lda, const double *__restrict__ B,
                                                        int64_t ldb, double beta, double *__restrict__ C,
                                                        int64_t ldc, int kslice, double *__restrict__ part) {
-    __shared__ double sA[GT][GT + 1];  // sA[kk][row]
-    __shared__ double sB[GT][GT + 1];  // sB[kk][col]
-    const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
+    extern __shared__ double s_gemm[];
+    double *sA = s_gemm;                  // sA[kk * (GT + 1) + r] = op(A)(row0 + r, kc + kk)
+    double *sB = s_gemm + GK * (GT + 1);  // sB[kk * (GT + 1) + c] = op(B)(kc + kk, col0 + c)
+    constexpr int PER = GT * GK / 256;    // elements of each panel per thread
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
     const int row0 = blockIdx.x * GT, col0 = blockIdx.y * GT;
     const int kz = blockIdx.z;
     const int kbeg = kz * kslice, kend = min(k, kbeg + kslice);
     double acc[2][2] = {{0, 0}, {0, 0}};
-    for (int kc = kbeg; kc < kend; kc += GT) {
-        for (int e = threadIdx.x; e < GT * GT; e += 256) {
-            int a = e % GT, b = e / GT;
-            // sA[kk][r]: element op(A)(row0 + r, kc + kk)
-            {
-                int r, kk;
-                if (ta) { kk = a; r = b; } else { r = a; kk = b; }
-                int gr = row0 + r, gk = kc + kk;
-                double v = 0.0;
-                if (gr < m && gk < kend) v = ta ? A[gk + lda * gr] : A[gr + lda * gk];
-                sA[kk][r] = v;
-            }
-            {
-                int cidx, kk;
-                if (tb) { cidx = a; kk = b; } else { kk = a; cidx = b; }
-                int gc = col0 + cidx, gk = kc + kk;
-                double v = 0.0;
-                if (gc < n && gk < kend) v = tb ? B[gc + ldb * gk] : B[gk + ldb * gc];
-                sB[kk][cidx] = v;
-            }
+    for (int kc = kbeg; kc < kend; kc += GK) {
+        double ra[PER], rb[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            // A panel: contiguous along r (op = A) or along kk (op = A^T)
+            int r, kk;
+            if (ta) { kk = e % GK; r = e / GK; } else { r = e % GT; kk = e / GT; }
+            int gr = row0 + r, gk = kc + kk;
+            ra[u] = (gr < m && gk < kend) ? (ta ? A[gk + lda * gr] : A[gr + lda * gk]) : 0.0;
+            // B panel: contiguous along kk (op = B) or along c (op = B^T)
+            int cc, kb;
+            if (tb) { cc = e % GT; kb = e / GT; } else { kb = e % GK; cc = e / GK; }
+            int gc = col0 + cc, gk2 = kc + kb;
+            rb[u] = (gc < n && gk2 < kend) ? (tb ? B[gc + ldb * gk2] : B[gk2 + ldb * gc]) : 0.0;
+        }
+        __syncthreads();  // the previous step's reads of the panels are done
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = tid + 256 * u;
+            int r, kk;
+            if (ta) { kk = e % GK; r = e / GK; } else { r = e % GT; kk = e / GT; }
+            sA[kk * (GT + 1) + r] = ra[u];
+            int cc, kb;
+            if (tb) { cc = e % GT; kb = e / GT; } else { kb = e % GK; cc = e / GK; }
+            sB[kb * (GT + 1) + cc] = rb[u];
         }
         __syncthreads();
+        const int kn = min(GK, kend - kc);
 #pragma unroll 8
-        for (int kk = 0; kk < GT; ++kk) {
-            double a0 = sA[kk][tx], a1 = sA[kk][tx + 16];
-            double b0 = sB[kk][ty], b1 = sB[kk][ty + 16];
+        for (int kk = 0; kk < kn; ++kk) {
+            const double a0 = sA[kk * (GT + 1) + tx], a1 = sA[kk * (GT + 1) + tx + 16];
+            const double b0 = sB[kk * (GT + 1) + ty], b1 = sB[kk * (GT + 1) + ty + 16];
             acc[0][0] += a0 * b0;
             acc[1][0] += a1 * b0;
             acc[0][1] += a0 * b1;
             acc[1][1] += a1 * b1;
         }
-        __syncthreads();
     }
     for (int x = 0; x < 2; ++x)
         for (int y = 0; y < 2; ++y) {
@@ -75,6 +89,8 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int ta, int tb, int m, in
             }
         }
 }
+
+constexpr size_t GEMM_LDS = (size_t)2 * GK * (GT + 1) * sizeof(double);
 
 __global__ void gemm_reduce_kernel(int m, int n, int nz, const double *__restrict__ part,
                                    double alpha, double beta, double *__restrict__ C, int64_t ldc) {
@@ -92,11 +108,15 @@ size_t gemm_ws_bytes(int m, int n, int k) {
     return nz > 1 ? (size_t)nz * m * n * sizeof(double) : 0;
 }
 
+// k-slices: one LDS step (GK values of k) per workgroup where the tile count
+// leaves the chip idle, at most 32 slices.
 int gemm_splits(int m, int n, int k) {
-    int tiles = ((m + GT - 1) / GT) * ((n + GT - 1) / GT);
-    int nz = 1;
-    while (tiles * nz < 256 && k / (nz * 2) >= 64 && nz < 32) nz *= 2;
-    return nz;
+    const int tiles = ((m + GT - 1) / GT) * ((n + GT - 1) / GT);
+    if (tiles >= 256) return 1;
+    int nz = (k + GK - 1) / GK;
+    nz = std::min(nz, 32);
+    while (nz > 1 && tiles * nz > 1024) nz = (nz + 1) / 2;
+    return std::max(nz, 1);
 }
 
 hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const double *A,
@@ -110,7 +130,10 @@ hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const dou
     nz = std::max(1, (k + kslice - 1) / kslice);
     dim3 grid((m + GT - 1) / GT, (n + GT - 1) / GT, nz);
     double *part = nz > 1 ? (double *)ws : nullptr;
-    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, s, ta, tb, m, n, k, alpha, A, lda, B,
+    hipError_t ea = hipFuncSetAttribute((const void *)gemm_f64_kernel,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)GEMM_LDS);
+    if (ea != hipSuccess) return ea;
+    hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), GEMM_LDS, s, ta, tb, m, n, k, alpha, A, lda, B,
                        ldb, beta, C, ldc, kslice, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || nz == 1) return e;
@@ -134,7 +157,7 @@ hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, do
                        double *Rinv, int64_t *flag, hipStream_t s) {
     const size_t lds = chol_lds_bytes(n);
     if (lds > 64 * 1024)
-        hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (hipError_t ea = hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return ea;
     hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(CHOL_THREADS), lds, s, G, n, ldg, shift_rel, R, Rinv, flag);
     return hipGetLastError();
 }
