@@ -34,12 +34,15 @@ __device__ __forceinline__ int rr_player(int x, int r, int ne) {
 // parallel round-robin sweep as jacobi_body, with A padded to an even order
 // ne (a zero row and column: the odd player's partner, whose rotation is the
 // identity, so no bound tests in the update) and a fixed work split computed
-// once: a thread owns row-pair I = tid % m of A for a stride of column pairs,
-// and row tid % n of V for a stride of column pairs.  The arithmetic of every
-// rotation and update is the one of jacobi_body.
+// once.  V does not feed the rotations, so its update lags one round behind:
+// while wave 0 computes the rotations of round r from A, waves 1.. apply the
+// rotations of round r - 1 to V (two sets of rotation parameters in LDS);
+// then every thread applies round r to A.  The arithmetic of every rotation
+// and update is the one of jacobi_body.
 constexpr int JS_MAXM = 64;
-constexpr int JS_KA = JS_MAXM / (EIG_THREADS / JS_MAXM);        // A blocks per thread
-constexpr int JS_KV = JS_MAXM / (EIG_THREADS / (2 * JS_MAXM));  // V pairs per thread
+constexpr int JS_VTHREADS = EIG_THREADS - 64;                    // waves 1.. update V
+constexpr int JS_KA = JS_MAXM / (EIG_THREADS / JS_MAXM);         // A blocks per thread
+constexpr int JS_KV = (JS_MAXM + JS_VTHREADS / (2 * JS_MAXM) - 1) / (JS_VTHREADS / (2 * JS_MAXM));
 constexpr int JS_CA = 4;  // A blocks whose loads are issued together
 constexpr int JS_CV = 8;  // V pairs whose loads are issued together
 
@@ -57,8 +60,8 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
                                                   double *__restrict__ lam, double tol,
                                                   int max_sweeps, int64_t *__restrict__ flag) {
     extern __shared__ double s_e[];
-    __shared__ double s_c[JS_MAXM], s_s[JS_MAXM];
-    __shared__ int s_p[JS_MAXM], s_q[JS_MAXM];
+    __shared__ double s_c[2][JS_MAXM], s_s[2][JS_MAXM];
+    __shared__ int s_p[2][JS_MAXM], s_q[2][JS_MAXM];
     __shared__ double s_red[2][EIG_THREADS / 64];
     __shared__ int s_sel[2 * JS_MAXM];
     __shared__ double s_sign[2 * JS_MAXM];
@@ -76,8 +79,40 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
         const int i = e % n, j = e / n;
         V[e] = (i == j) ? 1.0 : 0.0;
     }
+    // A: thread owns row pair Ia for the column pairs ja0, ja0 + ja, ...
     const int ja = EIG_THREADS / m, Ia = tid % m, ja0 = tid / m;
-    const int jv = EIG_THREADS / n, rv = tid % n, jv0 = tid / n;
+    // V (waves 1..): thread owns row rv for the column pairs jv0, jv0 + jv, ...
+    const int tv = tid - 64;
+    const int jv = JS_VTHREADS / n, rv = tv >= 0 ? tv % n : 0, jv0 = tv >= 0 ? tv / n : jv;
+
+    // V <- V J for the rotations of set `set` (threads of waves 1..)
+    auto update_v = [&](int set) {
+        if (jv0 >= jv) return;
+#pragma unroll 1
+        for (int k0 = 0; k0 < JS_KV; k0 += JS_CV) {
+            int pj[JS_CV], qj[JS_CV];
+            double vp[JS_CV], vq[JS_CV];
+#pragma unroll
+            for (int k = 0; k < JS_CV; ++k) {
+                const int J = jv0 + (k0 + k) * jv;
+                if (J < m) {
+                    pj[k] = rv + n * s_p[set][J];
+                    qj[k] = rv + n * s_q[set][J];
+                    vp[k] = V[pj[k]];
+                    vq[k] = V[qj[k]];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < JS_CV; ++k) {
+                const int J = jv0 + (k0 + k) * jv;
+                if (J < m) {
+                    const double cj = s_c[set][J], sj = s_s[set][J];
+                    V[pj[k]] = cj * vp[k] - sj * vq[k];
+                    V[qj[k]] = sj * vp[k] + cj * vq[k];
+                }
+            }
+        }
+    };
     __syncthreads();
 
     int sweep = 0;
@@ -120,90 +155,72 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
         }
         prev_off2 = s_red[0][0];
         for (int r = 0; r < ne - 1; ++r) {
-            if (tid < m) {
-                int p = rr_player(tid, r, ne), q = rr_player(ne - 1 - tid, r, ne);
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
+            const int set = r & 1;
+            if (tid < 64) {
+                if (tid < m) {
+                    int p = rr_player(tid, r, ne), q = rr_player(ne - 1 - tid, r, ne);
+                    if (p > q) {
+                        const int t = p;
+                        p = q;
+                        q = t;
+                    }
+                    double c = 1.0, sn = 0.0;
+                    const double apq = A[p + ne * q];
+                    if (apq != 0.0) {
+                        const double app = A[p + ne * p], aqq = A[q + ne * q];
+                        const double theta = (aqq - app) / (2.0 * apq);
+                        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        sn = t * c;
+                    }
+                    s_p[set][tid] = p;
+                    s_q[set][tid] = q;
+                    s_c[set][tid] = c;
+                    s_s[set][tid] = sn;
                 }
-                double c = 1.0, sn = 0.0;
-                const double apq = A[p + ne * q];
-                if (apq != 0.0) {
-                    const double app = A[p + ne * p], aqq = A[q + ne * q];
-                    const double theta = (aqq - app) / (2.0 * apq);
-                    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    sn = t * c;
-                }
-                s_p[tid] = p;
-                s_q[tid] = q;
-                s_c[tid] = c;
-                s_s[tid] = sn;
+            } else if (r > 0) {
+                update_v(set ^ 1);   // round r - 1
             }
             __syncthreads();
             if (ja0 < ja) {
-                const int pI = s_p[Ia], qI = s_q[Ia];
-                const double ci = s_c[Ia], si = s_s[Ia];
+                const int pI = s_p[set][Ia], qI = s_q[set][Ia];
+                const double ci = s_c[set][Ia], si = s_s[set][Ia];
 #pragma unroll 1
                 for (int k0 = 0; k0 < JS_KA; k0 += JS_CA) {
-                int pj[JS_CA], qj[JS_CA];
-                double a[JS_CA][4];
+                    int pj[JS_CA], qj[JS_CA];
+                    double a[JS_CA][4];
 #pragma unroll
-                for (int k = 0; k < JS_CA; ++k) {
-                    const int J = ja0 + (k0 + k) * ja;
-                    if (J < m) {
-                        pj[k] = ne * s_p[J];
-                        qj[k] = ne * s_q[J];
-                        a[k][0] = A[pI + pj[k]];
-                        a[k][1] = A[pI + qj[k]];
-                        a[k][2] = A[qI + pj[k]];
-                        a[k][3] = A[qI + qj[k]];
+                    for (int k = 0; k < JS_CA; ++k) {
+                        const int J = ja0 + (k0 + k) * ja;
+                        if (J < m) {
+                            pj[k] = ne * s_p[set][J];
+                            qj[k] = ne * s_q[set][J];
+                            a[k][0] = A[pI + pj[k]];
+                            a[k][1] = A[pI + qj[k]];
+                            a[k][2] = A[qI + pj[k]];
+                            a[k][3] = A[qI + qj[k]];
+                        }
                     }
-                }
 #pragma unroll
-                for (int k = 0; k < JS_CA; ++k) {
-                    const int J = ja0 + (k0 + k) * ja;
-                    if (J < m) {
-                        const double cj = s_c[J], sj = s_s[J];
-                        const double b00 = ci * a[k][0] - si * a[k][2], b01 = ci * a[k][1] - si * a[k][3];
-                        const double b10 = si * a[k][0] + ci * a[k][2], b11 = si * a[k][1] + ci * a[k][3];
-                        A[pI + pj[k]] = cj * b00 - sj * b01;
-                        A[pI + qj[k]] = sj * b00 + cj * b01;
-                        A[qI + pj[k]] = cj * b10 - sj * b11;
-                        A[qI + qj[k]] = sj * b10 + cj * b11;
+                    for (int k = 0; k < JS_CA; ++k) {
+                        const int J = ja0 + (k0 + k) * ja;
+                        if (J < m) {
+                            const double cj = s_c[set][J], sj = s_s[set][J];
+                            const double b00 = ci * a[k][0] - si * a[k][2], b01 = ci * a[k][1] - si * a[k][3];
+                            const double b10 = si * a[k][0] + ci * a[k][2], b11 = si * a[k][1] + ci * a[k][3];
+                            A[pI + pj[k]] = cj * b00 - sj * b01;
+                            A[pI + qj[k]] = sj * b00 + cj * b01;
+                            A[qI + pj[k]] = cj * b10 - sj * b11;
+                            A[qI + qj[k]] = sj * b10 + cj * b11;
+                        }
                     }
-                }
-                }
-            }
-            if (jv0 < jv) {
-#pragma unroll 1
-                for (int k0 = 0; k0 < JS_KV; k0 += JS_CV) {
-                int pj[JS_CV], qj[JS_CV];
-                double vp[JS_CV], vq[JS_CV];
-#pragma unroll
-                for (int k = 0; k < JS_CV; ++k) {
-                    const int J = jv0 + (k0 + k) * jv;
-                    if (J < m) {
-                        pj[k] = rv + n * s_p[J];
-                        qj[k] = rv + n * s_q[J];
-                        vp[k] = V[pj[k]];
-                        vq[k] = V[qj[k]];
-                    }
-                }
-#pragma unroll
-                for (int k = 0; k < JS_CV; ++k) {
-                    const int J = jv0 + (k0 + k) * jv;
-                    if (J < m) {
-                        const double cj = s_c[J], sj = s_s[J];
-                        V[pj[k]] = cj * vp[k] - sj * vq[k];
-                        V[qj[k]] = sj * vp[k] + cj * vq[k];
-                    }
-                }
                 }
             }
             __syncthreads();
         }
+        // the last round's V update
+        if (tid >= 64) update_v((ne - 2) & 1);
+        __syncthreads();
         ++sweep;
     }
     if (!converged && tid == 0 && flag) flag[0] = 1;

@@ -143,7 +143,8 @@ def main():
     w = pd.cpu().numpy()
     pred_tr = api.mlp_forward(pd, Xtr).cpu().numpy()
     pred_ho = api.mlp_forward(pd, dcol(X[:, ho])).cpu().numpy()
-    rep = {"meta": meta, "train_modes": int(len(tr)), "heldout_modes": int(len(ho)),
+    rep = {"meta": meta, "seed": args.seed, "steps": args.steps, "lr": args.lr,
+           "train_modes": int(len(tr)), "heldout_modes": int(len(ho)),
            "loss_history": hist,
            "train": evaluate(choose(pred_tr), te_ms[tr], ta_ms[tr]),
            "heldout": evaluate(choose(pred_ho), te_ms[ho], ta_ms[ho])}
