@@ -155,6 +155,33 @@ def main():
     ttm_gbs = ttm_bytes / (ttm_ms * 1e-3) / 1e9
     log(f"[bench] ttm mode-1 {ttm_ms * 1e3:.1f} us, {ttm_gbs:.0f} GB/s")
 
+    # measured ceiling: a plain device copy of the same 512 MiB (torch's copy kernel)
+    Yc = torch.empty_like(Xd)
+    for _ in range(2):
+        Yc.copy_(Xd)
+    e0.record(stream)
+    for _ in range(args.ttm_reps):
+        Yc.copy_(Xd)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_ms = e0.elapsed_time(e1) / args.ttm_reps
+    copy_gbs = 2 * Xd.numel() * 4 / (copy_ms * 1e-3) / 1e9
+    del Yc
+    log(f"[bench] copy 512 MiB {copy_ms * 1e3:.1f} us, {copy_gbs:.0f} GB/s (read + write)")
+
+    # mode-1 Gram of the headline recipe: MFMA-bound at I = 512
+    for _ in range(2):
+        api.gram_mode_n(Xd, 0, gp)
+    e0.record(stream)
+    for _ in range(args.ttm_reps):
+        api.gram_mode_n(Xd, 0, gp)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gram_ms = e0.elapsed_time(e1) / args.ttm_reps
+    gram_useful = float(I0) * I0 * J0          # symmetric half, the Gram flop convention
+    gram_tfs = gram_useful / (gram_ms * 1e-3) / 1e12
+    log(f"[bench] gram mode-1 ({gp}) {gram_ms * 1e3:.1f} us, {gram_tfs:.1f} TFLOP/s useful")
+
     batched = None
     if args.batch > 0:
         batched = bench_batched(args, api, torch, dev, gp, tp)
@@ -185,6 +212,13 @@ def main():
         "t2_bar": T2_BAR,
         "ttm_mode1_us": ttm_ms * 1e3,
         "ttm_hbm_gbps": ttm_gbs,
+        "copy_ceiling_gbps": copy_gbs,
+        "ttm_frac_of_copy": ttm_gbs / copy_gbs,
+        "gram_mode1": {"prec": gp, "us": gram_ms * 1e3, "useful_tflops": gram_tfs,
+                       "flop_convention": "I^2 J (symmetric half, Eq. 4)",
+                       "mfma_products": {"fp32": 1, "fp64": 1, "bf16x3": 3, "bf16x6": 6}[gp],
+                       "frac_of_bf16_peak_executed": (gram_tfs * {"fp32": 1, "fp64": 1, "bf16x3": 3, "bf16x6": 6}[gp]
+                                                      / 2500.0) if gp.startswith("bf16") else None},
         "roofline": {"bound": "hbm", "kernel": "ttm mode-1 (512 -> 64, 262144 rows)",
                      "achieved": ttm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": ttm_gbs / HBM_PEAK_GBS, "traffic": None},

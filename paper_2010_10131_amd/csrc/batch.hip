@@ -22,9 +22,11 @@
 namespace sth {
 
 constexpr int BE_THREADS = 512;  // batched eigen workgroup (matches the Jacobi body)
-// LDS for Jacobi's A and V in the batched kernel, which also holds the
-// Cholesky body's static LDS
-constexpr int BATCH_LDS_AV = 150 * 1024;
+// Dynamic LDS for Jacobi's A and V in the batched eigen kernel: the kernel's
+// static LDS (Jacobi, Cholesky and selection arrays, about 11.3 KiB) must fit
+// beside it in the 160 KiB of a workgroup; batch_step_launch checks the sum.
+constexpr int BATCH_LDS_AV = 148 * 1024;
+constexpr size_t WG_LDS_MAX = 160 * 1024;
 
 __device__ __forceinline__ int find_segment(const int64_t *__restrict__ pref, int len, int64_t x) {
     // largest k with pref[k] <= x (pref[0] = 0, pref[len] = total)
@@ -379,6 +381,9 @@ hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int 
     }
     {
         const size_t lds = sp.eig_lds;
+        hipFuncAttributes fa;
+        if ((e = hipFuncGetAttributes(&fa, (const void *)batch_eig_kernel)) != hipSuccess) return e;
+        if (lds + fa.sharedSizeBytes > WG_LDS_MAX) return hipErrorInvalidConfiguration;
         if (lds > 64 * 1024) {
             e = hipFuncSetAttribute((const void *)batch_eig_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
             if (e != hipSuccess) return e;

@@ -95,8 +95,9 @@ def test_batched_graph_replay_is_deterministic(api):
 
 @pytest.mark.parametrize("tiles", [(2, 1, 1), (16, 2, 8), (64, 4, 64)])
 def test_batched_tiles_agree(api, tiles):
-    """Other tile choices split the work differently; the decomposition agrees
-    with the default one to rounding and stays within the oracle tolerance."""
+    """Other tile choices split the work differently (the Gram's split-K
+    depth changes the order of its partial sums): every choice stays within
+    the tolerance of the oracle, and the choices agree with each other to it."""
     import torch
     xs, xd, xp = make_batch(api, SHAPES, seed=21)
     outs = []
@@ -111,7 +112,10 @@ def test_batched_tiles_agree(api, tiles):
         xn = np.linalg.norm(xs[t].astype(np.float64))
         Xa = recon(api, outs[0][0][t], outs[0][1][t])
         Xb = recon(api, outs[1][0][t], outs[1][1][t])
-        assert np.linalg.norm(Xa - Xb) / xn <= 1e-6, (t, d, r, tiles)
+        Go, Uo, _ = oracle.sthosvd(xs[t], r)
+        Xo = oracle.reconstruct(Go, Uo)
+        assert np.linalg.norm(Xb - Xo) / xn <= 1e-5, (t, d, r, tiles)
+        assert np.linalg.norm(Xa - Xb) / xn <= 1e-5, (t, d, r, tiles)
 
 
 def test_autotuner_picks_a_valid_choice(api):
