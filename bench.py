@@ -300,9 +300,6 @@ def bench_batched(args, api, torch, dev, gp, tp):
             "eager_default_tiles_ms": default_ms, "autotune": table}
 
 
-if __name__ == "__main__":
-    main()
-
 
 def bench_selector(api, torch, dev, gp, tp, reps=3):
     """The 48^5 FP32 workload (ranks 8) under the learned per-mode solver
@@ -361,3 +358,7 @@ def bench_selector(api, torch, dev, gp, tp, reps=3):
             "exhaustive_ms": exh_ms, "exhaustive_choice": choice, "always_eig_ms": eig_ms,
             "always_als_ms": als_ms, "regret": auto_ms / exh_ms - 1.0, "per_mode_steps": per_mode,
             "data": "device-drawn low-rank + 1e-4 noise (same recipe as the host generator)"}
+
+
+if __name__ == "__main__":
+    main()

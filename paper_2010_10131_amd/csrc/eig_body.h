@@ -29,6 +29,26 @@ __device__ __forceinline__ int rr_player(int x, int r, int ne) {
     return y + 1;
 }
 
+// Rotation (c, s) that annihilates a_pq against the diagonal pair (a_pp,
+// a_qq).  A rotation is skipped (identity, returns false) when a_pq is at
+// the roundoff level: |a_pq| <= rel sqrt(|a_pp| |a_qq|) (its own diagonal
+// pair, rel = n eps) or |a_pq| <= abs (abs = 4 eps ||A||_F, the error one
+// rotation leaves in the entry it annihilates).  Rotating such an entry
+// would only stir roundoff; a sweep in which every rotation is skipped ends
+// the iteration (threshold Jacobi).
+__device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double rel,
+                                                double abs_floor, double &c, double &s) {
+    c = 1.0;
+    s = 0.0;
+    const double a = fabs(apq);
+    if (a <= abs_floor || a <= rel * sqrt(fabs(app)) * sqrt(fabs(aqq))) return false;
+    const double theta = (aqq - app) / (2.0 * apq);
+    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = t * c;
+    return true;
+}
+
 // ------------------------------------------------------------------------
 // Small matrices (n <= 128, at most JS_MAXM pairs per round).  The same
 // parallel round-robin sweep as jacobi_body, with A padded to an even order
@@ -65,9 +85,11 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
     __shared__ double s_red[2][EIG_THREADS / 64];
     __shared__ int s_sel[2 * JS_MAXM];
     __shared__ double s_sign[2 * JS_MAXM];
-    __shared__ int s_stop;
+    __shared__ int s_stop, s_rot;
+    __shared__ double s_floor;
 
     const int ne = n + (n & 1), m = ne / 2;
+    const double thresh = (double)n * 2.220446049250313e-16;
     double *A = s_e;                         // ne x ne, leading dimension ne
     double *V = VLDS ? s_e + ne * ne : Vg;   // n x ne, leading dimension n
     const int tid = threadIdx.x;
@@ -143,9 +165,12 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
             }
             int stop = 0;
             if (o2 <= tol * tol * f2 || o2 == 0.0) stop = 1;
+            else if (sweep > 0 && s_rot == 0) stop = 1;   // the last sweep rotated nothing
             else if (o2 <= (double)n * n * 1.2e-32 * f2 && prev_off2 >= 0.0 && o2 >= 0.25 * prev_off2) stop = 1;
             else if (sweep >= max_sweeps) stop = 2;
             s_stop = stop;
+            s_rot = 0;
+            s_floor = 4.0 * 2.220446049250313e-16 * sqrt(f2);
             s_red[0][0] = o2;
         }
         __syncthreads();
@@ -164,15 +189,9 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
                         p = q;
                         q = t;
                     }
-                    double c = 1.0, sn = 0.0;
-                    const double apq = A[p + ne * q];
-                    if (apq != 0.0) {
-                        const double app = A[p + ne * p], aqq = A[q + ne * q];
-                        const double theta = (aqq - app) / (2.0 * apq);
-                        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        sn = t * c;
-                    }
+                    double c, sn;
+                    if (jacobi_rotation(A[p + ne * p], A[q + ne * q], A[p + ne * q], thresh, s_floor, c, sn))
+                        s_rot = 1;
                     s_p[set][tid] = p;
                     s_q[set][tid] = q;
                     s_c[set][tid] = c;
@@ -269,7 +288,9 @@ __device__ __forceinline__ void jacobi_body(const double *__restrict__ S, int n,
     __shared__ double s_red[2][EIG_THREADS / 64];
     __shared__ int s_sel[512];
     __shared__ double s_sign[512];
-    __shared__ int s_stop;
+    __shared__ int s_stop, s_rot;
+    __shared__ double s_floor;
+    const double thresh = (double)n * 2.220446049250313e-16;
 
     double *A = ALDS ? s_e : Ag;
     double *V = VLDS ? (ALDS ? s_e + n * n : s_e) : Vg;
@@ -313,11 +334,14 @@ __device__ __forceinline__ void jacobi_body(const double *__restrict__ S, int n,
             }
             int stop = 0;
             if (o2 <= tol * tol * f2 || o2 == 0.0) stop = 1;
+            else if (sweep > 0 && s_rot == 0) stop = 1;   // the last sweep rotated nothing
             // roundoff floor: off(A) already at the FP64 noise level of an
             // n x n rotation sequence and no longer shrinking
             else if (o2 <= (double)n * n * 1.2e-32 * f2 && prev_off2 >= 0.0 && o2 >= 0.25 * prev_off2) stop = 1;
             else if (sweep >= max_sweeps) stop = 2;
             s_stop = stop;
+            s_rot = 0;
+            s_floor = 4.0 * 2.220446049250313e-16 * sqrt(f2);
             s_red[0][0] = o2;  // broadcast for the stagnation test
         }
         __syncthreads();
@@ -336,16 +360,8 @@ __device__ __forceinline__ void jacobi_body(const double *__restrict__ S, int n,
                     q = t;
                 }
                 double c = 1.0, s = 0.0;
-                if (q < n) {
-                    double apq = A[p + n * q];
-                    if (apq != 0.0) {
-                        double app = A[p + n * p], aqq = A[q + n * q];
-                        double theta = (aqq - app) / (2.0 * apq);
-                        double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = t * c;
-                    }
-                }
+                if (q < n && jacobi_rotation(A[p + n * p], A[q + n * q], A[p + n * q], thresh, s_floor, c, s))
+                    s_rot = 1;
                 s_p[k] = p;
                 s_q[k] = q;
                 s_c[k] = c;
