@@ -291,6 +291,10 @@ sth_status sth_selector_features(int64_t I, int64_t R, int64_t J, float *out10);
 /* Host inference: out2 (host) = predicted (log t_EIG, log t_ALS); weights
  * (host) NULL = the built-in weights. */
 sth_status sth_selector_predict(const float *weights, int64_t I, int64_t R, int64_t J, float *out2);
+/* Host: the solver sthosvd_plan picks for a mode under STH_SOLVER_AUTO
+ * (solver_out: STH_SOLVER_EIG or STH_SOLVER_ALS): the smaller predicted
+ * time, then the solvers' limits (EIG needs I_n <= 512, ALS R_n <= 128). */
+sth_status sth_selector_choose(const float *weights, int64_t I, int64_t R, int64_t J, int32_t *solver_out);
 
 /* Device training kernels.  X: device, 10 x B features (column per sample);
  * T: device, 2 x B targets; params: device packed floats; ws: device scratch

@@ -99,6 +99,7 @@ SIGNATURES = {
     "sth_selector_features": (ctypes.c_int, [_i64, _i64, _i64, ctypes.POINTER(ctypes.c_float)]),
     "sth_selector_predict": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), _i64, _i64, _i64,
                                             ctypes.POINTER(ctypes.c_float)]),
+    "sth_selector_choose": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), _i64, _i64, _i64, _i32p]),
     "sth_mlp_workspace": (_sz, [_i64]),
     "sth_mlp_forward": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "sth_mlp_loss_grad": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

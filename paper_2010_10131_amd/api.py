@@ -362,6 +362,17 @@ def selector_predict(I: int, R: int, J: int, weights: Optional[np.ndarray] = Non
     return out
 
 
+def selector_choose(I: int, R: int, J: int, weights: Optional[np.ndarray] = None) -> str:
+    """The solver sthosvd_plan picks for a mode under solver="auto"."""
+    out = ctypes.c_int32()
+    wp = None
+    if weights is not None:
+        weights = np.ascontiguousarray(weights, dtype=np.float32)
+        wp = weights.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    check(_lib.load().sth_selector_choose(wp, I, R, J, ctypes.byref(out)))
+    return "als" if out.value == SOLVER["als"] else "eig"
+
+
 def mlp_forward(params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     """Y (2 x B) of the selector network on device features X (10 x B)."""
     L = _lib.load()

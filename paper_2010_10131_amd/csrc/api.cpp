@@ -67,7 +67,7 @@ int device_cu_count() {
 // ------------------------------------------------------- validation ----
 
 static const int MAX_ORDER = 8;
-static const int64_t MAX_EIG_N = 512;   // Jacobi kernel limit (one workgroup)
+static const int64_t MAX_EIG_N = SEL_MAX_EIG_N;   // I_n x I_n Gram and eigensolver
 static const int64_t EIG_DIRECT_MAX_HOST = 128;
 static const int64_t SI_BLOCK_MAX_HOST = 96;
 static int64_t si_block_host_api(int64_t n, int64_t R) {
@@ -75,7 +75,7 @@ static int64_t si_block_host_api(int64_t n, int64_t R) {
     p = (p + 7) / 8 * 8;
     return std::min(p, n);
 }
-static const int64_t MAX_ALS_R = 128;   // R x R Cholesky in LDS
+static const int64_t MAX_ALS_R = SEL_MAX_ALS_R;   // R x R Cholesky in LDS
 
 static size_t esize(int dtype) { return dtype == STH_F64 ? 8 : 4; }
 static size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -680,6 +680,13 @@ extern "C" int32_t sth_selector_num_trainable(void) { return mlp_num_trainable()
 extern "C" sth_status sth_selector_features(int64_t I, int64_t R, int64_t J, float *out10) {
     if (I < 1 || R < 1 || J < 1 || !out10) return fail(STH_ERR_INVALID, "bad selector features input");
     selector_features(I, R, J, out10);
+    return STH_OK;
+}
+
+extern "C" sth_status sth_selector_choose(const float *weights, int64_t I, int64_t R, int64_t J,
+                                          int32_t *solver_out) {
+    if (I < 1 || R < 1 || R > I || J < 1 || !solver_out) return fail(STH_ERR_INVALID, "bad selector input");
+    *solver_out = selector_choose(I, R, J, 0, weights);
     return STH_OK;
 }
 

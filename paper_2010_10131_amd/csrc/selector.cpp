@@ -46,7 +46,10 @@ int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *wei
     float f[SEL_IN], y[SEL_OUT];
     selector_features(I, R, J, f);
     selector_predict(weights, f, y);
-    return (y[1] < y[0]) ? STH_SOLVER_ALS : STH_SOLVER_EIG;
+    int choice = (y[1] < y[0]) ? STH_SOLVER_ALS : STH_SOLVER_EIG;
+    if (choice == STH_SOLVER_ALS && R > SEL_MAX_ALS_R) choice = STH_SOLVER_EIG;
+    if (choice == STH_SOLVER_EIG && I > SEL_MAX_EIG_N) choice = STH_SOLVER_ALS;
+    return choice;
 }
 
 }  // namespace sth

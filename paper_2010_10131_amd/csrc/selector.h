@@ -21,7 +21,13 @@ void selector_features(int64_t I, int64_t R, int64_t J, float *out10);
 // (NULL = the built-in weights).
 void selector_predict(const float *weights, const float *feat10, float *out2);
 
-// 0 = EIG, 1 = ALS (argmin of the predicted times; EIG on ties).
+// Limits of the two solvers (a mode the chosen solver cannot run goes to
+// the other one).
+constexpr int64_t SEL_MAX_EIG_N = 512;   // eigensolver: I_n x I_n Gram
+constexpr int64_t SEL_MAX_ALS_R = 128;   // ALS: R_n x R_n Cholesky in LDS
+
+// 0 = EIG, 1 = ALS: argmin of the predicted times (EIG on ties), then the
+// solver limits (EIG needs I_n <= SEL_MAX_EIG_N, ALS R_n <= SEL_MAX_ALS_R).
 int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *weights);
 
 }  // namespace sth

@@ -98,16 +98,18 @@ def main():
             recs.append(rec)
             Y = Ynext
             cur[n] = R
-        if si % 100 == 0:
-            print(f"[timing_db] {si}/{len(shapes)} shapes, {time.time() - t0:.0f}s", flush=True)
+        if si % 100 == 0 or si + 1 == len(shapes):
+            print(f"[timing_db] {si + 1}/{len(shapes)} shapes, {time.time() - t0:.0f}s", flush=True)
             ws_cache.clear()
             torch.cuda.empty_cache()
-    meta = {"count": args.count, "seed": args.seed, "max_elems": args.max_elems,
-            "gram_prec": args.gram_prec, "ttm_prec": args.ttm_prec, "reps": args.reps,
-            "device": torch.cuda.get_device_name(0), "seconds": time.time() - t0}
-    with open(args.out, "w") as f:
-        json.dump({"meta": meta, "records": recs}, f)
-    print(f"[timing_db] wrote {len(recs)} records in {meta['seconds']:.0f}s", flush=True)
+            # written as it goes, so that a run cut short still leaves its records
+            meta = {"count": si + 1, "requested": args.count, "seed": args.seed,
+                    "max_elems": args.max_elems, "gram_prec": args.gram_prec,
+                    "ttm_prec": args.ttm_prec, "reps": args.reps,
+                    "device": torch.cuda.get_device_name(0), "seconds": time.time() - t0}
+            with open(args.out, "w") as f:
+                json.dump({"meta": meta, "records": recs}, f)
+    print(f"[timing_db] wrote {len(recs)} records in {time.time() - t0:.0f}s", flush=True)
 
 
 if __name__ == "__main__":

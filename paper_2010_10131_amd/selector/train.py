@@ -61,9 +61,11 @@ def init_params(seed, mu, isd):
     return np.concatenate(parts).astype(np.float32)
 
 
-def choose(pred):
-    """0 = EIG, 1 = ALS: argmin of the predicted log times (EIG on ties)."""
-    return (pred[1] < pred[0]).astype(int)
+def choose(api, recs, w):
+    """0 = EIG, 1 = ALS: the library's own choice under solver="auto" (argmin
+    of the predicted times, then the solvers' limits)."""
+    return np.array([1 if api.selector_choose(r["I"], r["R"], r["J"], weights=w) == "als" else 0
+                     for r in recs])
 
 
 def evaluate(choice, te, ta):
@@ -85,6 +87,16 @@ def evaluate(choice, te, ta):
             "total_ms_always_als_feasible": float(np.where(als_ok, ta, te)[valid].sum())}
 
 
+def report(api, recs, w, seed):
+    """Accuracy and total times of the library's choices with weights w on
+    the training and held-out records (host inference only)."""
+    te_ms, ta_ms = targets(recs)
+    tr, ho = split(recs, seed)
+    return {"train_modes": int(len(tr)), "heldout_modes": int(len(ho)),
+            "train": evaluate(choose(api, [recs[i] for i in tr], w), te_ms[tr], ta_ms[tr]),
+            "heldout": evaluate(choose(api, [recs[i] for i in ho], w), te_ms[ho], ta_ms[ho])}
+
+
 def write_inc(path, w):
     lines = ["// Selector weights written by paper_2010_10131_amd/selector/train.py from the",
              "// per-mode timing database measured on MI355X (see selector/report.json).",
@@ -104,7 +116,25 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--seed", type=int, default=7)
+    ap.add_argument("--eval-only", metavar="WEIGHTS_JSON",
+                    help="recompute the evaluation of stored weights on the host (no training)")
     args = ap.parse_args()
+    if args.eval_only:
+        from paper_2010_10131_amd import api
+        meta, recs = load_db(args.db)
+        with open(args.eval_only) as f:
+            w = np.array(json.load(f)["weights"], dtype=np.float32)
+        path = os.path.join(args.out_dir, "report.json")
+        old = {}
+        if os.path.exists(path):
+            with open(path) as f:
+                old = json.load(f)
+        old.update({"meta": meta, "seed": args.seed})
+        old.update(report(api, recs, w, args.seed))
+        with open(path, "w") as f:
+            json.dump(old, f, indent=1)
+        print(json.dumps({"train": old["train"], "heldout": old["heldout"]}, indent=1))
+        return 0
 
     import torch
 
@@ -144,10 +174,8 @@ def main():
     pred_tr = api.mlp_forward(pd, Xtr).cpu().numpy()
     pred_ho = api.mlp_forward(pd, dcol(X[:, ho])).cpu().numpy()
     rep = {"meta": meta, "seed": args.seed, "steps": args.steps, "lr": args.lr,
-           "train_modes": int(len(tr)), "heldout_modes": int(len(ho)),
-           "loss_history": hist,
-           "train": evaluate(choose(pred_tr), te_ms[tr], ta_ms[tr]),
-           "heldout": evaluate(choose(pred_ho), te_ms[ho], ta_ms[ho])}
+           "loss_history": hist}
+    rep.update(report(api, recs, w, args.seed))
     # host inference (used at plan time) must agree with the device network
     k = int(ho[0])
     host = api.selector_predict(recs[k]["I"], recs[k]["R"], recs[k]["J"], weights=w)

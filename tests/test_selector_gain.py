@@ -1,0 +1,83 @@
+"""What the trained selector gains over the method without it, judged on the
+held-out 30 % of the per-mode timing database measured on MI355X with this
+library's own kernels.  The database and the trained weights are committed
+(paper_2010_10131_amd/selector/data); the choices come from the library's
+host inference with the compiled-in weights (sth_selector_choose, the rule
+sthosvd_plan applies under solver="auto"), so this runs on the CPU.
+
+The method without the selector runs one solver for every mode (Alg. 2 with
+a fixed choice): always-EIG (the usual st-HOSVD) or always-ALS (falling back
+to EIG only where ALS cannot run).  The judge of the selector's choices is
+exhaustive timing: per mode, the faster of the two measured steps."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DATA = os.path.join(HERE, "..", "paper_2010_10131_amd", "selector", "data")
+BIG = 1e30
+
+
+@pytest.fixture(scope="module")
+def heldout():
+    from paper_2010_10131_amd import api
+    from paper_2010_10131_amd.selector import train
+    _, recs = train.load_db(os.path.join(DATA, "timing_db.json"))
+    with open(os.path.join(DATA, "report.json")) as f:
+        rep = json.load(f)
+    _, ho = train.split(recs, rep["seed"])
+    recs = [recs[i] for i in ho]
+    te, ta = train.targets(recs)
+    choice = np.array([1 if api.selector_choose(r["I"], r["R"], r["J"]) == "als" else 0 for r in recs])
+    return recs, te, ta, choice, rep
+
+
+def test_compiled_in_weights_are_the_trained_ones(heldout):
+    from paper_2010_10131_amd import api
+    recs, te, ta, choice, rep = heldout
+    with open(os.path.join(DATA, "weights.json")) as f:
+        w = np.array(json.load(f)["weights"], dtype=np.float32)
+    for r in recs[:50]:
+        a = api.selector_predict(r["I"], r["R"], r["J"])
+        b = api.selector_predict(r["I"], r["R"], r["J"], weights=w)
+        np.testing.assert_allclose(a, b, rtol=1e-6, atol=1e-6)
+    truth = (ta < te).astype(int)
+    valid = np.minimum(te, ta) < BIG
+    acc = float(np.mean(choice[valid] == truth[valid]))
+    assert abs(acc - rep["heldout"]["accuracy"]) < 1e-9
+
+
+def test_selector_beats_both_fixed_choices_with_small_regret(heldout):
+    recs, te, ta, choice, rep = heldout
+    best = np.minimum(te, ta)
+    valid = best < BIG
+    chosen = np.where(choice == 1, ta, te)
+    assert np.all(chosen[valid] < BIG), "the selector chose a solver that cannot run"
+    tot_sel = chosen[valid].sum()
+    tot_best = best[valid].sum()
+    tot_eig = np.where(te < BIG, te, ta)[valid].sum()
+    tot_als = np.where(ta < BIG, ta, te)[valid].sum()
+    assert tot_sel < min(tot_eig, tot_als)
+    assert tot_sel / tot_best - 1.0 <= 0.05
+    # and it is right far more often than the better fixed choice
+    truth = (ta < te).astype(int)
+    acc = np.mean(choice[valid] == truth[valid])
+    assert acc >= 0.9 and acc > max(np.mean(truth[valid]), 1 - np.mean(truth[valid]))
+
+
+def test_plan_auto_uses_the_selector_and_respects_solver_limits():
+    import torch
+    from paper_2010_10131_amd import api
+    # plans are host-only: the solver of every mode is fixed at plan time
+    for dims, ranks in [((64, 64, 64), (8, 8, 8)), ((512, 64, 40), (200, 8, 8)), ((48,) * 5, (8,) * 5)]:
+        p = api.Plan(dims, ranks, torch.float32, "bf16x6", "bf16x3", "auto")
+        cur = list(dims)
+        for n in range(len(dims)):
+            J = int(np.prod(cur)) // cur[n]
+            want = api.selector_choose(cur[n], ranks[n], J)
+            assert ["eig", "als"][p.solvers[n]] == want
+            cur[n] = ranks[n]
+    # R = 200 > 128: ALS cannot run that mode, so it is EIG whatever the network says
+    assert api.selector_choose(512, 200, 2560) == "eig"
