@@ -225,12 +225,16 @@ sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R, 
                       int32_t prec, const void *Y, const double *U, int32_t transpose_u, void *Z,
                       void *ws, size_t ws_bytes, sth_stream_t stream);
 
-/* R leading eigenpairs of a symmetric n x n FP64 matrix S (device), by a
- * cyclic Jacobi eigensolver in FP64: U (device, n x R FP64, orthonormal,
- * largest-magnitude entry of each column positive) and lam (device, R
- * values, descending; may be NULL).  ws: device scratch of
- * eig_leading_workspace(n) bytes; an exceeded sweep cap is recorded in the
- * first 8 bytes of ws as a non-zero int64. */
+/* R leading eigenpairs of a symmetric n x n FP64 matrix S (device), in FP64:
+ * U (device, n x R FP64, orthonormal, largest-magnitude entry of each column
+ * positive) and lam (device, R values, descending; may be NULL).  n <= 128:
+ * parallel cyclic Jacobi on S; n > 128 with a subspace block
+ * p = max(R + 16, 1.5 R) (rounded up to 8) <= 96: subspace iteration on a
+ * seeded Gaussian block with Rayleigh-Ritz (S must then have rank >= p; a
+ * Gram matrix of rank below p goes through sthosvd_run, which passes the rank
+ * bound of each mode); otherwise Jacobi on S in the workspace.  ws: device
+ * scratch of eig_leading_workspace(n) bytes; an exceeded sweep cap or a
+ * breakdown is recorded in the first 8 bytes of ws as a non-zero int64. */
 size_t eig_leading_workspace(int64_t n);
 sth_status eig_leading(int64_t n, int64_t R, const double *S, double *U, double *lam,
                        int32_t max_sweeps, void *ws, size_t ws_bytes, sth_stream_t stream);

@@ -347,7 +347,7 @@ static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *s
     if (stp.solver == STH_SOLVER_EIG) {
         // Alg. 2 lines 6-8
         HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
-        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s), "eig");
+        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M), "eig");
         HIPCHK(ttm_prep_u(Un, stp.I, stp.R, 0, tp, uq, s), "ttm prep");
         HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
         return STH_OK;
@@ -510,7 +510,7 @@ extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double 
     if ((st = check_ptr(S, "S")) || (st = check_ptr(U, "U")) || (st = check_ptr(lam, "lam", true)) || (st = check_ptr(ws, "ws"))) return st;
     if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
     HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (int64_t *)ws,
-                      (hipStream_t)stream), "eig");
+                      (hipStream_t)stream, n), "eig");
     return STH_OK;
 }
 
@@ -849,7 +849,16 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             if (b.I > EIG_DIRECT_MAX_HOST && si_block_host_api(b.I, b.R) > SI_BLOCK_MAX_HOST)
                 return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n = %lld too large for the batched eigensolver", t, s, (long long)b.R);
             if (b.R > 64) return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n > 64 in the batched path", t, s);
-            maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.R));
+            b.sib = 0;
+            if (b.I > EIG_DIRECT_MAX_HOST) {
+                // the Gram of this step has rank <= L * M: the subspace block
+                // is capped there, and more vectors than that need the direct
+                // solver, which the batched eigen kernel has only for I <= 128
+                if (b.R > P)
+                    return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n = %lld exceeds the rank bound %lld of the mode-%d Gram (I_n > 128; use single runs)", t, s, (long long)b.R, (long long)P, s + 1);
+                b.sib = (int32_t)std::min<int64_t>(si_block_host_api(b.I, b.R), P);
+            }
+            maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.sib));
             b.nchunks = (int)((b.I + 31) / 32);
             b.ntiles = (int)((b.R + 15) / 16);
             b.rtb = b.ntiles <= 1 ? 1 : (b.ntiles <= 2 ? 2 : 4);
@@ -882,7 +891,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
         T.eig_lds = 0;
         T.max_nchunks = 0;
         for (int t = 0; t < count; ++t) {
-            T.eig_lds = std::max(T.eig_lds, batch_eig_lds(sd[s][t].I, sd[s][t].R));
+            T.eig_lds = std::max(T.eig_lds, batch_eig_lds(sd[s][t].I, sd[s][t].sib));
             T.max_nchunks = std::max(T.max_nchunks, sd[s][t].nchunks);
         }
         auto make = [&](const std::vector<int32_t> &list, const std::vector<int64_t> &units, int cls) {

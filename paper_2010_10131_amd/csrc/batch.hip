@@ -192,7 +192,7 @@ __global__ __launch_bounds__(BE_THREADS) void batch_eig_kernel(const BatchStep *
             jacobi_small_body<false>(S, n, R, scr, U, nullptr, tol, max_sweeps, flag);
         return;
     }
-    const int p = (int)si_block_dev(n, R);
+    const int p = d.sib;
     double *Q = scr, *Z = Q + (int64_t)n * p, *Z2 = Z + (int64_t)n * p, *G = Z2 + (int64_t)n * p;
     double *Rinv = G + p * p, *T = Rinv + p * p, *W = T + p * p, *jac = W + p * p;
     for (int e = threadIdx.x; e < n * p; e += BE_THREADS)
@@ -289,19 +289,17 @@ size_t batch_gram_lds(int prec, int wt) {
     return std::max(l1, gen);
 }
 
-size_t batch_eig_lds(int64_t n, int64_t R) {
+size_t batch_eig_lds(int64_t n, int64_t p) {
     auto jac = [](int64_t m) -> size_t {
         const size_t both = jacobi_small_lds(m, true);
         return both <= (size_t)BATCH_LDS_AV ? both : jacobi_small_lds(m, false);
     };
     if (n <= EIG_DIRECT_MAX) return jac(n);
-    const int64_t p = si_block_host(n, R);
     return std::max({jac(p), chol_lds_bytes(p), (size_t)2 * 32 * 33 * 8});
 }
 
-size_t batch_eig_scratch(int64_t n, int64_t R) {
+size_t batch_eig_scratch(int64_t n, int64_t p) {
     if (n <= EIG_DIRECT_MAX) return (size_t)2 * n * n * 8;
-    const int64_t p = si_block_host(n, R);
     return (size_t)(3 * n * p + 4 * p * p + 2 * p * p) * 8;
 }
 

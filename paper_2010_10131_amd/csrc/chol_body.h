@@ -6,186 +6,229 @@
 
 namespace sth {
 
-// One workgroup of NTH threads, n <= 128, everything in LDS (dynamic LDS of
-// chol_lds_bytes(n)).
-// G (n x n, symmetric, ldg) + shift_rel * trace(G) / n * I = L L^T, blocked
-// right-looking Cholesky with 16-column panels: the diagonal block is
-// factored by one wave in registers (row i of the block in lane i, columns
-// broadcast with cross-lane shuffles), the panel below by a row-parallel
-// forward substitution and the trailing matrix by an element-parallel
-// rank-16 update.  L is then inverted in place block column by block column
-// from the last one:  L^{-1}(B, K) = -(sum_{J in (K, B]} L^{-1}(B, J) L(J, K))
-// L(K, K)^{-1}.  Writes R = L^T (upper, may be NULL) and Rinv = L^{-T}
-// (upper).  A non-positive pivot sets flag[0] = 2 and is replaced by a tiny
-// positive one so that the run continues.
+// One workgroup of NTH threads (a multiple of 64, at least 256), n <= 128,
+// everything in LDS (dynamic LDS of chol_lds_bytes(n)).
+//
+// G (n x n, symmetric, ldg) + shift_rel * trace(G) / n * I = L L^T.  The
+// matrix is padded with an identity block to np = 16 * ceil(n / 16), so that
+// every block is a full 16 x 16 tile (the padded factor is diag(L, I)).
+// Blocked right-looking Cholesky with 16-column panels:
+//   * the diagonal block is factored by one wave in registers (row l of the
+//     block in lane l, right-looking within the block, columns broadcast with
+//     lane reads, 1 / sqrt from the reciprocal square root);
+//   * the panel below it by a row-parallel forward substitution;
+//   * the trailing matrix by a rank-16 update on the FP64 matrix cores
+//     (16 x 16 tiles of the lower triangle, four 16x16x4 products each).
+// L is then inverted in place block column by block column from the last
+// one:  L^{-1}(B, K) = -(sum_{J in (K, B]} L^{-1}(B, J) L(J, K)) L(K, K)^{-1},
+// both products on the matrix cores, L(K, K)^{-1} by forward substitution.
+// Writes R = L^T (upper, may be NULL) and Rinv = L^{-T} (upper), n x n.  A
+// non-positive pivot sets flag[0] = 2 and is replaced by a tiny positive one
+// so that the run continues.
+//
+// L lives in LDS with an odd leading dimension (np + 1), so that walking a
+// row and walking a column are both free of bank conflicts.
 constexpr int CB = 16;
 
-// Dynamic LDS of chol_body: L (n x n), the panel buffer (n x CB) and the
-// reciprocals of the diagonal of L (n).
-__host__ __device__ inline size_t chol_lds_bytes(int64_t n) { return (size_t)(n * n + n * CB + n) * 8; }
+__host__ __device__ inline int chol_np(int64_t n) { return (int)((n + CB - 1) / CB * CB); }
+__host__ __device__ inline int chol_ld(int64_t n) { return chol_np(n) + 1; }
 
-template <int CHOL_THREADS>
+// Dynamic LDS of chol_body: L (np x ld), the product buffer (np x CB) and the
+// reciprocals of the diagonal of L (np).
+__host__ __device__ inline size_t chol_lds_bytes(int64_t n) {
+    return (size_t)(chol_np(n) * chol_ld(n) + chol_np(n) * CB + chol_np(n)) * 8;
+}
+
+// value of v in lane `src` (src uniform across the wave)
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+template <int NTH>
 __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, int64_t ldg,
                                           double shift_rel, double *__restrict__ Rout,
                                           double *__restrict__ Rinv, int64_t *__restrict__ flag) {
-    extern __shared__ double s_l[];  // L, column-major, leading dimension n; then T (n x CB)
-    double *s_tmp = s_l + n * n;
-    double *s_rd = s_tmp + n * CB;    // 1 / L(i, i)
+    constexpr int NW = NTH / 64;
+    extern __shared__ double s_l[];  // L, column-major, leading dimension ld
+    const int np = chol_np(n), ld = np + 1, nb = np / CB;
+    double *s_tmp = s_l + np * ld;   // np x CB
+    double *s_rd = s_tmp + np * CB;  // 1 / L(i, i)
     __shared__ double s_dinv[CB * CB];
     __shared__ double s_tr;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < n * n; e += CHOL_THREADS) {
-        int i = e % n, j = e / n;
-        s_l[e] = (i >= j) ? G[i + ldg * j] : 0.0;
+    const int tr = lane & 15, tg = lane >> 4;   // matrix-core tile coordinates
+
+    // lower triangle of G padded with the identity, four columns per wave and
+    // step (8 loads in flight per thread)
+    for (int j0 = 4 * wave; j0 < np; j0 += 4 * NW) {
+        double v[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = j0 + u, i = lane + 64 * h;
+                double x = 0.0;
+                if (j < n && i < n) x = (i >= j) ? G[i + ldg * j] : 0.0;
+                else if (i == j) x = 1.0;
+                v[u][h] = x;
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int j = j0 + u, i = lane + 64 * h;
+                if (j < np && i < np) s_l[i + ld * j] = v[u][h];
+            }
     }
     __syncthreads();
     if (wave == 0) {
-        // trace, reduced across one wave from the copy in LDS
         double t = 0.0;
-        for (int i = lane; i < n; i += 64) t += s_l[i + n * i];
+        for (int i = lane; i < n; i += 64) t += s_l[i + ld * i];
         for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
         if (lane == 0) s_tr = t;
     }
     __syncthreads();
     if (shift_rel != 0.0) {
         const double sh = shift_rel * s_tr / n;
-        for (int i = tid; i < n; i += CHOL_THREADS) s_l[i + n * i] += sh;
+        for (int i = tid; i < n; i += NTH) s_l[i + ld * i] += sh;
         __syncthreads();
     }
     const double tiny = 1e-300 + 1e-30 * fabs(s_tr);
     bool bad = false;
-    for (int k0 = 0; k0 < n; k0 += CB) {
-        const int kn = min(CB, n - k0);
-        // 1. diagonal block, wave 0, row i in lane i
+    for (int kb = 0; kb < nb; ++kb) {
+        const int k0 = kb * CB, t0 = k0 + CB;
+        // 1. diagonal block: wave 0, row l of the block in lane l
         if (wave == 0) {
             double row[CB];
 #pragma unroll
-            for (int c = 0; c < CB; ++c) row[c] = (lane < kn && c < kn) ? s_l[k0 + lane + n * (k0 + c)] : 0.0;
+            for (int c = 0; c < CB; ++c) row[c] = (lane < CB) ? s_l[k0 + lane + ld * (k0 + c)] : 0.0;
 #pragma unroll
             for (int j = 0; j < CB; ++j) {
-                if (j < kn) {
-                    // d = a(j,j) - sum_{c<j} L(j,c)^2, computed in lane j, then broadcast
-                    double sacc = row[j];
-#pragma unroll
-                    for (int c = 0; c < CB; ++c)
-                        if (c < j) sacc -= row[c] * __shfl(row[c], j);
-                    double d = __shfl(sacc, j);
-                    if (!(d > 0.0)) {
-                        bad = true;
-                        d = tiny;
-                    }
-                    d = sqrt(d);
-                    const double rd = 1.0 / d;
-                    if (lane == j) {
-                        row[j] = d;
-                        s_rd[k0 + j] = rd;
-                    } else if (lane > j) {
-                        row[j] = sacc * rd;
-                    }
+                double d = lane_value(row[j], j);
+                if (!(d > 0.0)) {
+                    bad = true;
+                    d = tiny;
                 }
-            }
-            if (lane < kn)
+                const double rd = rsqrt(d);
+                if (lane == j) {
+                    row[j] = d * rd;
+                    s_rd[k0 + j] = rd;
+                } else if (lane > j) {
+                    row[j] *= rd;
+                }
+                // rank-1 update of the block's remaining columns
 #pragma unroll
-                for (int c = 0; c < CB; ++c)
-                    if (c < kn) s_l[k0 + lane + n * (k0 + c)] = (c <= lane) ? row[c] : 0.0;
+                for (int c = j + 1; c < CB; ++c) row[c] -= row[j] * lane_value(row[j], c);
+            }
+            if (lane < CB)
+#pragma unroll
+                for (int c = 0; c < CB; ++c) s_l[k0 + lane + ld * (k0 + c)] = (c <= lane) ? row[c] : 0.0;
         }
         __syncthreads();
-        // 2. panel rows i >= k0 + kn: forward substitution against the block
-        for (int i = k0 + kn + tid; i < n; i += CHOL_THREADS) {
+        if (t0 >= np) break;
+        // 2. panel rows i >= t0: forward substitution against the block
+        for (int i = t0 + tid; i < np; i += NTH) {
             double x[CB];
 #pragma unroll
             for (int c = 0; c < CB; ++c) {
-                if (c < kn) {
-                    double sacc = s_l[i + n * (k0 + c)];
+                double sacc = s_l[i + ld * (k0 + c)];
 #pragma unroll
-                    for (int d = 0; d < CB; ++d)
-                        if (d < c) sacc -= x[d] * s_l[k0 + c + n * (k0 + d)];
-                    x[c] = sacc * s_rd[k0 + c];
+                for (int d = 0; d < c; ++d) sacc -= x[d] * s_l[k0 + c + ld * (k0 + d)];
+                x[c] = sacc * s_rd[k0 + c];
+            }
+#pragma unroll
+            for (int c = 0; c < CB; ++c) s_l[i + ld * (k0 + c)] = x[c];
+        }
+        __syncthreads();
+        // 3. trailing update A(bi, bj) -= P(bi) P(bj)^T on the matrix cores,
+        //    lower-triangle tiles bi >= bj > kb, one tile per wave at a time
+        const int nt = nb - kb - 1;
+        for (int q = wave; q < nt * (nt + 1) / 2; q += NW) {
+            int bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
+            const int bj = q - bi * (bi + 1) / 2;
+            const int ri = t0 + CB * bi, cj = t0 + CB * bj;
+            f64x4 acc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[v] = s_l[ri + tg + 4 * v + ld * (cj + tr)];
+            // A operand: P(ri.., k) = s_l[ri + i + ld * (k0 + k)];  B operand:
+            // P^T(k, cj..) = s_l[cj + j + ld * (k0 + k)], i.e. b(k, j) with ldb swapped
+            {
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const double a = -s_l[ri + tr + ld * (k0 + 4 * kk + tg)];
+                    const double b = s_l[cj + tr + ld * (k0 + 4 * kk + tg)];
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                 }
             }
 #pragma unroll
-            for (int c = 0; c < CB; ++c)
-                if (c < kn) s_l[i + n * (k0 + c)] = x[c];
-        }
-        __syncthreads();
-        // 3. trailing update of the lower part
-        const int t0 = k0 + kn, w = n - t0;
-        for (int e = tid; e < w * w; e += CHOL_THREADS) {
-            const int i = t0 + e % w, j = t0 + e / w;
-            if (i < j) continue;
-            double sacc = 0.0;
-#pragma unroll
-            for (int c = 0; c < CB; ++c)
-                if (c < kn) sacc += s_l[i + n * (k0 + c)] * s_l[j + n * (k0 + c)];
-            s_l[i + n * j] -= sacc;
+            for (int v = 0; v < 4; ++v) s_l[ri + tg + 4 * v + ld * (cj + tr)] = acc[v];
         }
         __syncthreads();
     }
     if (bad && flag) flag[0] = 2;
     if (Rout)
-        for (int e = tid; e < n * n; e += CHOL_THREADS) {
-            int i = e % n, j = e / n;  // R(i, j) = L(j, i)
-            Rout[e] = (i <= j) ? s_l[j + n * i] : 0.0;
-        }
+        for (int j = wave; j < n; j += NW)       // R(i, j) = L(j, i)
+            for (int i = lane; i < n; i += 64) Rout[i + (int64_t)n * j] = (i <= j) ? s_l[j + ld * i] : 0.0;
     __syncthreads();
     // in-place inverse, block columns from the last one
-    const int nb = (n + CB - 1) / CB;
     for (int kb = nb - 1; kb >= 0; --kb) {
-        const int k0 = kb * CB, kn = min(CB, n - k0), t0 = k0 + kn;
+        const int k0 = kb * CB, t0 = k0 + CB;
         // D^{-1} of the diagonal block (lower), one thread per column
-        if (tid < kn) {
+        if (tid < CB) {
             const int c = tid;
             double x[CB];
 #pragma unroll
             for (int r = 0; r < CB; ++r) {
-                if (r < kn) {
-                    double sacc = (r == c) ? 1.0 : 0.0;
+                double sacc = (r == c) ? 1.0 : 0.0;
 #pragma unroll
-                    for (int d = 0; d < CB; ++d)
-                        if (d < r) sacc -= s_l[k0 + r + n * (k0 + d)] * x[d];
-                    x[r] = (r < c) ? 0.0 : sacc * s_rd[k0 + r];
+                for (int d = 0; d < r; ++d) sacc -= s_l[k0 + r + ld * (k0 + d)] * x[d];
+                x[r] = (r < c) ? 0.0 : sacc * s_rd[k0 + r];
+            }
+#pragma unroll
+            for (int r = 0; r < CB; ++r) s_dinv[r + CB * c] = x[r];
+        }
+        // T(bi) = sum_{bj = kb+1..bi} Linv(bi, bj) L(bj, kb): one row tile per wave
+        for (int bi = kb + 1 + wave; bi < nb; bi += NW) {
+            const int ri = CB * bi;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int bj = kb + 1; bj <= bi; ++bj) {
+                const int cj = CB * bj;
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const double a = s_l[ri + tr + ld * (cj + 4 * kk + tg)];   // Linv(ri + r, cj + k)
+                    const double b = s_l[cj + 4 * kk + tg + ld * (k0 + tr)];   // L(cj + k, k0 + c)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
                 }
             }
 #pragma unroll
-            for (int r = 0; r < CB; ++r)
-                if (r < kn) s_dinv[r + CB * c] = x[r];
-        }
-        // T(i, c) = sum_{j in [t0, i]} Linv(i, j) L(j, k0 + c) for rows i >= t0
-        for (int e = tid; e < (n - t0) * kn; e += CHOL_THREADS) {
-            const int i = t0 + e % (n - t0), c = e / (n - t0);
-            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-            int j = t0;
-            for (; j + 3 <= i; j += 4) {
-                s0 += s_l[i + n * j] * s_l[j + n * (k0 + c)];
-                s1 += s_l[i + n * (j + 1)] * s_l[j + 1 + n * (k0 + c)];
-                s2 += s_l[i + n * (j + 2)] * s_l[j + 2 + n * (k0 + c)];
-                s3 += s_l[i + n * (j + 3)] * s_l[j + 3 + n * (k0 + c)];
-            }
-            for (; j <= i; ++j) s0 += s_l[i + n * j] * s_l[j + n * (k0 + c)];
-            s_tmp[(i - t0) + (n - t0) * c] = (s0 + s1) + (s2 + s3);
+            for (int v = 0; v < 4; ++v) s_tmp[(ri - t0) + tg + 4 * v + np * tr] = acc[v];
         }
         __syncthreads();
-        // Linv(i, k0 + c) = -sum_d T(i, d) Dinv(d, c);  diagonal block = Dinv
-        for (int e = tid; e < (n - t0) * kn; e += CHOL_THREADS) {
-            const int i = t0 + e % (n - t0), c = e / (n - t0);
-            double sacc = 0.0;
+        // Linv(bi, kb) = -T(bi) Dinv;  Linv(kb, kb) = Dinv
+        for (int bi = kb + 1 + wave; bi < nb; bi += NW) {
+            const int ri = CB * bi;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int d = 0; d < CB; ++d)
-                if (d >= c && d < kn) sacc += s_tmp[(i - t0) + (n - t0) * d] * s_dinv[d + CB * c];
-            s_l[i + n * (k0 + c)] = -sacc;
+            for (int kk = 0; kk < 4; ++kk) {
+                const double a = -s_tmp[(ri - t0) + tr + np * (4 * kk + tg)];
+                const double b = s_dinv[(4 * kk + tg) + CB * tr];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) s_l[ri + tg + 4 * v + ld * (k0 + tr)] = acc[v];
         }
-        for (int e = tid; e < kn * kn; e += CHOL_THREADS) {
-            const int r = e % kn, c = e / kn;
-            s_l[k0 + r + n * (k0 + c)] = (r >= c) ? s_dinv[r + CB * c] : 0.0;
+        if (tid < CB * CB) {
+            const int r = tid % CB, c = tid / CB;
+            s_l[k0 + r + ld * (k0 + c)] = (r >= c) ? s_dinv[r + CB * c] : 0.0;
         }
         __syncthreads();
     }
-    for (int e = tid; e < n * n; e += CHOL_THREADS) {
-        int i = e % n, j = e / n;  // Rinv(i, j) = Linv(j, i)
-        Rinv[e] = (i <= j) ? s_l[j + n * i] : 0.0;
-    }
+    for (int j = wave; j < n; j += NW)           // Rinv(i, j) = Linv(j, i)
+        for (int i = lane; i < n; i += 64) Rinv[i + (int64_t)n * j] = (i <= j) ? s_l[j + ld * i] : 0.0;
 }
-
 
 }  // namespace sth

@@ -183,11 +183,15 @@ size_t eig_ws_bytes(int64_t n) {
 //     shifted Cholesky-QR, three passes for the last basis, two before), then
 //     Rayleigh-Ritz: Jacobi on T = Q^T S Q and U = Q W(:, :R), with the sign
 //     rule applied to U.
-//   otherwise: Jacobi on S with A and V in the workspace (slow; large R only).
+//   otherwise (large R, or R above the rank bound of S): Jacobi on S with A
+//   and V in the workspace.
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
-                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s) {
-    if (!use_si(n, R)) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
-    const int64_t p = si_block(n, R);
+                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound) {
+    // rank(S) <= rank_bound: a block wider than that would be rank deficient
+    // (Cholesky-QR breaks down), so the block shrinks to the bound, and a
+    // request of more than rank_bound vectors goes to the direct solver
+    if (!use_si(n, R) || R > rank_bound) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
+    const int64_t p = std::min(si_block(n, R), rank_bound);
     SiWs w = si_layout((char *)ws, n, p);
     const int ni = (int)n, pi = (int)p;
     hipError_t e;

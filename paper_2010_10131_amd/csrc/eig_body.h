@@ -93,9 +93,19 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
     double *A = s_e;                         // ne x ne, leading dimension ne
     double *V = VLDS ? s_e + ne * ne : Vg;   // n x ne, leading dimension n
     const int tid = threadIdx.x;
-    for (int e = tid; e < ne * ne; e += EIG_THREADS) {
-        const int i = e % ne, j = e / ne;
-        A[e] = (i < n && j < n) ? 0.5 * (S[i + n * j] + S[j + n * i]) : 0.0;
+    for (int e0 = tid; e0 < ne * ne; e0 += 4 * EIG_THREADS) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {   // 8 global loads in flight per thread
+            const int e = e0 + u * EIG_THREADS;
+            const int i = e % ne, j = e / ne;
+            v[u] = (e < ne * ne && i < n && j < n) ? 0.5 * (S[i + n * j] + S[j + n * i]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * EIG_THREADS;
+            if (e < ne * ne) A[e] = v[u];
+        }
     }
     for (int e = tid; e < n * ne; e += EIG_THREADS) {
         const int i = e % n, j = e / n;

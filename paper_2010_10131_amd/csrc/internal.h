@@ -33,7 +33,7 @@ hipError_t gram_launch(int dtype, int prec, const void *A, const void *B, int64_
 // Eigensolver (eig.hip)
 size_t eig_ws_bytes(int64_t n);
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
-                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s);
+                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound);
 
 // Small FP64 LA and reductions (la.hip)
 int gemm_splits(int m, int n, int k);
@@ -64,7 +64,7 @@ struct BatchStep {
     int64_t kper, gram_wg;
     int32_t nkc, nbi, nblocks, wt;
     int32_t nchunks, ntiles, rtb, contig;
-    int32_t tensor, pad;
+    int32_t tensor, sib;   // sib: subspace-iteration block (I > 128), capped at L * M
 };
 struct BatchLaunch {
     const int32_t *list;  // device: indices into the step's descriptors
@@ -84,8 +84,8 @@ struct BatchStepPlan {
     BatchLaunch prep;
 };
 size_t batch_gram_lds(int prec, int wt);
-size_t batch_eig_lds(int64_t n, int64_t R);
-size_t batch_eig_scratch(int64_t n, int64_t R);
+size_t batch_eig_lds(int64_t n, int64_t p);   // p: the step's subspace block (0 for n <= 128)
+size_t batch_eig_scratch(int64_t n, int64_t p);
 hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int gram_prec,
                              int ttm_prec, int order, int mode, char *ws, const void *const *Xp,
                              void *const *Cp, double *const *Up, int64_t *flag, int max_sweeps,

@@ -157,3 +157,14 @@ def test_batched_tiles_validation():
         with pytest.raises(SthError) as e:
             api.BatchPlan(sh, tiles=bad)
         assert e.value.status == STH_ERR_INVALID, bad
+
+
+def test_batched_plan_rejects_rank_above_the_gram_rank_bound():
+    """Mode 3 of (33, 20, 150) with ranks (5, 3, 24): the Gram has rank <= 15
+    < 24 and I_3 > 128, which only the single-tensor path solves."""
+    from paper_2010_10131_amd import api
+    from paper_2010_10131_amd._lib import SthError, STH_ERR_UNSUPPORTED
+    with pytest.raises(SthError) as e:
+        api.BatchPlan([((33, 20, 150), (5, 3, 24))])
+    assert e.value.status == STH_ERR_UNSUPPORTED
+    assert api.BatchPlan([((33, 20, 150), (5, 4, 18))]).workspace_bytes > 0

@@ -267,6 +267,23 @@ def test_decomposition_fp64_edge_cases(api, dims, ranks, order):
     assert t1 <= 1e-11 and t2 <= 1e-11, (t1, t2)
 
 
+@pytest.mark.parametrize("dims,ranks", [
+    ((33, 20, 150), (5, 3, 24)),   # mode 3: rank(Gram) <= 15 < R = 24 (direct solver, n > 128)
+    ((33, 20, 150), (5, 4, 18)),   # mode 3: rank(Gram) <= 20 < block 40 (block capped at 20)
+])
+def test_gram_rank_below_the_subspace_block(api, dims, ranks):
+    """Ranks at or above what the earlier truncations leave: only X^ and
+    ||G|| are defined (the completing eigenvectors are arbitrary), and the
+    factors stay orthonormal."""
+    X = wl.lowrank_plus_noise(dims, ranks, "none", 1e-4, 11, "float32")
+    G, U, _ = api.sthosvd(api.to_device(X), ranks, "fp64", "fp32")
+    Go, Uo, _ = oracle.sthosvd(X, ranks)
+    t1, t2, _, Un = t1_t2(api, X, G, U, Go, Uo)
+    assert t1 <= 1e-5 and t2 <= 1e-5, (t1, t2)
+    for n in range(3):
+        np.testing.assert_allclose(Un[n].T @ Un[n], np.eye(ranks[n]), atol=1e-12)
+
+
 @pytest.mark.parametrize("variant_dims,ranks,per_mode", [
     ((24, 20, 18), (4, 5, 3), ("als", "als", "als")),
     ((24, 20, 18), (4, 5, 3), ("eig", "als", "eig")),
