@@ -229,7 +229,7 @@ sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R, 
  * U (device, n x R FP64, orthonormal, largest-magnitude entry of each column
  * positive) and lam (device, R values, descending; may be NULL).  n <= 128:
  * parallel cyclic Jacobi on S; n > 128 with a subspace block
- * p = max(R + 16, 1.5 R) (rounded up to 8) <= 96: subspace iteration on a
+ * p = R + 16 (rounded up to 8) <= 96: subspace iteration on a
  * seeded Gaussian block with Rayleigh-Ritz (S must then have rank >= p; a
  * Gram matrix of rank below p goes through sthosvd_run, which passes the rank
  * bound of each mode); otherwise Jacobi on S in the workspace.  ws: device

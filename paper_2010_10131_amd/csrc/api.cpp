@@ -71,7 +71,7 @@ static const int64_t MAX_EIG_N = SEL_MAX_EIG_N;   // I_n x I_n Gram and eigensol
 static const int64_t EIG_DIRECT_MAX_HOST = 128;
 static const int64_t SI_BLOCK_MAX_HOST = 96;
 static int64_t si_block_host_api(int64_t n, int64_t R) {
-    int64_t p = std::max<int64_t>(R + 16, (3 * R + 1) / 2);
+    int64_t p = R + 16;   // the same rule as the device side
     p = (p + 7) / 8 * 8;
     return std::min(p, n);
 }

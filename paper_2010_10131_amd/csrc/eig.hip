@@ -125,7 +125,8 @@ hipError_t cholqr_pass(const double *A, double *Q, int n, int p, double shift_re
 // passes = 3: shifted Cholesky-QR3 (orthonormal to working accuracy for
 // condition numbers up to ~1/eps); passes = 2: the shifted pass and one plain
 // pass, enough for the intermediate bases of the subspace iteration, which
-// only need to be well conditioned.
+// only need to be well conditioned (the shifted pass alone leaves them too
+// ill-conditioned for the next product's orthonormalization).
 hipError_t orth(double *A, double *Q, int n, int p, int passes, SiWs &w, int64_t *flag, hipStream_t s) {
     hipError_t e;
     const double shift = 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16;
@@ -178,7 +179,7 @@ size_t eig_ws_bytes(int64_t n) {
 
 // R leading eigenpairs of the symmetric n x n matrix S.
 //   n <= 128: cyclic Jacobi on S itself (one workgroup, LDS).
-//   n > 128 with a block p = max(R + 16, 1.5 R) <= 96: subspace iteration
+//   n > 128 with a block p = R + 16 (rounded up to 8) <= 96: subspace iteration
 //     Q <- orth(S Q) from a seeded Gaussian block (SI_ITERS = 3 times; orth is
 //     shifted Cholesky-QR, three passes for the last basis, two before), then
 //     Rayleigh-Ritz: Jacobi on T = Q^T S Q and U = Q W(:, :R), with the sign

@@ -12,7 +12,7 @@ constexpr int EIG_LDS_AV = 150 * 1024;   // LDS bytes available for Jacobi's A a
 
 // Subspace-iteration block size for n > EIG_DIRECT_MAX.
 __host__ __device__ inline int64_t si_block_dev(int64_t n, int64_t R) {
-    int64_t p = (R + 16 > (3 * R + 1) / 2) ? R + 16 : (3 * R + 1) / 2;
+    int64_t p = R + 16;   // 16 guard vectors beyond the R wanted ones
     p = (p + 7) / 8 * 8;
     return p < n ? p : n;
 }
