@@ -70,6 +70,14 @@ __global__ __launch_bounds__(64 * WAVES) void ttm_kernel(
                                                     nrowblocks, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
+template <int PREC, int NT, int CPW>
+__global__ __launch_bounds__(64 * KS_WAVES) void ttm_ks_kernel(
+    const float *__restrict__ Y, const uint4 *__restrict__ Uq, float *__restrict__ Z, int64_t K,
+    int64_t Rout, int64_t P, int nchunks, int ntiles, int64_t nblocks) {
+    ttm_ks_body<PREC, NT, CPW>(Y, Uq, Z, K, Rout, P, nchunks, ntiles, nblocks, blockIdx.x, gridDim.x,
+                               blockIdx.y);
+}
+
 // ---------------------------------------------------------------- host ----
 
 size_t ttm_prep_bytes(int64_t K, int64_t Rout, int prec) {
@@ -123,6 +131,24 @@ hipError_t launch_ttm_t(const T *Y, const uint4 *Uq, T *Z, int64_t L, int64_t K,
     return hipGetLastError();
 }
 
+template <int PREC, int CPW>
+hipError_t launch_ttm_ks(const float *Y, const uint4 *Uq, float *Z, int64_t K, int64_t Rout, int64_t M,
+                         hipStream_t s) {
+    constexpr int NT = 2;
+    const int nchunks = (int)((K + KC - 1) / KC);
+    const int ntiles = (int)((Rout + 15) / 16);
+    const int nrb = (ntiles + 3) / 4;
+    const int64_t nblocks = (M + 16 * NT - 1) / (16 * NT);
+    const size_t lds = ttm_ks_lds(NT);
+    const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(nblocks, (int64_t)device_cu_count()));
+    auto kern = ttm_ks_kernel<PREC, NT, CPW>;
+    hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)wgs, (unsigned)nrb), dim3(64 * KS_WAVES), lds, s, Y, Uq, Z, K,
+                       Rout, M, nchunks, ntiles, nblocks);
+    return hipGetLastError();
+}
+
 template <typename T, int PREC, int RTB>
 hipError_t launch_ttm_r(const T *Y, const uint4 *Uq, T *Z, int64_t L, int64_t K, int64_t Rout,
                         int64_t M, hipStream_t s) {
@@ -130,6 +156,14 @@ hipError_t launch_ttm_r(const T *Y, const uint4 *Uq, T *Z, int64_t L, int64_t K,
     const size_t lds = (size_t)nchunks * RTB * Frag<PREC>::NQ * 64 * 16;
     const bool contig = (L == 1) && (K % (16 / sizeof(T)) == 0) &&
                         ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
+    // contiguous rows of 256 < K <= 512 values in FP32 storage: the K-split
+    // kernel (all eight waves busy, whole row blocks streamed)
+    if constexpr (sizeof(T) == 4 && (PREC == P_FP32 || PREC == P_BF16X3) && RTB == 4) {
+        const int nchunks = (int)((K + KC - 1) / KC);
+        if (contig && nchunks > 8 && nchunks <= 16)
+            return launch_ttm_ks<PREC, 2>(reinterpret_cast<const float *>(Y), Uq, reinterpret_cast<float *>(Z),
+                                          K, Rout, M, s);
+    }
     // row tiles per wave: keeps a lane under 256 VGPRs (8 waves per workgroup)
     constexpr int NT = (PREC == P_FP64) ? (RTB == 1 ? 2 : 1) : (RTB == 1 ? 4 : 2);
     if (lds <= TTM_LDS_MAX) {

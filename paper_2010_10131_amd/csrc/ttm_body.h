@@ -191,3 +191,165 @@ __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *_
 }
 
 }  // namespace sth
+
+namespace sth {
+
+// ---------------------------------------------------------------------------
+// K-split TTM for the contiguous view (L = 1: row p of Y is K consecutive
+// values).  The eight waves of a workgroup share every block of 16 * NT rows:
+// wave w takes the CPW chunks [w * CPW, (w + 1) * CPW) of the K range, holds
+// the matching factor fragments in registers for the whole run, and
+// multiplies its slice of the block's rows; the eight partial 16*NT x 64
+// results meet in LDS (double-buffered, one barrier per block) and are summed
+// into Z in a fixed order.  So a workgroup streams whole blocks of
+// consecutive rows (16 * NT * K * 4 bytes) and keeps the next block's loads
+// in flight while the current one is reduced.
+constexpr int KS_WAVES = 8;
+constexpr int KS_RS = 68;  // LDS row stride of the partials (64 columns + 4: no bank conflicts)
+
+__host__ __device__ inline size_t ttm_ks_lds(int nt) { return (size_t)2 * KS_WAVES * 16 * nt * KS_RS * 4; }
+
+// PERM: lane group g holds k = 4g .. 4g+3 and 16 + 4g .. 16 + 4g + 3 of each
+// 32-wide chunk (the factor quads are prepared with the same order), so the
+// four groups of a row read its 64 bytes in one contiguous run per load.
+template <int PREC, int NT, int CPW, bool PERM = false>
+__device__ __forceinline__ void ttm_ks_body(const float *__restrict__ Y, const uint4 *__restrict__ Uq,
+                                            float *__restrict__ Z, int64_t K, int64_t Rout, int64_t P,
+                                            int nchunks, int ntiles, int64_t nblocks, int64_t wg,
+                                            int64_t nwg, int rb) {
+    constexpr int NQ = Frag<PREC>::NQ;
+    constexpr int RTB = 4;
+    constexpr int ROWS = 16 * NT;
+    extern __shared__ float s_part[];  // [2][KS_WAVES][ROWS][KS_RS]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4;
+    const int rt0 = rb * RTB;
+    const int c0 = wave * CPW;
+
+    // this wave's factor fragments: chunks c0 .. c0 + CPW - 1, r-tiles of block rb
+    FragQ<PREC> uf[CPW][RTB];
+#pragma unroll
+    for (int j = 0; j < CPW; ++j)
+#pragma unroll
+        for (int rt = 0; rt < RTB; ++rt) {
+            const int c = c0 + j, rtg = rt0 + rt;
+            const bool ok = c < nchunks && rtg < ntiles;
+            const uint4 *src = Uq + (((int64_t)(ok ? c : 0) * ntiles + (ok ? rtg : 0)) * NQ) * 64 + lane;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) uf[j][rt].q[q] = ok ? src[q * 64] : make_uint4(0, 0, 0, 0);
+        }
+
+    auto load_block = [&](int64_t blk, float (&x)[CPW][NT][8]) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int64_t p = blk * ROWS + 16 * nt + (lane & 15);
+            const int64_t pc = p < P ? p : P - 1;
+#pragma unroll
+            for (int j = 0; j < CPW; ++j) {
+                const int64_t kb = (int64_t)(c0 + j) * KC + 8 * g;
+                if (c0 + j < nchunks) {
+                    if (PERM) {
+                        const int64_t kc = (int64_t)(c0 + j) * KC;
+                        const float *src = Y + K * pc + kc + 4 * g;
+                        if (kc + KC <= K) {
+                            const float4 u = *reinterpret_cast<const float4 *>(src);
+                            const float4 w = *reinterpret_cast<const float4 *>(src + 16);
+                            x[j][nt][0] = u.x; x[j][nt][1] = u.y; x[j][nt][2] = u.z; x[j][nt][3] = u.w;
+                            x[j][nt][4] = w.x; x[j][nt][5] = w.y; x[j][nt][6] = w.z; x[j][nt][7] = w.w;
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 8; ++e) {
+                                const int64_t k = kc + 4 * g + (e < 4 ? e : 12 + e);
+                                x[j][nt][e] = k < K ? Y[K * pc + k] : 0.f;
+                            }
+                        }
+                    } else {
+                        ttm_load_chunk<float, true>(Y, K * pc, 1, K, kb, x[j][nt]);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) x[j][nt][e] = 0.f;
+                }
+            }
+        }
+    };
+    auto compute_store = [&](const float (&x)[CPW][NT][8], int buf) {
+        f32x4 acc[NT][RTB];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt) acc[nt][rt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < CPW; ++j) {
+            Frag<PREC> yb[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) make_frag(x[j][nt], yb[nt]);
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) mma_frag(uf[j][rt].f, yb[nt], acc[nt][rt]);
+        }
+        // partial D[r][p]: lane holds r = 16 rt + 4 g + v, p = 16 nt + lane % 16
+        float *dst = s_part + ((size_t)(buf * KS_WAVES + wave) * ROWS) * KS_RS;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int rt = 0; rt < RTB; ++rt)
+                *reinterpret_cast<float4 *>(dst + (16 * nt + (lane & 15)) * KS_RS + 16 * rt + 4 * g) =
+                    make_float4(acc[nt][rt][0], acc[nt][rt][1], acc[nt][rt][2], acc[nt][rt][3]);
+    };
+    auto reduce_store = [&](int64_t blk, int buf) {
+        // ROWS x 64 outputs, four consecutive r per thread, waves summed in order
+        for (int o = threadIdx.x; o < ROWS * 16; o += 64 * KS_WAVES) {
+            const int pl = o >> 4, r4 = (o & 15) * 4;
+            const float *src = s_part + ((size_t)(buf * KS_WAVES) * ROWS + pl) * KS_RS + r4;
+            float4 s = *reinterpret_cast<const float4 *>(src);
+#pragma unroll
+            for (int w = 1; w < KS_WAVES; ++w) {
+                const float4 t = *reinterpret_cast<const float4 *>(src + (size_t)w * ROWS * KS_RS);
+                s.x += t.x;
+                s.y += t.y;
+                s.z += t.z;
+                s.w += t.w;
+            }
+            const int64_t p = blk * ROWS + pl;
+            const int64_t r = (int64_t)rt0 * 16 + r4;
+            if (p < P && r < Rout) {
+                float *z = Z + r + Rout * p;
+                if ((Rout & 3) == 0) {
+                    *reinterpret_cast<float4 *>(z) = s;
+                } else {
+                    z[0] = s.x;
+                    if (r + 1 < Rout) z[1] = s.y;
+                    if (r + 2 < Rout) z[2] = s.z;
+                    if (r + 3 < Rout) z[3] = s.w;
+                }
+            }
+        }
+    };
+
+    // three register buffers: while block b is multiplied, blocks b + nwg and
+    // b + 2 nwg are in flight
+    float xa[CPW][NT][8], xb[CPW][NT][8], xc[CPW][NT][8];
+    int64_t blk = wg;
+    if (blk < nblocks) load_block(blk, xa);
+    if (blk + nwg < nblocks) load_block(blk + nwg, xb);
+    int buf = 0;
+    auto step = [&](float (&cur)[CPW][NT][8], float (&nx2)[CPW][NT][8]) {
+        if (blk + 2 * nwg < nblocks) load_block(blk + 2 * nwg, nx2);
+        compute_store(cur, buf);
+        __syncthreads();
+        reduce_store(blk, buf);
+        buf ^= 1;
+        blk += nwg;
+    };
+    while (blk < nblocks) {
+        step(xa, xc);
+        if (blk >= nblocks) break;
+        step(xb, xa);
+        if (blk >= nblocks) break;
+        step(xc, xb);
+    }
+}
+
+}  // namespace sth
