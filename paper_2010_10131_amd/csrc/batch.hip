@@ -65,9 +65,9 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const BatchStep *__rest
     const int64_t P = d.L * d.M;
     if (d.L == 1 && WT >= 2) {
         if ((d.I & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0))
-            gram_l1_body<PREC, WT, true>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
+            gram_l1_body<PREC, WT, WT, 2, 2, true>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
         else
-            gram_l1_body<PREC, WT, false>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
+            gram_l1_body<PREC, WT, WT, 2, 2, false>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
     } else {
         gram_body<float, PREC, WT, true>(Y, Y, d.L, d.I, d.I, P, d.kper, d.nkc, d.nbi, d.nbi,
                                         d.nblocks, d.gram_wg, local, part);

@@ -260,14 +260,18 @@ __device__ __forceinline__ void l1_store(uint8_t *slab, int TB, int g, int row, 
     }
 }
 
-template <int PREC, int WT, bool VEC4>
+// Waves form a WI x WJ grid over the TB x TB output block, each owning
+// WTI x WTJ tiles of 16 x 16 (TB = 16 WTI WI = 16 WTJ WJ).
+template <int PREC, int WTI, int WTJ, int WI, int WJ, bool VEC4>
 __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_t I, int64_t P,
                                              int64_t kper, int nkc, int nblocks, int64_t total_wg,
                                              int64_t lid, double *__restrict__ partials) {
-    constexpr int TB = 32 * WT;
+    constexpr int TB = 16 * WTI * WI;
+    static_assert(TB == 16 * WTJ * WJ, "square output block");
+    constexpr int NTH = 64 * WI * WJ;
     constexpr int NQ = Frag<PREC>::NQ;
     constexpr int IQ = TB / 4;          // 16-byte column quads per row
-    constexpr int PH = 256 / IQ;        // rows covered by one pass of the workgroup
+    constexpr int PH = NTH / IQ;        // rows covered by one pass of the workgroup
     constexpr int LPT = KC / PH;        // rows (loads) per thread per chunk
     constexpr int SLAB = NQ * 4 * TB * 16;  // bytes of one operand buffer
     typedef typename Acc<PREC>::type AccT;
@@ -288,8 +292,9 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
     const int nch = (int)((pend - pbeg + KC - 1) / KC);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wi = wave >> 1, wj = wave & 1;
-    const bool active = !(diag && wi < wj);
+    const int wi = wave / WJ, wj = wave % WJ;
+    // a wave whose tiles lie wholly above the diagonal of a diagonal block idles
+    const bool active = !(diag && (wi + 1) * 16 * WTI <= wj * 16 * WTJ);
     const int iq = tid % IQ, ph = tid / IQ;
     const int g_st = ph % 4, slot0 = LPT * (ph / 4);
 
@@ -324,12 +329,12 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
         }
     };
 
-    AccT acc[WT][WT];
-    f64x4 acc64[WT][WT];
+    AccT acc[WTI][WTJ];
+    f64x4 acc64[WTI][WTJ];
 #pragma unroll
-    for (int x = 0; x < WT; ++x)
+    for (int x = 0; x < WTI; ++x)
 #pragma unroll
-        for (int y = 0; y < WT; ++y) {
+        for (int y = 0; y < WTJ; ++y) {
             acc[x][y] = AccT{0, 0, 0, 0};
             acc64[x][y] = f64x4{0, 0, 0, 0};
         }
@@ -339,32 +344,32 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
         const uint4 *sA = reinterpret_cast<const uint4 *>(lds + (size_t)(buf * 2 + 0) * SLAB);
         const uint4 *sB = reinterpret_cast<const uint4 *>(lds + (size_t)(buf * 2 + (diag ? 0 : 1)) * SLAB);
         const int g = lane >> 4;
-        Frag<PREC> fa[WT], fb[WT];
+        Frag<PREC> fa[WTI], fb[WTJ];
 #pragma unroll
-        for (int x = 0; x < WT; ++x) {
+        for (int x = 0; x < WTI; ++x) {
             FragQ<PREC> t;
-            const int row = wi * (16 * WT) + 16 * x + (lane & 15);
+            const int row = wi * (16 * WTI) + 16 * x + (lane & 15);
 #pragma unroll
             for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sA[(qq * 4 + g) * TB + row];
             fa[x] = t.f;
         }
 #pragma unroll
-        for (int y = 0; y < WT; ++y) {
+        for (int y = 0; y < WTJ; ++y) {
             FragQ<PREC> t;
-            const int row = wj * (16 * WT) + 16 * y + (lane & 15);
+            const int row = wj * (16 * WTJ) + 16 * y + (lane & 15);
 #pragma unroll
             for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sB[(qq * 4 + g) * TB + row];
             fb[y] = t.f;
         }
 #pragma unroll
-        for (int x = 0; x < WT; ++x)
+        for (int x = 0; x < WTI; ++x)
 #pragma unroll
-            for (int y = 0; y < WT; ++y) mma_frag(fa[x], fb[y], acc[x][y]);
+            for (int y = 0; y < WTJ; ++y) mma_frag(fa[x], fb[y], acc[x][y]);
         if (!F64ACC && ((c + 1) % GRAM_FLUSH == 0 || c + 1 == nch)) {
 #pragma unroll
-            for (int x = 0; x < WT; ++x)
+            for (int x = 0; x < WTI; ++x)
 #pragma unroll
-                for (int y = 0; y < WT; ++y) {
+                for (int y = 0; y < WTJ; ++y) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) acc64[x][y][v] += (double)acc[x][y][v];
                     acc[x][y] = AccT{0, 0, 0, 0};
@@ -412,13 +417,13 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
     if (!active) return;
     double *dst = partials + ((int64_t)kc * nblocks + q) * (int64_t)TB * TB;
 #pragma unroll
-    for (int x = 0; x < WT; ++x)
+    for (int x = 0; x < WTI; ++x)
 #pragma unroll
-        for (int y = 0; y < WT; ++y) {
-            const int jl = wj * (16 * WT) + 16 * y + (lane & 15);
+        for (int y = 0; y < WTJ; ++y) {
+            const int jl = wj * (16 * WTJ) + 16 * y + (lane & 15);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int il = wi * (16 * WT) + 16 * x + drow<PREC>(lane >> 4, v);
+                const int il = wi * (16 * WTI) + 16 * x + drow<PREC>(lane >> 4, v);
                 dst[il + TB * jl] = F64ACC ? (double)acc[x][y][v] : acc64[x][y][v];
             }
         }
