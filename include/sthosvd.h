@@ -225,6 +225,30 @@ sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R, 
                       int32_t prec, const void *Y, const double *U, int32_t transpose_u, void *Z,
                       void *ws, size_t ws_bytes, sth_stream_t stream);
 
+/* Device bytes of a prepared (pre-split) I_n x R factor for precision prec. */
+size_t ttm_factor_bytes(int64_t I, int64_t R, int32_t prec);
+
+/* Splits the FP64 factor U (device, I_n x R, or R x I_n with transpose_u = 1,
+ * as in ttm_mode_n) once into the matrix-core operand layout that the TTM
+ * kernels read for precision prec (one, two, three or six bf16/FP32/FP64
+ * pieces per entry, Section IV's split of the factor).  out: device buffer
+ * of ttm_factor_bytes(I, R, prec) bytes, owned by the caller, opaque; it stays
+ * valid for any tensor whose mode n has I_n entries, as long as U does not
+ * change.  For callers that apply one factor to many tensors.  Errors:
+ * STH_ERR_INVALID (sizes, prec, NULL), STH_ERR_LAYOUT (unaligned pointer),
+ * STH_ERR_NOMEM (out_bytes too small). */
+sth_status ttm_factor_prepare(int64_t I, int64_t R, int32_t prec, const double *U,
+                              int32_t transpose_u, void *out, size_t out_bytes,
+                              sth_stream_t stream);
+
+/* ttm_mode_n with a factor prepared by ttm_factor_prepare for the same I_n,
+ * R and prec: one kernel launch, no workspace.  Gives the same bits as
+ * ttm_mode_n with the unprepared factor.  uprep_bytes below
+ * ttm_factor_bytes(I_n, R, prec) is STH_ERR_INVALID. */
+sth_status ttm_mode_n_prepared(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                               int32_t dtype, int32_t prec, const void *Y, const void *Uprep,
+                               size_t uprep_bytes, void *Z, sth_stream_t stream);
+
 /* R leading eigenpairs of a symmetric n x n FP64 matrix S (device), in FP64:
  * U (device, n x R FP64, orthonormal, largest-magnitude entry of each column
  * positive) and lam (device, R values, descending; may be NULL).  n <= 128:

@@ -76,6 +76,9 @@ SIGNATURES = {
     "ttt_mode_n": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ttm_mode_n_workspace": (_sz, [_i64, _i64]),
     "ttm_mode_n": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "ttm_factor_bytes": (_sz, [_i64, _i64, _i32]),
+    "ttm_factor_prepare": (ctypes.c_int, [_i64, _i64, _i32, _vp, _i32, _vp, _sz, _vp]),
+    "ttm_mode_n_prepared": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]),
     "eig_leading_workspace": (_sz, [_i64]),
     "eig_leading": (ctypes.c_int, [_i64, _i64, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),
     "tucker_reconstruct_workspace": (_sz, [_i32, _i64p, _i64p, _i32]),

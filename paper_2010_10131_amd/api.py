@@ -18,7 +18,7 @@ from ._lib import PREC, SOLVER, check, i32arr, i64arr, ptrarr
 
 __all__ = [
     "fortran_empty", "to_device", "to_numpy", "Plan", "sthosvd", "gram_mode_n", "ttt_mode_n",
-    "ttm_mode_n", "eig_leading", "tucker_reconstruct", "tucker_error", "sumsq", "mode_step",
+    "ttm_mode_n", "ttm_factor_prepare", "ttm_mode_n_prepared", "eig_leading", "tucker_reconstruct", "tucker_error", "sumsq", "mode_step",
     "selector_features", "selector_predict", "mlp_forward", "mlp_loss_grad", "mlp_adam",
     "BatchPlan",
 ]
@@ -239,6 +239,39 @@ def ttm_mode_n(Y: torch.Tensor, U: torch.Tensor, n: int, prec="fp32",
                        ctypes.c_void_p(U.data_ptr()), 1 if transpose_u else 0,
                        ctypes.c_void_p(Z.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                        _stream()))
+    return Z
+
+
+def ttm_factor_prepare(U: torch.Tensor, prec="fp32", transpose_u: bool = False) -> torch.Tensor:
+    """Splits an FP64 factor once for ttm_mode_n_prepared (opaque uint8 device buffer)."""
+    _need(U, "U")
+    if U.dtype != torch.float64:
+        raise TypeError("factors are FP64")
+    R, k = U.shape if transpose_u else U.shape[::-1]
+    L = _lib.load()
+    nbytes = L.ttm_factor_bytes(k, R, _prec(prec))
+    out = torch.empty(nbytes, dtype=torch.uint8, device=U.device)
+    check(L.ttm_factor_prepare(k, R, _prec(prec), ctypes.c_void_p(U.data_ptr()), 1 if transpose_u else 0,
+                               ctypes.c_void_p(out.data_ptr()), out.numel(), _stream()))
+    return out
+
+
+def ttm_mode_n_prepared(Y: torch.Tensor, Uprep: torch.Tensor, n: int, R: int, prec="fp32",
+                        out: torch.Tensor = None) -> torch.Tensor:
+    """ttm_mode_n with a factor from ttm_factor_prepare (one kernel launch).  `out`
+    (column-major, the dims of Y with dims[n] = R) is written when given."""
+    _need(Y, "Y")
+    _need(Uprep, "Uprep")
+    L = _lib.load()
+    oshape = list(Y.shape)
+    oshape[n] = R
+    Z = out if out is not None else fortran_empty(oshape, Y.dtype, Y.device)
+    if list(Z.shape) != oshape or Z.dtype != Y.dtype:
+        raise ValueError("out has the wrong shape or dtype")
+    _need(Z, "out")
+    check(L.ttm_mode_n_prepared(Y.dim(), i64arr(Y.shape), n, R, _dtype_code(Y), _prec(prec),
+                                ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(Uprep.data_ptr()),
+                                Uprep.numel(), ctypes.c_void_p(Z.data_ptr()), _stream()))
     return Z
 
 

@@ -500,6 +500,42 @@ extern "C" sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, 
     return STH_OK;
 }
 
+extern "C" size_t ttm_factor_bytes(int64_t I, int64_t R, int32_t prec) {
+    if (I < 1 || R < 1 || prec < STH_PREC_FP64 || prec > STH_PREC_BF16X6) return 0;
+    return ttm_prep_bytes(I, R, prec);
+}
+
+extern "C" sth_status ttm_factor_prepare(int64_t I, int64_t R, int32_t prec, const double *U,
+                                         int32_t transpose_u, void *out, size_t out_bytes,
+                                         sth_stream_t stream) {
+    if (I < 1 || R < 1) return fail(STH_ERR_INVALID, "factor %lld x %lld", (long long)I, (long long)R);
+    sth_status st;
+    if ((st = check_dtype_prec(STH_F32, prec, "prec"))) return st;
+    if ((st = check_ptr(U, "U")) || (st = check_ptr(out, "out"))) return st;
+    size_t need = ttm_prep_bytes(I, R, prec);
+    if (out_bytes < need) return fail(STH_ERR_NOMEM, "prepared factor %zu < %zu bytes", out_bytes, need);
+    HIPCHK(ttm_prep_u(U, I, R, transpose_u ? 1 : 0, prec, out, (hipStream_t)stream), "ttm prep");
+    return STH_OK;
+}
+
+extern "C" sth_status ttm_mode_n_prepared(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                                          int32_t dtype, int32_t prec, const void *Y,
+                                          const void *Uprep, size_t uprep_bytes, void *Z,
+                                          sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (n < 0 || n >= order) return fail(STH_ERR_INVALID, "mode %d outside 0..%d", n, order - 1);
+    if (R < 1) return fail(STH_ERR_INVALID, "R < 1");
+    if ((st = check_dtype_prec(dtype, prec, "prec"))) return st;
+    if ((st = check_ptr(Y, "Y")) || (st = check_ptr(Uprep, "Uprep")) || (st = check_ptr(Z, "Z"))) return st;
+    int64_t L, I, M;
+    lim(order, dims, n, L, I, M);
+    size_t need = ttm_prep_bytes(I, R, prec);
+    if (uprep_bytes < need) return fail(STH_ERR_INVALID, "prepared factor %zu < %zu bytes", uprep_bytes, need);
+    HIPCHK(ttm_launch(dtype, prec, Y, Uprep, Z, L, I, R, M, (hipStream_t)stream), "ttm");
+    return STH_OK;
+}
+
 extern "C" size_t eig_leading_workspace(int64_t n) { return n >= 1 ? align_up(eig_ws_bytes(n)) : 0; }
 
 extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double *U, double *lam,

@@ -107,7 +107,7 @@ __global__ void batch_reduce_kernel(const BatchStep *__restrict__ descs,
 __device__ void wg_gemm(int ta, int tb, int m, int n, int k, const double *__restrict__ A,
                         int64_t lda, const double *__restrict__ B, int64_t ldb,
                         double *__restrict__ C, int64_t ldc) {
-    extern __shared__ double s_dyn[];
+    extern __shared__ __align__(16) double s_dyn[];
     double *sA = s_dyn;             // [kk][33]
     double *sB = s_dyn + 32 * 33;   // [kk][33]
     const int tid = threadIdx.x;
@@ -299,7 +299,7 @@ size_t batch_eig_lds(int64_t n, int64_t p) {
 }
 
 size_t batch_eig_scratch(int64_t n, int64_t p) {
-    if (n <= EIG_DIRECT_MAX) return (size_t)2 * n * n * 8;
+    if (n <= EIG_DIRECT_MAX) return std::max((size_t)2 * n * n * 8, jacobi_small_vg(n));
     return (size_t)(3 * n * p + 4 * p * p + 2 * p * p) * 8;
 }
 

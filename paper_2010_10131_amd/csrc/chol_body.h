@@ -51,7 +51,7 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
                                           double shift_rel, double *__restrict__ Rout,
                                           double *__restrict__ Rinv, int64_t *__restrict__ flag) {
     constexpr int NW = NTH / 64;
-    extern __shared__ double s_l[];  // L, column-major, leading dimension ld
+    extern __shared__ __align__(16) double s_l[];  // L, column-major, leading dimension ld
     const int np = chol_np(n), ld = np + 1, nb = np / CB;
     double *s_tmp = s_l + np * ld;   // np x CB
     double *s_rd = s_tmp + np * CB;  // 1 / L(i, i)

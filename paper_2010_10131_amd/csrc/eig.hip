@@ -101,7 +101,7 @@ SiWs si_layout(char *ws, int64_t n, int64_t p) {
     w.T = d; d += p * p;
     w.W = d; d += p * p;
     w.gws = d; d += std::max<size_t>(gemm_ws_bytes((int)p, (int)p, (int)n), gemm_ws_bytes((int)n, (int)p, (int)n)) / 8 + 1;
-    w.jac = (char *)d;
+    w.jac = (char *)(((uintptr_t)d + 255) & ~(uintptr_t)255);   // 16-byte accesses in the Jacobi
     return w;
 }
 

@@ -31,20 +31,35 @@ __device__ __forceinline__ int rr_player(int x, int r, int ne) {
 
 // Rotation (c, s) that annihilates a_pq against the diagonal pair (a_pp,
 // a_qq).  A rotation is skipped (identity, returns false) when a_pq is at
-// the roundoff level: |a_pq| <= rel sqrt(|a_pp| |a_qq|) (its own diagonal
-// pair, rel = n eps) or |a_pq| <= abs (abs = 4 eps ||A||_F, the error one
-// rotation leaves in the entry it annihilates).  Rotating such an entry
-// would only stir roundoff; a sweep in which every rotation is skipped ends
-// the iteration (threshold Jacobi).
+// the roundoff level: |a_pq| <= rel sqrt(|a_pp|) sqrt(|a_qq|) (its own
+// diagonal pair, rel = n eps) or |a_pq| <= abs (abs = 4 eps ||A||_F, the
+// error one rotation leaves in the entry it annihilates).  Rotating such an
+// entry would only stir roundoff; a sweep in which every rotation is skipped
+// ends the iteration (threshold Jacobi).
+//
+// With d = a_qq - a_pp the tangent of the smaller rotation angle is
+//   t = 2 a_pq sgn(d) / (|d| + sqrt(d^2 + 4 a_pq^2))     (sgn(0) = +1),
+// the classical t = sgn(theta) / (|theta| + sqrt(1 + theta^2)) with
+// theta = d / (2 a_pq) multiplied through by |2 a_pq|; c = 1 / sqrt(1 + t^2)
+// and s = t c.  One square root, one division and one reciprocal square root;
+// when d^2 + 4 a_pq^2 leaves the FP64 range the theta form is used instead.
 __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double apq, double rel,
                                                 double abs_floor, double &c, double &s) {
     c = 1.0;
     s = 0.0;
     const double a = fabs(apq);
     if (a <= abs_floor || a <= rel * sqrt(fabs(app)) * sqrt(fabs(aqq))) return false;
-    const double theta = (aqq - app) / (2.0 * apq);
-    const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
-    c = 1.0 / sqrt(1.0 + t * t);
+    const double d = aqq - app;
+    const double h = sqrt(d * d + 4.0 * apq * apq);
+    double t;
+    if (h <= 1.0e300) {
+        t = (d >= 0.0 ? 2.0 * apq : -2.0 * apq) / (fabs(d) + h);
+        c = rsqrt(1.0 + t * t);
+    } else {
+        const double theta = d / (2.0 * apq);
+        t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(1.0 + theta * theta));
+        c = 1.0 / sqrt(1.0 + t * t);
+    }
     s = t * c;
     return true;
 }
@@ -57,31 +72,129 @@ __device__ __forceinline__ bool jacobi_rotation(double app, double aqq, double a
 // once.  V does not feed the rotations, so its update lags one round behind:
 // while wave 0 computes the rotations of round r from A, waves 1.. apply the
 // rotations of round r - 1 to V (two sets of rotation parameters in LDS);
-// then every thread applies round r to A.  The arithmetic of every rotation
-// and update is the one of jacobi_body.
+// then every thread applies round r to A.
+//
+// The round is bound by LDS latency, so every update first reads all the
+// rotation parameters it needs (packed (p, q) and (c, s) pairs, indices
+// clamped to a valid pair so that the reads need no branch), then all its
+// matrix entries (predicated), then writes.  V is ne x ne with an even
+// leading dimension and each thread of its update owns a pair of adjacent
+// rows, so its entries move 16 bytes at a time.  A round whose rotations are
+// all the identity (the last sweep of the threshold rule) updates nothing.
 constexpr int JS_MAXM = 64;
-constexpr int JS_VTHREADS = EIG_THREADS - 64;                    // waves 1.. update V
-constexpr int JS_KA = JS_MAXM / (EIG_THREADS / JS_MAXM);         // A blocks per thread
-constexpr int JS_KV = (JS_MAXM + JS_VTHREADS / (2 * JS_MAXM) - 1) / (JS_VTHREADS / (2 * JS_MAXM));
-constexpr int JS_CA = 4;  // A blocks whose loads are issued together
-constexpr int JS_CV = 8;  // V pairs whose loads are issued together
+constexpr int JS_VTHREADS = EIG_THREADS - 64;   // waves 1.. update V
+constexpr int JS_CV = 4;                        // V pairs per batch of reads
 
-// Dynamic LDS of jacobi_small_body: A (ne x ne) and, when v_lds, V (n x ne).
+// Dynamic LDS of jacobi_small_body: A (ne x ne) and, when v_lds, V (ne x ne).
 __host__ __device__ inline size_t jacobi_small_lds(int64_t n, bool v_lds) {
     const int64_t ne = n + (n & 1);
-    return (size_t)(ne * ne + (v_lds ? n * ne : 0)) * 8;
+    return (size_t)(ne * ne * (v_lds ? 2 : 1)) * 8;
 }
-// Global V (when not in LDS) needs n * ne doubles.
-__host__ __device__ inline size_t jacobi_small_vg(int64_t n) { return (size_t)(n * (n + (n & 1))) * 8; }
+// Global V (when not in LDS): ne x ne doubles, 16-byte aligned.
+__host__ __device__ inline size_t jacobi_small_vg(int64_t n) {
+    const int64_t ne = n + (n & 1);
+    return (size_t)(ne * ne) * 8;
+}
+
+// A <- J^T A J for the rotations of `set`: the thread owns row pair Ia and
+// the column pairs ja0, ja0 + ja, ... (nka of them), CA per batch of reads.
+template <int CA>
+__device__ __forceinline__ void jacobi_small_update_a(double *__restrict__ A, int ne, int m,
+                                                      const int2 *__restrict__ pq,
+                                                      const double2 *__restrict__ cs, int Ia,
+                                                      int ja0, int ja, int nka) {
+    if (nka == 0) return;
+    const int2 pqI = pq[Ia];
+    const double2 csI = cs[Ia];
+    const int pI = pqI.x, qI = pqI.y;
+    const double ci = csI.x, si = csI.y;
+#pragma unroll 1
+    for (int k0 = 0; k0 < nka; k0 += CA) {
+        int pj[CA], qj[CA];
+        double cj[CA], sj[CA], a[CA][4];
+#pragma unroll
+        for (int k = 0; k < CA; ++k) {
+            const int J = min(ja0 + (k0 + k) * ja, m - 1);
+            const int2 t = pq[J];
+            const double2 u = cs[J];
+            pj[k] = ne * t.x;
+            qj[k] = ne * t.y;
+            cj[k] = u.x;
+            sj[k] = u.y;
+        }
+#pragma unroll
+        for (int k = 0; k < CA; ++k) {
+            if (k0 + k < nka) {
+                a[k][0] = A[pI + pj[k]];
+                a[k][1] = A[pI + qj[k]];
+                a[k][2] = A[qI + pj[k]];
+                a[k][3] = A[qI + qj[k]];
+            } else {
+                a[k][0] = a[k][1] = a[k][2] = a[k][3] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < CA; ++k)
+            if (k0 + k < nka) {
+                const double b00 = ci * a[k][0] - si * a[k][2], b01 = ci * a[k][1] - si * a[k][3];
+                const double b10 = si * a[k][0] + ci * a[k][2], b11 = si * a[k][1] + ci * a[k][3];
+                A[pI + pj[k]] = cj[k] * b00 - sj[k] * b01;
+                A[pI + qj[k]] = sj[k] * b00 + cj[k] * b01;
+                A[qI + pj[k]] = cj[k] * b10 - sj[k] * b11;
+                A[qI + qj[k]] = sj[k] * b10 + cj[k] * b11;
+            }
+    }
+}
+
+// V <- V J for the rotations of `set`: the thread owns rows (2 rp, 2 rp + 1)
+// of the pairs jw0, jw0 + jw, ... (nkw of them).  V2 views V (ne x ne,
+// leading dimension ne) as ne / 2 x ne pairs of doubles.
+__device__ __forceinline__ void jacobi_small_update_v(double2 *__restrict__ V2, int nh, int m,
+                                                      const int2 *__restrict__ pq,
+                                                      const double2 *__restrict__ cs, int rp,
+                                                      int jw0, int jw, int nkw) {
+#pragma unroll 1
+    for (int k0 = 0; k0 < nkw; k0 += JS_CV) {
+        int pj[JS_CV], qj[JS_CV];
+        double cj[JS_CV], sj[JS_CV];
+        double2 vp[JS_CV], vq[JS_CV];
+#pragma unroll
+        for (int k = 0; k < JS_CV; ++k) {
+            const int J = min(jw0 + (k0 + k) * jw, m - 1);
+            const int2 t = pq[J];
+            const double2 u = cs[J];
+            pj[k] = rp + nh * t.x;
+            qj[k] = rp + nh * t.y;
+            cj[k] = u.x;
+            sj[k] = u.y;
+        }
+#pragma unroll
+        for (int k = 0; k < JS_CV; ++k) {
+            if (k0 + k < nkw) {
+                vp[k] = V2[pj[k]];
+                vq[k] = V2[qj[k]];
+            } else {
+                vp[k] = vq[k] = make_double2(0.0, 0.0);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < JS_CV; ++k)
+            if (k0 + k < nkw) {
+                V2[pj[k]] = make_double2(cj[k] * vp[k].x - sj[k] * vq[k].x, cj[k] * vp[k].y - sj[k] * vq[k].y);
+                V2[qj[k]] = make_double2(sj[k] * vp[k].x + cj[k] * vq[k].x, sj[k] * vp[k].y + cj[k] * vq[k].y);
+            }
+    }
+}
 
 template <bool VLDS>
 __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, int n, int R,
                                                   double *__restrict__ Vg, double *__restrict__ U,
                                                   double *__restrict__ lam, double tol,
                                                   int max_sweeps, int64_t *__restrict__ flag) {
-    extern __shared__ double s_e[];
-    __shared__ double s_c[2][JS_MAXM], s_s[2][JS_MAXM];
-    __shared__ int s_p[2][JS_MAXM], s_q[2][JS_MAXM];
+    extern __shared__ __align__(16) double s_e[];   // 16-byte aligned: V is read 16 bytes at a time
+    __shared__ int2 s_pq[2][JS_MAXM];
+    __shared__ double2 s_cs[2][JS_MAXM];
+    __shared__ int s_any[2];
     __shared__ double s_red[2][EIG_THREADS / 64];
     __shared__ int s_sel[2 * JS_MAXM];
     __shared__ double s_sign[2 * JS_MAXM];
@@ -91,7 +204,7 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
     const int ne = n + (n & 1), m = ne / 2;
     const double thresh = (double)n * 2.220446049250313e-16;
     double *A = s_e;                         // ne x ne, leading dimension ne
-    double *V = VLDS ? s_e + ne * ne : Vg;   // n x ne, leading dimension n
+    double *V = VLDS ? s_e + ne * ne : Vg;   // ne x ne, leading dimension ne
     const int tid = threadIdx.x;
     for (int e0 = tid; e0 < ne * ne; e0 += 4 * EIG_THREADS) {
         double v[4];
@@ -107,43 +220,23 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
             if (e < ne * ne) A[e] = v[u];
         }
     }
-    for (int e = tid; e < n * ne; e += EIG_THREADS) {
-        const int i = e % n, j = e / n;
-        V[e] = (i == j) ? 1.0 : 0.0;
+    for (int e = tid; e < ne * ne; e += EIG_THREADS) {
+        const int i = e % ne, j = e / ne;
+        V[e] = (i == j && i < n) ? 1.0 : 0.0;
     }
     // A: thread owns row pair Ia for the column pairs ja0, ja0 + ja, ...
     const int ja = EIG_THREADS / m, Ia = tid % m, ja0 = tid / m;
-    // V (waves 1..): thread owns row rv for the column pairs jv0, jv0 + jv, ...
+    const int nka = ja0 < ja ? (m - ja0 + ja - 1) / ja : 0;
+    const int cap = (m + ja - 1) / ja;       // the most column pairs of any thread
+    // V (waves 1..): thread owns row pair rp for the pairs jw0, jw0 + jw, ...
     const int tv = tid - 64;
-    const int jv = JS_VTHREADS / n, rv = tv >= 0 ? tv % n : 0, jv0 = tv >= 0 ? tv / n : jv;
-
-    // V <- V J for the rotations of set `set` (threads of waves 1..)
-    auto update_v = [&](int set) {
-        if (jv0 >= jv) return;
-#pragma unroll 1
-        for (int k0 = 0; k0 < JS_KV; k0 += JS_CV) {
-            int pj[JS_CV], qj[JS_CV];
-            double vp[JS_CV], vq[JS_CV];
-#pragma unroll
-            for (int k = 0; k < JS_CV; ++k) {
-                const int J = jv0 + (k0 + k) * jv;
-                if (J < m) {
-                    pj[k] = rv + n * s_p[set][J];
-                    qj[k] = rv + n * s_q[set][J];
-                    vp[k] = V[pj[k]];
-                    vq[k] = V[qj[k]];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < JS_CV; ++k) {
-                const int J = jv0 + (k0 + k) * jv;
-                if (J < m) {
-                    const double cj = s_c[set][J], sj = s_s[set][J];
-                    V[pj[k]] = cj * vp[k] - sj * vq[k];
-                    V[qj[k]] = sj * vp[k] + cj * vq[k];
-                }
-            }
-        }
+    const int jw = JS_VTHREADS / m, rp = tv >= 0 ? tv % m : 0, jw0 = tv >= 0 ? tv / m : jw;
+    const int nkw = (tv >= 0 && jw0 < jw) ? (m - jw0 + jw - 1) / jw : 0;
+    double2 *V2 = reinterpret_cast<double2 *>(V);
+    auto update_a = [&](int set) {
+        if (cap <= 2) jacobi_small_update_a<2>(A, ne, m, s_pq[set], s_cs[set], Ia, ja0, ja, nka);
+        else if (cap <= 4) jacobi_small_update_a<4>(A, ne, m, s_pq[set], s_cs[set], Ia, ja0, ja, nka);
+        else jacobi_small_update_a<8>(A, ne, m, s_pq[set], s_cs[set], Ia, ja0, ja, nka);
     };
     __syncthreads();
 
@@ -192,6 +285,7 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
         for (int r = 0; r < ne - 1; ++r) {
             const int set = r & 1;
             if (tid < 64) {
+                bool rot = false;
                 if (tid < m) {
                     int p = rr_player(tid, r, ne), q = rr_player(ne - 1 - tid, r, ne);
                     if (p > q) {
@@ -200,55 +294,25 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
                         q = t;
                     }
                     double c, sn;
-                    if (jacobi_rotation(A[p + ne * p], A[q + ne * q], A[p + ne * q], thresh, s_floor, c, sn))
-                        s_rot = 1;
-                    s_p[set][tid] = p;
-                    s_q[set][tid] = q;
-                    s_c[set][tid] = c;
-                    s_s[set][tid] = sn;
+                    rot = jacobi_rotation(A[p + ne * p], A[q + ne * q], A[p + ne * q], thresh, s_floor, c, sn);
+                    s_pq[set][tid] = make_int2(p, q);
+                    s_cs[set][tid] = make_double2(c, sn);
                 }
-            } else if (r > 0) {
-                update_v(set ^ 1);   // round r - 1
+                const bool any = __ballot(rot) != 0;
+                if (tid == 0) {
+                    s_any[set] = any ? 1 : 0;
+                    if (any) s_rot = 1;
+                }
+            } else if (r > 0 && s_any[set ^ 1]) {
+                jacobi_small_update_v(V2, m, m, s_pq[set ^ 1], s_cs[set ^ 1], rp, jw0, jw, nkw);   // round r - 1
             }
             __syncthreads();
-            if (ja0 < ja) {
-                const int pI = s_p[set][Ia], qI = s_q[set][Ia];
-                const double ci = s_c[set][Ia], si = s_s[set][Ia];
-#pragma unroll 1
-                for (int k0 = 0; k0 < JS_KA; k0 += JS_CA) {
-                    int pj[JS_CA], qj[JS_CA];
-                    double a[JS_CA][4];
-#pragma unroll
-                    for (int k = 0; k < JS_CA; ++k) {
-                        const int J = ja0 + (k0 + k) * ja;
-                        if (J < m) {
-                            pj[k] = ne * s_p[set][J];
-                            qj[k] = ne * s_q[set][J];
-                            a[k][0] = A[pI + pj[k]];
-                            a[k][1] = A[pI + qj[k]];
-                            a[k][2] = A[qI + pj[k]];
-                            a[k][3] = A[qI + qj[k]];
-                        }
-                    }
-#pragma unroll
-                    for (int k = 0; k < JS_CA; ++k) {
-                        const int J = ja0 + (k0 + k) * ja;
-                        if (J < m) {
-                            const double cj = s_c[set][J], sj = s_s[set][J];
-                            const double b00 = ci * a[k][0] - si * a[k][2], b01 = ci * a[k][1] - si * a[k][3];
-                            const double b10 = si * a[k][0] + ci * a[k][2], b11 = si * a[k][1] + ci * a[k][3];
-                            A[pI + pj[k]] = cj * b00 - sj * b01;
-                            A[pI + qj[k]] = sj * b00 + cj * b01;
-                            A[qI + pj[k]] = cj * b10 - sj * b11;
-                            A[qI + qj[k]] = sj * b10 + cj * b11;
-                        }
-                    }
-                }
-            }
+            if (s_any[set]) update_a(set);
             __syncthreads();
         }
         // the last round's V update
-        if (tid >= 64) update_v((ne - 2) & 1);
+        if (tid >= 64 && s_any[(ne - 2) & 1])
+            jacobi_small_update_v(V2, m, m, s_pq[(ne - 2) & 1], s_cs[(ne - 2) & 1], rp, jw0, jw, nkw);
         __syncthreads();
         ++sweep;
     }
@@ -268,21 +332,21 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
     for (int r = tid; r < R; r += EIG_THREADS) {
         const int col = s_sel[r];
         int arg = 0;
-        double best = fabs(V[n * col]);
+        double best = fabs(V[ne * col]);
         for (int i = 1; i < n; ++i) {
-            const double v = fabs(V[i + n * col]);
+            const double v = fabs(V[i + ne * col]);
             if (v > best) {
                 best = v;
                 arg = i;
             }
         }
-        s_sign[r] = V[arg + n * col] < 0 ? -1.0 : 1.0;
+        s_sign[r] = V[arg + ne * col] < 0 ? -1.0 : 1.0;
         if (lam) lam[r] = A[col + ne * col];
     }
     __syncthreads();
     for (int e = tid; e < n * R; e += EIG_THREADS) {
         const int i = e % n, r = e / n;
-        U[e] = s_sign[r] * V[i + n * s_sel[r]];
+        U[e] = s_sign[r] * V[i + ne * s_sel[r]];
     }
 }
 
@@ -292,7 +356,7 @@ __device__ __forceinline__ void jacobi_body(const double *__restrict__ S, int n,
                                             double *__restrict__ U, double *__restrict__ lam,
                                             double tol, int max_sweeps,
                                             int64_t *__restrict__ flag) {
-    extern __shared__ double s_e[];
+    extern __shared__ __align__(16) double s_e[];   // 16-byte aligned: V is read 16 bytes at a time
     __shared__ double s_c[256], s_s[256];
     __shared__ int s_p[256], s_q[256];
     __shared__ double s_red[2][EIG_THREADS / 64];

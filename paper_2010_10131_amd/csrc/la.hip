@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(int ta, int tb, int m, in
                                                        int64_t lda, const double *__restrict__ B,
                                                        int64_t ldb, double beta, double *__restrict__ C,
                                                        int64_t ldc, int kslice, double *__restrict__ part) {
-    extern __shared__ double s_gemm[];
+    extern __shared__ __align__(16) double s_gemm[];
     double *sA = s_gemm;                  // sA[kk * (GT + 1) + r] = op(A)(row0 + r, kc + kk)
     double *sB = s_gemm + GK * (GT + 1);  // sB[kk * (GT + 1) + c] = op(B)(kc + kk, col0 + c)
     constexpr int PER = GT * GK / 256;    // elements of each panel per thread

@@ -220,7 +220,7 @@ __device__ __forceinline__ void ttm_ks_body(const float *__restrict__ Y, const u
     constexpr int NQ = Frag<PREC>::NQ;
     constexpr int RTB = 4;
     constexpr int ROWS = 16 * NT;
-    extern __shared__ float s_part[];  // [2][KS_WAVES][ROWS][KS_RS]
+    extern __shared__ __align__(16) float s_part[];  // [2][KS_WAVES][ROWS][KS_RS], read as float4
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane >> 4;
     const int rt0 = rb * RTB;

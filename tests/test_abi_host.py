@@ -125,6 +125,22 @@ def test_entry_points_reject_bad_arguments_before_launch(lib):
                         ctypes.c_void_p(0x3000), ctypes.c_void_p(0x4000), 1 << 20, None)
     assert st == _lib.STH_ERR_INVALID
     assert b"R" in lib.sth_last_error()
+    # prepared factors: sizes and argument checks before any launch
+    assert 0 < lib.ttm_factor_bytes(64, 16, 1) <= lib.ttm_mode_n_workspace(64, 16)
+    assert lib.ttm_factor_bytes(64, 16, 9) == 0 and lib.ttm_factor_bytes(0, 16, 1) == 0
+    nb = lib.ttm_factor_bytes(40, 8, 2)
+    st = lib.ttm_factor_prepare(40, 8, 2, ctypes.c_void_p(0x1000), 0, ctypes.c_void_p(0x2000),
+                                nb - 16, None)
+    assert st == _lib.STH_ERR_NOMEM
+    st = lib.ttm_factor_prepare(40, 8, 2, ctypes.c_void_p(0x1001), 0, ctypes.c_void_p(0x2000),
+                                nb, None)
+    assert st == _lib.STH_ERR_LAYOUT
+    st = lib.ttm_mode_n_prepared(3, dims, 1, 8, 1, 2, ctypes.c_void_p(0x1000),
+                                 ctypes.c_void_p(0x2000), 16, ctypes.c_void_p(0x3000), None)
+    assert st == _lib.STH_ERR_INVALID
+    st = lib.ttm_mode_n_prepared(3, dims, 1, 8, 0, 2, ctypes.c_void_p(0x1000),
+                                 ctypes.c_void_p(0x2000), 1 << 20, ctypes.c_void_p(0x3000), None)
+    assert st == _lib.STH_ERR_INVALID      # FP64 data needs FP64 products
 
 
 def test_batched_plan_validation():

@@ -94,6 +94,25 @@ def test_ttm_transposed_factor_expands(api, prec):
     check_bound(Z, ref, oracle.ttm_tensor(np.abs(Y), np.abs(W), 1), tol_for(prec, 5), "ttm^T")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("dims,n,R", [((40, 520, 3), 1, 64), ((512, 300), 0, 64), ((9, 33, 7), 2, 5)])
+def test_ttm_prepared_factor_matches(api, dims, n, R, prec):
+    """One prepared factor applied twice gives the bits of ttm_mode_n (same kernel, same split)."""
+    dtype = "float64" if prec == "fp64" else "float32"
+    Y = api.to_device(randn(dims, 11 + n, dtype))
+    U = api.to_device(np.asfortranarray(np.random.default_rng(5 + R).standard_normal((dims[n], R))))
+    Up = api.ttm_factor_prepare(U, prec)
+    Z0 = api.to_numpy(api.ttm_mode_n(Y, U, n, prec))
+    for _ in range(2):
+        Z1 = api.to_numpy(api.ttm_mode_n_prepared(Y, Up, n, R, prec))
+        assert np.array_equal(Z0, Z1), f"prepared ttm {dims} n={n} {prec}"
+    Wt = api.to_device(np.asfortranarray(np.random.default_rng(6).standard_normal((dims[n], R))))
+    Z2 = api.to_numpy(api.ttm_mode_n_prepared(api.to_device(api.to_numpy(api.ttm_mode_n_prepared(
+        Y, Up, n, R, prec))), api.ttm_factor_prepare(Wt, prec, transpose_u=True), n, dims[n], prec))
+    Z3 = api.to_numpy(api.ttm_mode_n(api.to_device(Z0), Wt, n, prec, transpose_u=True))
+    assert np.array_equal(Z2, Z3)
+
+
 # ------------------------------------------------------------ Gram / TTT ----
 
 GRAM_CASES = [
