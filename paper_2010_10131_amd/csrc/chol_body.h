@@ -15,13 +15,16 @@ namespace sth {
 // Blocked right-looking Cholesky with 16-column panels:
 //   * the diagonal block is factored by one wave in registers (row l of the
 //     block in lane l, right-looking within the block, columns broadcast with
-//     lane reads, 1 / sqrt from the reciprocal square root);
-//   * the panel below it by a row-parallel forward substitution;
-//   * the trailing matrix by a rank-16 update on the FP64 matrix cores
-//     (16 x 16 tiles of the lower triangle, four 16x16x4 products each).
+//     lane reads, 1 / sqrt from the reciprocal square root), and the same
+//     wave inverts it (lane c solves for column c of D^{-1} = L(K, K)^{-1});
+//     D^{-1} is kept, transposed, in the unused upper half of the block;
+//   * the panel below it is P = A(B, K) D^{-T}, one 16 x 16 x 16 product per
+//     row tile on the FP64 matrix cores;
+//   * the trailing matrix gets the rank-16 update A(bi, bj) -= P(bi) P(bj)^T
+//     on the matrix cores (16 x 16 tiles of the lower triangle).
 // L is then inverted in place block column by block column from the last
-// one:  L^{-1}(B, K) = -(sum_{J in (K, B]} L^{-1}(B, J) L(J, K)) L(K, K)^{-1},
-// both products on the matrix cores, L(K, K)^{-1} by forward substitution.
+// one:  L^{-1}(B, K) = -(sum_{J in (K, B]} L^{-1}(B, J) L(J, K)) D_K^{-1},
+// both products on the matrix cores, D_K^{-1} the kept inverse.
 // Writes R = L^T (upper, may be NULL) and Rinv = L^{-T} (upper), n x n.  A
 // non-positive pivot sets flag[0] = 2 and is replaced by a tiny positive one
 // so that the run continues.
@@ -51,6 +54,7 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
                                           double shift_rel, double *__restrict__ Rout,
                                           double *__restrict__ Rinv, int64_t *__restrict__ flag) {
     constexpr int NW = NTH / 64;
+    constexpr int LC = 8;   // columns per wave and load step (16 loads in flight per thread)
     extern __shared__ __align__(16) double s_l[];  // L, column-major, leading dimension ld
     const int np = chol_np(n), ld = np + 1, nb = np / CB;
     double *s_tmp = s_l + np * ld;   // np x CB
@@ -61,12 +65,11 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
     const int lane = tid & 63, wave = tid >> 6;
     const int tr = lane & 15, tg = lane >> 4;   // matrix-core tile coordinates
 
-    // lower triangle of G padded with the identity, four columns per wave and
-    // step (8 loads in flight per thread)
-    for (int j0 = 4 * wave; j0 < np; j0 += 4 * NW) {
-        double v[4][2];
+    // lower triangle of G padded with the identity
+    for (int j0 = LC * wave; j0 < np; j0 += LC * NW) {
+        double v[LC][2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < LC; ++u)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int j = j0 + u, i = lane + 64 * h;
@@ -76,7 +79,7 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
                 v[u][h] = x;
             }
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
+        for (int u = 0; u < LC; ++u)
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int j = j0 + u, i = lane + 64 * h;
@@ -103,6 +106,7 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
         // 1. diagonal block: wave 0, row l of the block in lane l
         if (wave == 0) {
             double row[CB];
+            double myrd = 0.0;
 #pragma unroll
             for (int c = 0; c < CB; ++c) row[c] = (lane < CB) ? s_l[k0 + lane + ld * (k0 + c)] : 0.0;
 #pragma unroll
@@ -115,7 +119,7 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
                 const double rd = rsqrt(d);
                 if (lane == j) {
                     row[j] = d * rd;
-                    s_rd[k0 + j] = rd;
+                    myrd = rd;
                 } else if (lane > j) {
                     row[j] *= rd;
                 }
@@ -123,24 +127,39 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
 #pragma unroll
                 for (int c = j + 1; c < CB; ++c) row[c] -= row[j] * lane_value(row[j], c);
             }
-            if (lane < CB)
+            // column `lane` of D^{-1}: x_r = (delta_{r,lane} - sum_{d<r} L(r, d) x_d) / L(r, r)
+            double x[CB];
 #pragma unroll
-                for (int c = 0; c < CB; ++c) s_l[k0 + lane + ld * (k0 + c)] = (c <= lane) ? row[c] : 0.0;
+            for (int r = 0; r < CB; ++r) {
+                double sacc = (r == lane) ? 1.0 : 0.0;
+#pragma unroll
+                for (int d = 0; d < r; ++d) sacc -= lane_value(row[d], r) * x[d];
+                x[r] = sacc * lane_value(myrd, r);
+            }
+            // row `lane` of the block: L(lane, c) for c <= lane, D^{-1}(c, lane) above
+            if (lane < CB) {
+#pragma unroll
+                for (int c = 0; c < CB; ++c) s_l[k0 + lane + ld * (k0 + c)] = (c <= lane) ? row[c] : x[c];
+                s_rd[k0 + lane] = myrd;
+            }
         }
         __syncthreads();
         if (t0 >= np) break;
-        // 2. panel rows i >= t0: forward substitution against the block
-        for (int i = t0 + tid; i < np; i += NTH) {
-            double x[CB];
+        // 2. panel P(bi) = A(bi, K) D^{-T}, one row tile per wave at a time;
+        //    D^{-T}(k, c) = D^{-1}(c, k): the upper half for c > k, 1 / L(k, k) for c = k
+        for (int bi = kb + 1 + wave; bi < nb; bi += NW) {
+            const int ri = CB * bi;
+            f64x4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < CB; ++c) {
-                double sacc = s_l[i + ld * (k0 + c)];
-#pragma unroll
-                for (int d = 0; d < c; ++d) sacc -= x[d] * s_l[k0 + c + ld * (k0 + d)];
-                x[c] = sacc * s_rd[k0 + c];
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + tg;
+                const double a = s_l[ri + tr + ld * (k0 + k)];
+                const double dup = s_l[k0 + k + ld * (k0 + tr)];
+                const double b = tr > k ? dup : (tr == k ? s_rd[k0 + k] : 0.0);
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
 #pragma unroll
-            for (int c = 0; c < CB; ++c) s_l[i + ld * (k0 + c)] = x[c];
+            for (int v = 0; v < 4; ++v) s_l[ri + tg + 4 * v + ld * (k0 + tr)] = acc[v];
         }
         __syncthreads();
         // 3. trailing update A(bi, bj) -= P(bi) P(bj)^T on the matrix cores,
@@ -156,13 +175,11 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
             for (int v = 0; v < 4; ++v) acc[v] = s_l[ri + tg + 4 * v + ld * (cj + tr)];
             // A operand: P(ri.., k) = s_l[ri + i + ld * (k0 + k)];  B operand:
             // P^T(k, cj..) = s_l[cj + j + ld * (k0 + k)], i.e. b(k, j) with ldb swapped
-            {
 #pragma unroll
-                for (int kk = 0; kk < 4; ++kk) {
-                    const double a = -s_l[ri + tr + ld * (k0 + 4 * kk + tg)];
-                    const double b = s_l[cj + tr + ld * (k0 + 4 * kk + tg)];
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-                }
+            for (int kk = 0; kk < 4; ++kk) {
+                const double a = -s_l[ri + tr + ld * (k0 + 4 * kk + tg)];
+                const double b = s_l[cj + tr + ld * (k0 + 4 * kk + tg)];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) s_l[ri + tg + 4 * v + ld * (cj + tr)] = acc[v];
@@ -177,19 +194,10 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
     // in-place inverse, block columns from the last one
     for (int kb = nb - 1; kb >= 0; --kb) {
         const int k0 = kb * CB, t0 = k0 + CB;
-        // D^{-1} of the diagonal block (lower), one thread per column
-        if (tid < CB) {
-            const int c = tid;
-            double x[CB];
-#pragma unroll
-            for (int r = 0; r < CB; ++r) {
-                double sacc = (r == c) ? 1.0 : 0.0;
-#pragma unroll
-                for (int d = 0; d < r; ++d) sacc -= s_l[k0 + r + ld * (k0 + d)] * x[d];
-                x[r] = (r < c) ? 0.0 : sacc * s_rd[k0 + r];
-            }
-#pragma unroll
-            for (int r = 0; r < CB; ++r) s_dinv[r + CB * c] = x[r];
+        // D^{-1} of the diagonal block (lower) from its kept transpose
+        for (int e = tid; e < CB * CB; e += NTH) {
+            const int r = e % CB, c = e / CB;
+            s_dinv[e] = r > c ? s_l[k0 + c + ld * (k0 + r)] : (r == c ? s_rd[k0 + r] : 0.0);
         }
         // T(bi) = sum_{bj = kb+1..bi} Linv(bi, bj) L(bj, kb): one row tile per wave
         for (int bi = kb + 1 + wave; bi < nb; bi += NW) {
@@ -221,9 +229,9 @@ __device__ __forceinline__ void chol_body(const double *__restrict__ G, int n, i
 #pragma unroll
             for (int v = 0; v < 4; ++v) s_l[ri + tg + 4 * v + ld * (k0 + tr)] = acc[v];
         }
-        if (tid < CB * CB) {
-            const int r = tid % CB, c = tid / CB;
-            s_l[k0 + r + ld * (k0 + c)] = (r >= c) ? s_dinv[r + CB * c] : 0.0;
+        for (int e = tid; e < CB * CB; e += NTH) {
+            const int r = e % CB, c = e / CB;
+            s_l[k0 + r + ld * (k0 + c)] = s_dinv[e];
         }
         __syncthreads();
     }

@@ -143,7 +143,7 @@ hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const dou
     return hipGetLastError();
 }
 
-constexpr int CHOL_THREADS = 256;
+constexpr int CHOL_THREADS = 512;
 
 __global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(const double *__restrict__ G, int n,
                                                             int64_t ldg, double shift_rel,
