@@ -34,6 +34,15 @@ RECIPES = [
 ]
 T2_BAR = 1e-5
 
+# HBM bytes of one mode-1 TTM launch (bf16x3 products, 512 -> 64 over 262144
+# rows) from two rocprofv3 --pmc passes over this benchmark: FETCH_SIZE and
+# WRITE_SIZE in KiB per dispatch, each scaled by what the same counter reads
+# for a plain 512 MiB device copy of known size (fetch x 2.000, write x 1.000).
+# Source: profiles/ttm_mode1_512cubed_bf16x3_hbm_traffic.md.  Valid only for
+# that kernel as it is; None for any other TTM precision.
+TTM_PMC = {"ttm": "bf16x3", "fetch_kib": 262797.5, "fetch_scale": 2.000,
+           "write_kib": 65595.4, "write_scale": 1.000}
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -195,6 +204,10 @@ def main():
         selector = bench_selector(api, torch, dev, gp, tp)
 
     fp32_ms = results[fp32_name]["ms"]
+    ttm_traffic = None
+    if tp == TTM_PMC["ttm"]:
+        ttm_traffic = (TTM_PMC["fetch_kib"] * TTM_PMC["fetch_scale"]
+                       + TTM_PMC["write_kib"] * TTM_PMC["write_scale"]) * 1024
     out = {
         "metric": "st-HOSVD wall time & TTM HBM GB/s: mixed-precision vs FP32 at equal rel. error",
         "value": 1e3 / ms,
@@ -225,7 +238,8 @@ def main():
                                                       / 2500.0) if gp.startswith("bf16") else None},
         "roofline": {"bound": "hbm", "kernel": "ttm mode-1 (512 -> 64, 262144 rows)",
                      "achieved": ttm_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ttm_gbs / HBM_PEAK_GBS, "traffic": None},
+                     "frac": ttm_gbs / HBM_PEAK_GBS, "traffic": ttm_traffic,
+                     "algorithmic_bytes": ttm_bytes},
         "cpu_baseline": cpu,
         "batched": batched,
         "selector": selector,
