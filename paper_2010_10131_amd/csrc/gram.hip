@@ -40,24 +40,25 @@ __global__ __launch_bounds__(256) void gram_kernel(const T *__restrict__ A, cons
                                 xcd_logical_id(total_wg), partials);
 }
 
-// TB = 32 * WT.  FP32 / FP64 products with WT = 4 run eight waves of 64 x 32
-// each (2 x 4 grid), which keeps a wave's FP32 and FP64 accumulators in its
-// registers (measured 1.36x faster on the 512-wide Gram); the bf16-split
-// products, bound by LDS reads of the fragments, keep four waves of 64 x 64
-// (2 x 2 grid, half the fragment reads per product).
+// TB = 32 * WT.  With WT = 4 the block runs eight waves of 64 x 32 each
+// (2 x 4 grid): a wave's FP32 accumulators and their FP64 partial sums then
+// stay in its own registers (four waves of 64 x 64 need more than a wave's
+// 256 registers and shuttle them through the accumulation registers every
+// chunk); measured on the 512-wide Gram: FP32 products 1.36x, bf16x3 1.5x
+// faster than four waves.
 template <int PREC, int WT>
-constexpr bool gram_l1_eight_waves() { return WT == 4 && (PREC == P_FP32 || PREC == P_FP64); }
+constexpr bool gram_l1_eight_waves() { return WT == 4; }
 
-template <int PREC, int WT, bool VEC4>
+template <int PREC, int WT, bool VEC4, bool FULLI>
 __global__ __launch_bounds__((gram_l1_eight_waves<PREC, WT>() ? 512 : 256)) void gram_l1_kernel(
     const float *__restrict__ Y, int64_t I, int64_t P, int64_t kper, int nkc, int nblocks,
     int64_t total_wg, double *__restrict__ partials) {
     if constexpr (gram_l1_eight_waves<PREC, WT>())
-        gram_l1_body<PREC, 4, 2, 2, 4, VEC4>(Y, I, P, kper, nkc, nblocks, total_wg, xcd_logical_id(total_wg),
-                                             partials);
+        gram_l1_body<PREC, 4, 2, 2, 4, VEC4, FULLI>(Y, I, P, kper, nkc, nblocks, total_wg,
+                                                    xcd_logical_id(total_wg), partials);
     else
-        gram_l1_body<PREC, WT, WT, 2, 2, VEC4>(Y, I, P, kper, nkc, nblocks, total_wg, xcd_logical_id(total_wg),
-                                               partials);
+        gram_l1_body<PREC, WT, WT, 2, 2, VEC4, FULLI>(Y, I, P, kper, nkc, nblocks, total_wg,
+                                                      xcd_logical_id(total_wg), partials);
 }
 
 // Sums the partial blocks over the row ranges in a fixed order and writes
@@ -131,7 +132,11 @@ hipError_t launch_gram_l1(const float *A, int64_t IA, int64_t M, const GramShape
     const int64_t per_xcd = (total + 7) / 8;
     const size_t lds = (size_t)2 * 2 * Frag<PREC>::NQ * 4 * TB * 16;
     const bool vec = (IA % 4 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
-    auto kern = vec ? gram_l1_kernel<PREC, WT, true> : gram_l1_kernel<PREC, WT, false>;
+    // I a multiple of the block edge: the branch-free loads
+    // (blocks of 64 and 128: whole fragment octets per thread)
+    auto kern = !vec ? gram_l1_kernel<PREC, WT, false, false>
+                     : (IA % TB == 0 ? gram_l1_kernel<PREC, WT, true, (WT >= 2)>
+                                     : gram_l1_kernel<PREC, WT, true, false>);
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;

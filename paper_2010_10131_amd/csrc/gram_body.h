@@ -262,7 +262,13 @@ __device__ __forceinline__ void l1_store(uint8_t *slab, int TB, int g, int row, 
 
 // Waves form a WI x WJ grid over the TB x TB output block, each owning
 // WTI x WTJ tiles of 16 x 16 (TB = 16 WTI WI = 16 WTJ WJ).
-template <int PREC, int WTI, int WTJ, int WI, int WJ, bool VEC4>
+// FULLI: I is a multiple of TB and rows are 16-byte aligned, so every load is
+// one float4 with no branch (rows past the range are clamped and zeroed by a
+// select) and the prefetches are issued unconditionally (chunk index clamped;
+// a diagonal block loads its one operand twice, from cache).  Branch-free
+// loads let the compiler wait for exactly the chunk being stored instead of
+// draining every load in flight before the next ones are issued.
+template <int PREC, int WTI, int WTJ, int WI, int WJ, bool VEC4, bool FULLI = false>
 __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_t I, int64_t P,
                                              int64_t kper, int nkc, int nblocks, int64_t total_wg,
                                              int64_t lid, double *__restrict__ partials) {
@@ -298,7 +304,28 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
     const int iq = tid % IQ, ph = tid / IQ;
     const int g_st = ph % 4, slot0 = LPT * (ph / 4);
 
+    // FULLI: thread (il, kq) owns column il of the block and the KPT
+    // consecutive rows kq * KPT .. of each chunk (lanes along the column, so
+    // every load instruction reads 256 contiguous bytes); it splits them into
+    // whole fragment quads and writes 16 bytes per quad, consecutive lanes to
+    // consecutive rows of the slab (no LDS bank conflicts).
+    constexpr int KG = NTH / TB;      // row groups per chunk
+    constexpr int KPT = KC / KG;      // rows per thread per chunk (4 * LPT floats)
+    static_assert(!FULLI || (KPT == 4 * LPT && KPT % 8 == 0), "thread tiling of the full path");
+    const int il = tid % TB, kq = tid / TB;
     auto load = [&](int64_t pc, int64_t c0, float4 (&r)[LPT]) {
+        if constexpr (FULLI) {
+            float *rf = &r[0].x;
+            const float *src = Y + c0 + il;
+#pragma unroll
+            for (int s = 0; s < KPT; ++s) {
+                const int64_t p = pc + kq * KPT + s;
+                const int64_t pcl = p < pend ? p : pend - 1;
+                const float v = src[I * pcl];
+                rf[s] = p < pend ? v : 0.f;
+            }
+            return;
+        }
         const int64_t col = c0 + 4 * iq;
 #pragma unroll
         for (int s = 0; s < LPT; ++s) {
@@ -320,6 +347,22 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
     };
     auto store = [&](int buf, int op, const float4 (&r)[LPT]) {
         uint8_t *slab = lds + (size_t)(buf * 2 + op) * SLAB;
+        if constexpr (FULLI) {
+            const float *rf = &r[0].x;
+            uint4 *sq = reinterpret_cast<uint4 *>(slab);
+#pragma unroll
+            for (int o = 0; o < KPT / 8; ++o) {
+                float v[8];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = rf[8 * o + e];
+                FragQ<PREC> t;
+                make_frag(v, t.f);
+                const int g = kq * (KPT / 8) + o;
+#pragma unroll
+                for (int qq = 0; qq < NQ; ++qq) sq[(qq * 4 + g) * TB + il] = t.q[qq];
+            }
+            return;
+        }
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             float v[LPT];
@@ -378,7 +421,22 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
     };
 
     float4 ra0[LPT], rb0[LPT], ra1[LPT], rb1[LPT];
-    if (nch > 0) {
+    auto prefetch = [&](int cn, float4 (&ra)[LPT], float4 (&rb)[LPT]) {
+        if (FULLI) {
+            const int64_t pc = pbeg + (int64_t)(cn < nch ? cn : nch - 1) * KC;
+            load(pc, i0, ra);
+            load(pc, j0, rb);
+        } else if (cn < nch) {
+            load(pbeg + (int64_t)cn * KC, i0, ra);
+            if (!diag) load(pbeg + (int64_t)cn * KC, j0, rb);
+        }
+    };
+    if (FULLI && nch > 0) {
+        prefetch(0, ra0, rb0);
+        prefetch(1, ra1, rb1);
+        store(0, 0, ra0);
+        store(0, 1, rb0);
+    } else if (nch > 0) {
         load(pbeg, i0, ra0);
         if (!diag) load(pbeg, j0, rb0);
         if (nch > 1) {
@@ -389,12 +447,26 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
         if (!diag) store(0, 1, rb0);
     }
     __syncthreads();
+    if constexpr (FULLI) {
+        // the same two-stage pipeline with every load and LDS store issued
+        // unconditionally (clamped chunks past the end are stored and never
+        // multiplied); only the matrix-core work of a missing odd chunk is skipped
+        for (int c = 0; c < nch; c += 2) {
+            prefetch(c + 2, ra0, rb0);
+            compute(0, c);
+            store(1, 0, ra1);
+            store(1, 1, rb1);
+            __syncthreads();
+            prefetch(c + 3, ra1, rb1);
+            if (c + 1 < nch) compute(1, c + 1);
+            store(0, 0, ra0);
+            store(0, 1, rb0);
+            __syncthreads();
+        }
+    } else
     for (int c = 0; c < nch; c += 2) {
         // chunk c in buffer 0; chunk c+1 in flight in ra1/rb1
-        if (c + 2 < nch) {
-            load(pbeg + (int64_t)(c + 2) * KC, i0, ra0);
-            if (!diag) load(pbeg + (int64_t)(c + 2) * KC, j0, rb0);
-        }
+        prefetch(c + 2, ra0, rb0);
         compute(0, c);
         if (c + 1 < nch) {
             store(1, 0, ra1);
@@ -403,10 +475,7 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
         __syncthreads();
         if (c + 1 >= nch) break;
         // chunk c+1 in buffer 1; chunk c+2 in flight in ra0/rb0
-        if (c + 3 < nch) {
-            load(pbeg + (int64_t)(c + 3) * KC, i0, ra1);
-            if (!diag) load(pbeg + (int64_t)(c + 3) * KC, j0, rb1);
-        }
+        prefetch(c + 3, ra1, rb1);
         compute(1, c + 1);
         if (c + 2 < nch) {
             store(0, 0, ra0);

@@ -70,12 +70,12 @@ __global__ __launch_bounds__(64 * WAVES) void ttm_kernel(
                                                     nrowblocks, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
-template <int PREC, int NT, int CPW>
+template <int PREC, int NT, int CPW, bool FULL>
 __global__ __launch_bounds__(64 * KS_WAVES) void ttm_ks_kernel(
     const float *__restrict__ Y, const uint4 *__restrict__ Uq, float *__restrict__ Z, int64_t K,
     int64_t Rout, int64_t P, int nchunks, int ntiles, int64_t nblocks) {
-    ttm_ks_body<PREC, NT, CPW>(Y, Uq, Z, K, Rout, P, nchunks, ntiles, nblocks, blockIdx.x, gridDim.x,
-                               blockIdx.y);
+    ttm_ks_body<PREC, NT, CPW, false, FULL>(Y, Uq, Z, K, Rout, P, nchunks, ntiles, nblocks, blockIdx.x,
+                                            gridDim.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------- host ----
@@ -141,7 +141,9 @@ hipError_t launch_ttm_ks(const float *Y, const uint4 *Uq, float *Z, int64_t K, i
     const int64_t nblocks = (M + 16 * NT - 1) / (16 * NT);
     const size_t lds = ttm_ks_lds(NT);
     const int64_t wgs = std::max<int64_t>(1, std::min<int64_t>(nblocks, (int64_t)device_cu_count()));
-    auto kern = ttm_ks_kernel<PREC, NT, CPW>;
+    // whole chunks for every wave: the branch-free kernel
+    auto kern = (K == (int64_t)KS_WAVES * CPW * KC) ? ttm_ks_kernel<PREC, NT, CPW, true>
+                                                    : ttm_ks_kernel<PREC, NT, CPW, false>;
     hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)wgs, (unsigned)nrb), dim3(64 * KS_WAVES), lds, s, Y, Uq, Z, K,

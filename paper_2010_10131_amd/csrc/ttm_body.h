@@ -212,7 +212,12 @@ __host__ __device__ inline size_t ttm_ks_lds(int nt) { return (size_t)2 * KS_WAV
 // PERM: lane group g holds k = 4g .. 4g+3 and 16 + 4g .. 16 + 4g + 3 of each
 // 32-wide chunk (the factor quads are prepared with the same order), so the
 // four groups of a row read its 64 bytes in one contiguous run per load.
-template <int PREC, int NT, int CPW, bool PERM = false>
+// FULL: K = KS_WAVES * CPW * 32 exactly, so every wave's chunks are whole and
+// the loads need no branch; the prefetches are then issued unconditionally
+// (the block index clamped to the last block), which lets the compiler wait
+// for exactly the block being multiplied instead of for every load in
+// flight.
+template <int PREC, int NT, int CPW, bool PERM = false, bool FULL = false>
 __device__ __forceinline__ void ttm_ks_body(const float *__restrict__ Y, const uint4 *__restrict__ Uq,
                                             float *__restrict__ Z, int64_t K, int64_t Rout, int64_t P,
                                             int nchunks, int ntiles, int64_t nblocks, int64_t wg,
@@ -244,6 +249,17 @@ __device__ __forceinline__ void ttm_ks_body(const float *__restrict__ Y, const u
         for (int nt = 0; nt < NT; ++nt) {
             const int64_t p = blk * ROWS + 16 * nt + (lane & 15);
             const int64_t pc = p < P ? p : P - 1;
+            if constexpr (FULL) {
+#pragma unroll
+                for (int j = 0; j < CPW; ++j) {
+                    const float *src = Y + K * pc + (int64_t)(c0 + j) * KC + 8 * g;
+                    const float4 u = *reinterpret_cast<const float4 *>(src);
+                    const float4 w = *reinterpret_cast<const float4 *>(src + 4);
+                    x[j][nt][0] = u.x; x[j][nt][1] = u.y; x[j][nt][2] = u.z; x[j][nt][3] = u.w;
+                    x[j][nt][4] = w.x; x[j][nt][5] = w.y; x[j][nt][6] = w.z; x[j][nt][7] = w.w;
+                }
+                continue;
+            }
 #pragma unroll
             for (int j = 0; j < CPW; ++j) {
                 const int64_t kb = (int64_t)(c0 + j) * KC + 8 * g;
@@ -332,11 +348,24 @@ __device__ __forceinline__ void ttm_ks_body(const float *__restrict__ Y, const u
     // b + 2 nwg are in flight
     float xa[CPW][NT][8], xb[CPW][NT][8], xc[CPW][NT][8];
     int64_t blk = wg;
-    if (blk < nblocks) load_block(blk, xa);
-    if (blk + nwg < nblocks) load_block(blk + nwg, xb);
+    const int64_t last = nblocks - 1;
+    if (FULL) {
+        load_block(blk < last ? blk : last, xa);
+        load_block(blk + nwg < last ? blk + nwg : last, xb);
+    } else {
+        if (blk < nblocks) load_block(blk, xa);
+        if (blk + nwg < nblocks) load_block(blk + nwg, xb);
+    }
     int buf = 0;
     auto step = [&](float (&cur)[CPW][NT][8], float (&nx2)[CPW][NT][8]) {
-        if (blk + 2 * nwg < nblocks) load_block(blk + 2 * nwg, nx2);
+        if (FULL) {
+            load_block(blk + 2 * nwg < last ? blk + 2 * nwg : last, nx2);
+            // keep these loads ahead of the block's products: issued here they
+            // are in flight for the whole multiply
+            __builtin_amdgcn_sched_barrier(0);
+        } else if (blk + 2 * nwg < nblocks) {
+            load_block(blk + 2 * nwg, nx2);
+        }
         compute_store(cur, buf);
         __syncthreads();
         reduce_store(blk, buf);

@@ -68,6 +68,9 @@ TTM_CASES = [
     ((5, 7, 130), 2, 130),        # R > 64: several r-blocks
     ((1, 1, 1), 1, 1),            # degenerate
     ((200, 3), 1, 2),             # M = 1, tiny K
+    ((512, 300), 0, 64),          # contiguous rows, K = 512: K-split kernel, whole chunks, ragged row block
+    ((384, 77), 0, 40),           # K-split with 12 chunks (idle waves), ragged R
+    ((300, 50), 0, 20),           # K-split with a ragged last chunk
 ]
 
 
