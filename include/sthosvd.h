@@ -133,7 +133,11 @@ void sthosvd_plan_destroy(sth_plan *plan);
  * drawn on the device from the counter-based generator seeded by
  * (seed, mode).  workspace: device, >= the plan's workspace_bytes.
  * Enqueue-only; the eigenvectors carry the sign convention "largest-magnitude
- * entry positive". */
+ * entry positive".  The EIG solver takes the R_n leading eigenvectors by
+ * Jacobi up to I_n = 96 and by subspace iteration with Rayleigh-Ritz above
+ * (block R_n + 16 rounded up to 8, at most 96 and within the Gram's rank
+ * bound; Jacobi otherwise), which yields the leading subspace to working
+ * accuracy when the spectrum has a gap after R_n. */
 sth_status sthosvd_run(const sth_plan *plan, const void *X, void *core, double *const *U,
                        double *const *eigvals, const double *const *als_init, uint64_t seed,
                        void *workspace, size_t workspace_bytes, sth_stream_t stream);

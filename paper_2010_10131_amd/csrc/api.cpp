@@ -69,6 +69,7 @@ int device_cu_count() {
 static const int MAX_ORDER = 8;
 static const int64_t MAX_EIG_N = SEL_MAX_EIG_N;   // I_n x I_n Gram and eigensolver
 static const int64_t EIG_DIRECT_MAX_HOST = 128;
+static const int64_t EIG_LDS_DIRECT_MAX_HOST = 96;   // Jacobi with A and V in LDS
 static const int64_t SI_BLOCK_MAX_HOST = 96;
 static int64_t si_block_host_api(int64_t n, int64_t R) {
     int64_t p = R + 16;   // the same rule as the device side
@@ -347,7 +348,8 @@ static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *s
     if (stp.solver == STH_SOLVER_EIG) {
         // Alg. 2 lines 6-8
         HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
-        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M), "eig");
+        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M,
+                          EIG_LDS_DIRECT_MAX_HOST), "eig");
         HIPCHK(ttm_prep_u(Un, stp.I, stp.R, 0, tp, uq, s), "ttm prep");
         HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
         return STH_OK;
@@ -546,7 +548,7 @@ extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double 
     if ((st = check_ptr(S, "S")) || (st = check_ptr(U, "U")) || (st = check_ptr(lam, "lam", true)) || (st = check_ptr(ws, "ws"))) return st;
     if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
     HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (int64_t *)ws,
-                      (hipStream_t)stream, n), "eig");
+                      (hipStream_t)stream, n, EIG_DIRECT_MAX_HOST), "eig");
     return STH_OK;
 }
 
@@ -886,7 +888,13 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
                 return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n = %lld too large for the batched eigensolver", t, s, (long long)b.R);
             if (b.R > 64) return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n > 64 in the batched path", t, s);
             b.sib = 0;
-            if (b.I > EIG_DIRECT_MAX_HOST) {
+            const int64_t pb = si_block_host_api(b.I, b.R);
+            if (b.I > EIG_LDS_DIRECT_MAX_HOST && b.I <= EIG_DIRECT_MAX_HOST && pb <= SI_BLOCK_MAX_HOST &&
+                pb < b.I && b.R <= P) {
+                // orders 97..128: the subspace iteration when its block fits
+                // (the Jacobi would keep V in the workspace there)
+                b.sib = (int32_t)std::min<int64_t>(pb, P);
+            } else if (b.I > EIG_DIRECT_MAX_HOST) {
                 // the Gram of this step has rank <= L * M: the subspace block
                 // is capped there, and more vectors than that need the direct
                 // solver, which the batched eigen kernel has only for I <= 128

@@ -185,7 +185,7 @@ __global__ __launch_bounds__(BE_THREADS) void batch_eig_kernel(const BatchStep *
     const double *S = (const double *)(ws + d.S_off);
     double *U = Up[(int64_t)d.tensor * order + mode];
     double *scr = (double *)(ws + d.eig_off);
-    if (n <= EIG_DIRECT_MAX) {
+    if (d.sib == 0) {   // direct Jacobi
         if (jacobi_small_lds(n, true) <= (size_t)BATCH_LDS_AV)
             jacobi_small_body<true>(S, n, R, scr, U, nullptr, tol, max_sweeps, flag);
         else
@@ -294,12 +294,12 @@ size_t batch_eig_lds(int64_t n, int64_t p) {
         const size_t both = jacobi_small_lds(m, true);
         return both <= (size_t)BATCH_LDS_AV ? both : jacobi_small_lds(m, false);
     };
-    if (n <= EIG_DIRECT_MAX) return jac(n);
+    if (p == 0) return jac(n);
     return std::max({jac(p), chol_lds_bytes(p), (size_t)2 * 32 * 33 * 8});
 }
 
 size_t batch_eig_scratch(int64_t n, int64_t p) {
-    if (n <= EIG_DIRECT_MAX) return std::max((size_t)2 * n * n * 8, jacobi_small_vg(n));
+    if (p == 0) return std::max((size_t)2 * n * n * 8, jacobi_small_vg(n));
     return (size_t)(3 * n * p + 4 * p * p + 2 * p * p) * 8;
 }
 

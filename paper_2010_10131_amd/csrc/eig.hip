@@ -47,7 +47,7 @@ __global__ void sign_fix_kernel(double *__restrict__ U, int n, int R) {
     __shared__ double s_v[256];
     __shared__ int s_i[256];
     double best = -1.0;
-    int arg = n;
+    int arg = 0;   // in range even when every entry is NaN (no comparison succeeds)
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         double v = fabs(U[i + (int64_t)n * r]);
         if (v > best) {
@@ -80,7 +80,11 @@ namespace {
 constexpr int SI_ITERS = SI_ITERS_DEV;
 int64_t si_block(int64_t n, int64_t R) { return si_block_host(n, R); }
 
-bool use_si(int64_t n, int64_t R) { return n > EIG_DIRECT_MAX && si_block(n, R) <= SI_BLOCK_MAX; }
+// si_min: the order above which the subspace iteration may be used
+bool use_si(int64_t n, int64_t R, int64_t si_min) {
+    const int64_t p = si_block(n, R);
+    return n > si_min && p <= SI_BLOCK_MAX && p < n;
+}
 
 struct SiWs {
     double *Q, *Z, *Z2, *G, *Rf, *Rinv, *T, *W, *gws;
@@ -173,13 +177,15 @@ size_t eig_ws_bytes(int64_t n) {
     size_t b = jacobi_ws(n);
     // subspace iteration for any R that selects it
     for (int64_t R = 1; R <= n; ++R)
-        if (use_si(n, R)) b = std::max(b, si_bytes(n, si_block(n, R)));
+        if (use_si(n, R, EIG_LDS_DIRECT_MAX)) b = std::max(b, si_bytes(n, si_block(n, R)));
     return b;
 }
 
 // R leading eigenpairs of the symmetric n x n matrix S.
-//   n <= 128: cyclic Jacobi on S itself (one workgroup, LDS).
-//   n > 128 with a block p = R + 16 (rounded up to 8) <= 96: subspace iteration
+//   n <= si_min (128 for eig_leading, 96 for the decompositions, which need
+//   the leading subspace only): cyclic Jacobi on S itself (one workgroup,
+//   LDS; V in the workspace above order 96).
+//   n > si_min with a block p = R + 16 (rounded up to 8) <= 96, p < n: subspace iteration
 //     Q <- orth(S Q) from a seeded Gaussian block (SI_ITERS = 3 times; orth is
 //     shifted Cholesky-QR, three passes for the last basis, two before), then
 //     Rayleigh-Ritz: Jacobi on T = Q^T S Q and U = Q W(:, :R), with the sign
@@ -187,11 +193,12 @@ size_t eig_ws_bytes(int64_t n) {
 //   otherwise (large R, or R above the rank bound of S): Jacobi on S with A
 //   and V in the workspace.
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
-                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound) {
+                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound,
+                      int64_t si_min) {
     // rank(S) <= rank_bound: a block wider than that would be rank deficient
     // (Cholesky-QR breaks down), so the block shrinks to the bound, and a
     // request of more than rank_bound vectors goes to the direct solver
-    if (!use_si(n, R) || R > rank_bound) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
+    if (!use_si(n, R, si_min) || R > rank_bound) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
     const int64_t p = std::min(si_block(n, R), rank_bound);
     SiWs w = si_layout((char *)ws, n, p);
     const int ni = (int)n, pi = (int)p;

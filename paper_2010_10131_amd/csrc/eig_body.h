@@ -6,11 +6,15 @@
 namespace sth {
 
 constexpr int64_t EIG_DIRECT_MAX = 128;  // Jacobi on the whole matrix up to this order
+// Largest order whose A and V both fit in LDS for the Jacobi (V goes to the
+// workspace above it).  The decompositions, which need the leading subspace
+// only, take the subspace iteration from the next order on when its block fits.
+constexpr int64_t EIG_LDS_DIRECT_MAX = 96;
 constexpr int64_t SI_BLOCK_MAX = 96;     // Rayleigh-Ritz block kept in LDS
 constexpr int SI_ITERS_DEV = 3;          // subspace iterations before Rayleigh-Ritz
 constexpr int EIG_LDS_AV = 150 * 1024;   // LDS bytes available for Jacobi's A and V
 
-// Subspace-iteration block size for n > EIG_DIRECT_MAX.
+// Block size of the subspace iteration.
 __host__ __device__ inline int64_t si_block_dev(int64_t n, int64_t R) {
     int64_t p = R + 16;   // 16 guard vectors beyond the R wanted ones
     p = (p + 7) / 8 * 8;
@@ -318,12 +322,17 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
     }
     if (!converged && tid == 0 && flag) flag[0] = 1;
 
-    // descending order of the diagonal, ties by index
+    // descending order of the diagonal, ties by index.  A NaN on the diagonal
+    // (non-finite input) sorts last and raises flag 3, so that the ranks stay
+    // a permutation of 0..n-1 and every selected column is in range.
     for (int i = tid; i < n; i += EIG_THREADS) {
-        const double li = A[i + ne * i];
+        const double di = A[i + ne * i];
+        const double li = (di == di) ? di : -HUGE_VAL;
+        if (di != di && flag) flag[0] = 3;
         int rank = 0;
         for (int j = 0; j < n; ++j) {
-            const double lj = A[j + ne * j];
+            const double dj = A[j + ne * j];
+            const double lj = (dj == dj) ? dj : -HUGE_VAL;
             rank += (lj > li) || (lj == li && j < i);
         }
         if (rank < R) s_sel[rank] = i;
@@ -516,12 +525,16 @@ __device__ __forceinline__ void jacobi_body(const double *__restrict__ S, int n,
     }
     if (!converged && tid == 0 && flag) flag[0] = 1;
 
-    // descending order of the diagonal, ties by index
+    // descending order of the diagonal, ties by index (NaN last, flag 3;
+    // the ranks stay a permutation, so every selected column is in range)
     for (int i = tid; i < n; i += EIG_THREADS) {
-        const double li = A[i + n * i];
+        const double di = A[i + n * i];
+        const double li = (di == di) ? di : -HUGE_VAL;
+        if (di != di && flag) flag[0] = 3;
         int rank = 0;
         for (int j = 0; j < n; ++j) {
-            const double lj = A[j + n * j];
+            const double dj = A[j + n * j];
+            const double lj = (dj == dj) ? dj : -HUGE_VAL;
             rank += (lj > li) || (lj == li && j < i);
         }
         if (rank < R) s_sel[rank] = i;

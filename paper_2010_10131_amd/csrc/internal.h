@@ -32,8 +32,10 @@ hipError_t gram_launch(int dtype, int prec, const void *A, const void *B, int64_
 
 // Eigensolver (eig.hip)
 size_t eig_ws_bytes(int64_t n);
+// si_min: the order above which the subspace iteration may replace Jacobi
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
-                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound);
+                      int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound,
+                      int64_t si_min);
 
 // Small FP64 LA and reductions (la.hip)
 int gemm_splits(int m, int n, int k);
@@ -84,7 +86,7 @@ struct BatchStepPlan {
     BatchLaunch prep;
 };
 size_t batch_gram_lds(int prec, int wt);
-size_t batch_eig_lds(int64_t n, int64_t p);   // p: the step's subspace block (0 for n <= 128)
+size_t batch_eig_lds(int64_t n, int64_t p);   // p: the step's subspace block (0: direct Jacobi)
 size_t batch_eig_scratch(int64_t n, int64_t p);
 hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int gram_prec,
                              int ttm_prec, int order, int mode, char *ws, const void *const *Xp,

@@ -4,6 +4,13 @@ both the EIG and the ALS step of Alg. 2 are timed on the same working tensor.
 One record per (shape, mode): the shape features I_n, R_n, J_n (on the current
 working tensor) and the median times of both solvers.
 
+The tensors have the structure Tucker is run on: multilinear rank equal to
+the target ranks plus 1e-4 relative Gaussian noise (the workloads' recipe).
+The eigensolver's time depends on the Gram's spectrum (how many Jacobi
+sweeps it takes), which the shape features cannot see, so the database is
+measured on the kind of spectrum the selector will meet; --data gaussian
+fills the tensors with plain Gaussian values instead.
+
   python -m paper_2010_10131_amd.selector.timing_db --count 2000 --out db.json
 """
 from __future__ import annotations
@@ -60,6 +67,8 @@ def main():
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--gram-prec", default="bf16x6")
     ap.add_argument("--ttm-prec", default="bf16x3")
+    ap.add_argument("--data", choices=("lowrank", "gaussian"), default="lowrank")
+    ap.add_argument("--noise", type=float, default=1e-4)
     ap.add_argument("--out", required=True)
     args = ap.parse_args()
 
@@ -74,16 +83,21 @@ def main():
     t0 = time.time()
     ws_cache = {}
     for si, (dims, ranks) in enumerate(shapes):
-        g = torch.Generator(device=dev)
-        g.manual_seed(args.seed + si)
-        Y = torch.randn(tuple(dims[::-1]), generator=g, device=dev, dtype=torch.float32)
-        Y = Y.permute(*range(len(dims) - 1, -1, -1))
+        if args.data == "lowrank":
+            import workloads
+            Y = workloads.lowrank_plus_noise_device(dims, ranks, nu=args.noise, seed=args.seed + si, device=dev)
+        else:
+            g = torch.Generator(device=dev)
+            g.manual_seed(args.seed + si)
+            Y = torch.randn(tuple(dims[::-1]), generator=g, device=dev, dtype=torch.float32)
+            Y = Y.permute(*range(len(dims) - 1, -1, -1))
         cur = list(dims)
         for n in range(len(dims)):
             R = ranks[n]
             I = cur[n]
             J = int(np.prod(cur)) // I
             rec = {"shape": si, "order": len(dims), "mode": n, "I": I, "R": R, "J": J}
+            Ynext = None
             for solver in ("eig", "als"):
                 try:
                     t, Z = time_step(api, torch, Y, n, R, solver, args.gram_prec, args.ttm_prec,
@@ -93,9 +107,17 @@ def main():
                     rec["t_" + solver] = None
                     rec["err_" + solver] = str(e)
                     Z = None
-                if Z is not None:
-                    Ynext = Z
+                if Z is not None and not bool(torch.isfinite(Z).all()):
+                    # e.g. ALS with R_n above the rank of the unfolding: its
+                    # normal equations are singular; the solver is not an option
+                    rec["t_" + solver] = None
+                    rec["err_" + solver] = "non-finite result"
+                    Z = None
+                if Z is not None and Ynext is None:
+                    Ynext = Z              # the EIG result when there is one
             recs.append(rec)
+            if Ynext is None:
+                break
             Y = Ynext
             cur[n] = R
         if si % 100 == 0 or si + 1 == len(shapes):
@@ -104,6 +126,7 @@ def main():
             torch.cuda.empty_cache()
             # written as it goes, so that a run cut short still leaves its records
             meta = {"count": si + 1, "requested": args.count, "seed": args.seed,
+                    "data": args.data, "noise": args.noise if args.data == "lowrank" else None,
                     "max_elems": args.max_elems, "gram_prec": args.gram_prec,
                     "ttm_prec": args.ttm_prec, "reps": args.reps,
                     "device": torch.cuda.get_device_name(0), "seconds": time.time() - t0}

@@ -13,7 +13,10 @@ pytestmark = pytest.mark.gpu
 # iteration), small and large ranks, a mode of size < 32
 SHAPES = [((40, 36, 33), (4, 5, 6)), ((37, 60, 50), (6, 8, 5)), ((130, 40, 35), (16, 6, 5)),
           ((200, 150, 33), (30, 20, 5)), ((64, 256, 40), (10, 40, 8)), ((96, 96, 96), (12, 12, 12)),
-          ((33, 20, 150), (5, 4, 18)), ((250, 60, 32), (60, 9, 5))]
+          ((33, 20, 150), (5, 4, 18)), ((250, 60, 32), (60, 9, 5)),
+          ((120, 50, 40), (12, 6, 5)), ((110, 4, 5), (25, 3, 4))]
+# ((120, 50, 40), ...): order 120 takes the subspace iteration; ((110, 4, 5), ...):
+# R_1 = 25 exceeds the rank bound 20 of the mode-1 Gram, which keeps the Jacobi
 # ((33, 20, 150), (5, 4, 18)): the mode-3 Gram has rank <= 5 * 4 = 20, below the
 # subspace block max(18 + 16, 27) -> 40, which the plan caps at 20
 

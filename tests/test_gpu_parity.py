@@ -233,6 +233,20 @@ def test_eig_subspace_iteration_gapless_rate(api):
     np.testing.assert_allclose(ev.cpu().numpy(), lo[:R], rtol=10 * rate)
 
 
+def test_eig_nan_input_is_contained(api):
+    """A NaN on the diagonal (a non-finite Gram, e.g. from a failed ALS step
+    upstream) is reported as flag 3 and sorts last, so the selection stays a
+    permutation and no column index leaves the matrix; order 110 keeps V in
+    the workspace, where a stray column would be a stray global address."""
+    import torch
+    S = spd_with_spectrum(2.0 ** (-np.arange(110) / 4.0), 110)
+    S[5, 5] = np.nan
+    U, ev, ws = api.eig_leading(api.to_device(S), 6, max_sweeps=3)
+    torch.cuda.synchronize()
+    assert int(ws[:8].view(dtype=torch.int64).item()) == 3
+    assert U.shape == (110, 6)
+
+
 def test_eig_degenerate_and_cap(api):
     import torch
     S = np.asfortranarray(np.diag([3.0, 1.0, 3.0, 2.0]))
@@ -292,6 +306,9 @@ def test_decomposition_fp64_edge_cases(api, dims, ranks, order):
 @pytest.mark.parametrize("dims,ranks", [
     ((33, 20, 150), (5, 3, 24)),   # mode 3: rank(Gram) <= 15 < R = 24 (direct solver, n > 128)
     ((33, 20, 150), (5, 4, 18)),   # mode 3: rank(Gram) <= 20 < block 40 (block capped at 20)
+    ((120, 50, 40), (12, 6, 5)),   # mode 1, order 120: subspace iteration (block 32)
+    ((110, 4, 5), (25, 3, 4)),     # mode 1, order 110: R above the rank bound 20 -> Jacobi
+    ((24, 100, 9), (6, 40, 3)),    # mode 2, order 100: block 56 capped at the rank bound 54
 ])
 def test_gram_rank_below_the_subspace_block(api, dims, ranks):
     """Ranks at or above what the earlier truncations leave: only X^ and
