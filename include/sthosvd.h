@@ -135,7 +135,8 @@ void sthosvd_plan_destroy(sth_plan *plan);
  * Enqueue-only; the eigenvectors carry the sign convention "largest-magnitude
  * entry positive".  The EIG solver takes the R_n leading eigenvectors by
  * Jacobi up to I_n = 96 and by subspace iteration with Rayleigh-Ritz above
- * (block R_n + 16 rounded up to 8, at most 96 and within the Gram's rank
+ * (block R_n + 16 rounded up to 8, at most 128 with at least 4 guard
+ * vectors, and within the Gram's rank
  * bound; Jacobi otherwise), which yields the leading subspace to working
  * accuracy when the spectrum has a gap after R_n. */
 sth_status sthosvd_run(const sth_plan *plan, const void *X, void *core, double *const *U,
@@ -257,7 +258,7 @@ sth_status ttm_mode_n_prepared(int32_t order, const int64_t *dims, int32_t n, in
  * U (device, n x R FP64, orthonormal, largest-magnitude entry of each column
  * positive) and lam (device, R values, descending; may be NULL).  n <= 128:
  * parallel cyclic Jacobi on S; n > 128 with a subspace block
- * p = R + 16 (rounded up to 8) <= 96: subspace iteration on a
+ * p = R + 16 (rounded up to 8; down to R + 4 near the cap) <= 128: subspace iteration on a
  * seeded Gaussian block with Rayleigh-Ritz (S must then have rank >= p; a
  * Gram matrix of rank below p goes through sthosvd_run, which passes the rank
  * bound of each mode); otherwise Jacobi on S in the workspace.  ws: device

@@ -10,14 +10,16 @@ constexpr int64_t EIG_DIRECT_MAX = 128;  // Jacobi on the whole matrix up to thi
 // workspace above it).  The decompositions, which need the leading subspace
 // only, take the subspace iteration from the next order on when its block fits.
 constexpr int64_t EIG_LDS_DIRECT_MAX = 96;
-constexpr int64_t SI_BLOCK_MAX = 96;     // Rayleigh-Ritz block kept in LDS
+constexpr int64_t SI_BLOCK_MAX = 128;    // Rayleigh-Ritz block (Cholesky-QR and small Jacobi reach 128)
 constexpr int SI_ITERS_DEV = 3;          // subspace iterations before Rayleigh-Ritz
 constexpr int EIG_LDS_AV = 150 * 1024;   // LDS bytes available for Jacobi's A and V
 
-// Block size of the subspace iteration.
+// Block size of the subspace iteration: R + 16 guard vectors, rounded up to
+// 8; near the cap the guard shrinks, down to 4 vectors.
 __host__ __device__ inline int64_t si_block_dev(int64_t n, int64_t R) {
-    int64_t p = R + 16;   // 16 guard vectors beyond the R wanted ones
+    int64_t p = R + 16;
     p = (p + 7) / 8 * 8;
+    if (p > SI_BLOCK_MAX && R + 4 <= SI_BLOCK_MAX) p = SI_BLOCK_MAX;
     return p < n ? p : n;
 }
 inline int64_t si_block_host(int64_t n, int64_t R) { return si_block_dev(n, R); }

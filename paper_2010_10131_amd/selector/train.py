@@ -69,16 +69,23 @@ def choose(api, recs, w):
 
 
 def evaluate(choice, te, ta):
+    """Accuracy, totals and regret over the modes where both solvers have a
+    time (a missing time is a solver beyond its limits or, for ALS, a
+    non-finite result: R_n above the rank of the unfolding, which the shape
+    features cannot see); those modes are counted separately."""
     best = np.minimum(te, ta)
     chosen = np.where(choice == 1, ta, te)
-    valid = best < BIG
+    valid = (te < BIG) & (ta < BIG)
     truth = (ta < te).astype(int)
     acc = float(np.mean(choice[valid] == truth[valid]))
     tot_best = float(best[valid].sum())
-    tot_chosen = float(np.minimum(chosen[valid], BIG).sum())
+    tot_chosen = float(chosen[valid].sum())
     eig_ok = te < BIG
     als_ok = ta < BIG
     return {"accuracy": acc, "modes": int(valid.sum()),
+            "modes_one_solver_only": int((eig_ok != als_ok).sum()),
+            "chose_a_missing_solver": int(((choice == 1) & ~als_ok & eig_ok).sum()
+                                          + ((choice == 0) & ~eig_ok & als_ok).sum()),
             "total_ms_exhaustive": tot_best, "total_ms_selected": tot_chosen,
             "regret": tot_chosen / tot_best - 1.0,
             "total_ms_always_eig": float(te[eig_ok].sum()) if eig_ok.all() else None,

@@ -201,12 +201,14 @@ def test_eig_parity(api, n, R):
     np.testing.assert_allclose(U.T @ U, np.eye(R), atol=1e-12)
 
 
-@pytest.mark.parametrize("n,R", [(129, 8), (200, 16), (256, 40), (512, 64), (512, 8)])
+@pytest.mark.parametrize("n,R", [(129, 8), (200, 16), (256, 40), (512, 64), (512, 8),
+                                 (300, 100), (478, 122)])   # blocks 120 and 128 (guard 6)
 def test_eig_subspace_iteration_parity(api, n, R):
     """n > 128: subspace iteration + Rayleigh-Ritz.  The spectrum has the
     structure of a low-rank-plus-noise Gram (a gap after the R leading
     eigenvalues), so the leading eigenvectors are well determined."""
-    lam = np.concatenate([2.0 ** (-np.arange(R) / 4.0), 1e-9 * np.exp(-np.arange(n - R) / n)])
+    # the R leading eigenvalues span at most 2^-8, then a gap to the 1e-9 floor
+    lam = np.concatenate([2.0 ** (-np.arange(R) * min(0.25, 8.0 / R)), 1e-9 * np.exp(-np.arange(n - R) / n)])
     S = spd_with_spectrum(lam, n + R)
     U, ev, ws = api.eig_leading(api.to_device(S), R)
     U, ev = api.to_numpy(U), ev.cpu().numpy()
