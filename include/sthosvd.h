@@ -326,7 +326,9 @@ sth_status sth_selector_features(int64_t I, int64_t R, int64_t J, float *out10);
 sth_status sth_selector_predict(const float *weights, int64_t I, int64_t R, int64_t J, float *out2);
 /* Host: the solver sthosvd_plan picks for a mode under STH_SOLVER_AUTO
  * (solver_out: STH_SOLVER_EIG or STH_SOLVER_ALS): the smaller predicted
- * time, then the solvers' limits (EIG needs I_n <= 512, ALS R_n <= 128). */
+ * time, then the solvers' limits (EIG needs I_n <= 512, ALS R_n <= 128; above
+ * order 128 with R_n in 125..128, where EIG would run cyclic Jacobi on the
+ * whole Gram, ALS). */
 sth_status sth_selector_choose(const float *weights, int64_t I, int64_t R, int64_t J, int32_t *solver_out);
 
 /* Device training kernels.  X: device, 10 x B features (column per sample);

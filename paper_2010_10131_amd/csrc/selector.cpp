@@ -48,6 +48,8 @@ int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *wei
     selector_predict(weights, f, y);
     int choice = (y[1] < y[0]) ? STH_SOLVER_ALS : STH_SOLVER_EIG;
     if (choice == STH_SOLVER_ALS && R > SEL_MAX_ALS_R) choice = STH_SOLVER_EIG;
+    if (choice == STH_SOLVER_EIG && I > SEL_EIG_DIRECT_MAX && R > SEL_EIG_SI_MAX_R && R <= SEL_MAX_ALS_R)
+        choice = STH_SOLVER_ALS;
     if (choice == STH_SOLVER_EIG && I > SEL_MAX_EIG_N) choice = STH_SOLVER_ALS;
     return choice;
 }

@@ -25,9 +25,15 @@ void selector_predict(const float *weights, const float *feat10, float *out2);
 // the other one).
 constexpr int64_t SEL_MAX_EIG_N = 512;   // eigensolver: I_n x I_n Gram
 constexpr int64_t SEL_MAX_ALS_R = 128;   // ALS: R_n x R_n Cholesky in LDS
+// EIG above order 128 with R_n > 124 leaves no room for the subspace block's
+// guard vectors and runs cyclic Jacobi on the whole Gram, two orders of
+// magnitude slower than ALS there: ALS is taken whenever its limit allows.
+constexpr int64_t SEL_EIG_SI_MAX_R = 124;
+constexpr int64_t SEL_EIG_DIRECT_MAX = 128;
 
 // 0 = EIG, 1 = ALS: argmin of the predicted times (EIG on ties), then the
-// solver limits (EIG needs I_n <= SEL_MAX_EIG_N, ALS R_n <= SEL_MAX_ALS_R).
+// solver limits (EIG needs I_n <= SEL_MAX_EIG_N, ALS R_n <= SEL_MAX_ALS_R) and
+// the whole-Gram Jacobi rule above.
 int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *weights);
 
 }  // namespace sth
