@@ -91,10 +91,11 @@ constexpr int JS_MAXM = 64;
 constexpr int JS_VTHREADS = EIG_THREADS - 64;   // waves 1.. update V
 constexpr int JS_CV = 4;                        // V pairs per batch of reads
 
-// Dynamic LDS of jacobi_small_body: A (ne x ne) and, when v_lds, V (ne x ne).
+// Dynamic LDS of jacobi_small_body: A (upper triangle of an ne x ne array
+// with the odd leading dimension ne + 1) and, when v_lds, V (ne x ne).
 __host__ __device__ inline size_t jacobi_small_lds(int64_t n, bool v_lds) {
     const int64_t ne = n + (n & 1);
-    return (size_t)(ne * ne * (v_lds ? 2 : 1)) * 8;
+    return (size_t)(ne * (ne + 1) + (v_lds ? ne * ne : 0)) * 8;
 }
 // Global V (when not in LDS): ne x ne doubles, 16-byte aligned.
 __host__ __device__ inline size_t jacobi_small_vg(int64_t n) {
@@ -102,54 +103,63 @@ __host__ __device__ inline size_t jacobi_small_vg(int64_t n) {
     return (size_t)(ne * ne) * 8;
 }
 
-// A <- J^T A J for the rotations of `set`: the thread owns row pair Ia and
-// the column pairs ja0, ja0 + ja, ... (nka of them), CA per batch of reads.
-template <int CA>
-__device__ __forceinline__ void jacobi_small_update_a(double *__restrict__ A, int ne, int m,
-                                                      const int2 *__restrict__ pq,
-                                                      const double2 *__restrict__ cs, int Ia,
-                                                      int ja0, int ja, int nka) {
-    if (nka == 0) return;
-    const int2 pqI = pq[Ia];
-    const double2 csI = cs[Ia];
-    const int pI = pqI.x, qI = pqI.y;
-    const double ci = csI.x, si = csI.y;
-#pragma unroll 1
-    for (int k0 = 0; k0 < nka; k0 += CA) {
-        int pj[CA], qj[CA];
-        double cj[CA], sj[CA], a[CA][4];
+// Position of the symmetric entry (r, c) in the stored upper triangle.
+__device__ __forceinline__ int sym_at(int r, int c, int la) {
+    return min(r, c) + la * max(r, c);
+}
+
+// A <- J^T A J for the rotations of `set`, on the upper triangle only: the
+// m (m + 1) / 2 blocks of pair rows I <= pair columns J are dealt to the
+// threads in row order, block b to thread b mod EIG_THREADS (the thread's
+// blocks bI[k], bJ[k], k < nb, decoded once; unused slots hold pair 0).  A
+// block's four entries are read from and written to their stored positions;
+// in a diagonal block (I = J) the (1, 0) entry is the stored (0, 1) entry
+// again, so its result goes to the unused lower slot.  The odd leading
+// dimension keeps both access directions (consecutive rows or consecutive
+// columns across a wave) free of bank conflicts.
+constexpr int JS_SB = 5;   // blocks per thread: 64 * 65 / 2 = 2080 over 512 threads
+template <int SB>
+__device__ __forceinline__ void jacobi_small_update_sym(double *__restrict__ A, int la,
+                                                        const int2 *__restrict__ pq,
+                                                        const double2 *__restrict__ cs,
+                                                        const int *bI, const int *bJ, int nb) {
+    int r00[SB], r01[SB], r10[SB], r11[SB], w10[SB];
+    double ci[SB], si[SB], cj[SB], sj[SB], a[SB][4];
 #pragma unroll
-        for (int k = 0; k < CA; ++k) {
-            const int J = min(ja0 + (k0 + k) * ja, m - 1);
-            const int2 t = pq[J];
-            const double2 u = cs[J];
-            pj[k] = ne * t.x;
-            qj[k] = ne * t.y;
-            cj[k] = u.x;
-            sj[k] = u.y;
-        }
-#pragma unroll
-        for (int k = 0; k < CA; ++k) {
-            if (k0 + k < nka) {
-                a[k][0] = A[pI + pj[k]];
-                a[k][1] = A[pI + qj[k]];
-                a[k][2] = A[qI + pj[k]];
-                a[k][3] = A[qI + qj[k]];
-            } else {
-                a[k][0] = a[k][1] = a[k][2] = a[k][3] = 0.0;
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < CA; ++k)
-            if (k0 + k < nka) {
-                const double b00 = ci * a[k][0] - si * a[k][2], b01 = ci * a[k][1] - si * a[k][3];
-                const double b10 = si * a[k][0] + ci * a[k][2], b11 = si * a[k][1] + ci * a[k][3];
-                A[pI + pj[k]] = cj[k] * b00 - sj[k] * b01;
-                A[pI + qj[k]] = sj[k] * b00 + cj[k] * b01;
-                A[qI + pj[k]] = cj[k] * b10 - sj[k] * b11;
-                A[qI + qj[k]] = sj[k] * b10 + cj[k] * b11;
-            }
+    for (int k = 0; k < SB; ++k) {
+        const int2 tI = pq[bI[k]], tJ = pq[bJ[k]];
+        const double2 uI = cs[bI[k]], uJ = cs[bJ[k]];
+        ci[k] = uI.x;
+        si[k] = uI.y;
+        cj[k] = uJ.x;
+        sj[k] = uJ.y;
+        r00[k] = sym_at(tI.x, tJ.x, la);
+        r01[k] = sym_at(tI.x, tJ.y, la);
+        r10[k] = sym_at(tI.y, tJ.x, la);
+        r11[k] = sym_at(tI.y, tJ.y, la);
+        w10[k] = bI[k] == bJ[k] ? tI.y + la * tI.x : r10[k];
     }
+#pragma unroll
+    for (int k = 0; k < SB; ++k) {
+        if (k < nb) {
+            a[k][0] = A[r00[k]];
+            a[k][1] = A[r01[k]];
+            a[k][2] = A[r10[k]];
+            a[k][3] = A[r11[k]];
+        } else {
+            a[k][0] = a[k][1] = a[k][2] = a[k][3] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < SB; ++k)
+        if (k < nb) {
+            const double b00 = ci[k] * a[k][0] - si[k] * a[k][2], b01 = ci[k] * a[k][1] - si[k] * a[k][3];
+            const double b10 = si[k] * a[k][0] + ci[k] * a[k][2], b11 = si[k] * a[k][1] + ci[k] * a[k][3];
+            A[r00[k]] = cj[k] * b00 - sj[k] * b01;
+            A[r01[k]] = sj[k] * b00 + cj[k] * b01;
+            A[w10[k]] = cj[k] * b10 - sj[k] * b11;
+            A[r11[k]] = sj[k] * b10 + cj[k] * b11;
+        }
 }
 
 // V <- V J for the rotations of `set`: the thread owns rows (2 rp, 2 rp + 1)
@@ -209,8 +219,9 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
 
     const int ne = n + (n & 1), m = ne / 2;
     const double thresh = (double)n * 2.220446049250313e-16;
-    double *A = s_e;                         // ne x ne, leading dimension ne
-    double *V = VLDS ? s_e + ne * ne : Vg;   // ne x ne, leading dimension ne
+    const int la = ne + 1;                   // odd leading dimension of A
+    double *A = s_e;                         // upper triangle of ne x ne, leading dimension la
+    double *V = VLDS ? s_e + ne * la : Vg;   // ne x ne, leading dimension ne
     const int tid = threadIdx.x;
     for (int e0 = tid; e0 < ne * ne; e0 += 4 * EIG_THREADS) {
         double v[4];
@@ -223,26 +234,42 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int e = e0 + u * EIG_THREADS;
-            if (e < ne * ne) A[e] = v[u];
+            if (e < ne * ne) A[e % ne + la * (e / ne)] = v[u];
         }
     }
     for (int e = tid; e < ne * ne; e += EIG_THREADS) {
         const int i = e % ne, j = e / ne;
         V[e] = (i == j && i < n) ? 1.0 : 0.0;
     }
-    // A: thread owns row pair Ia for the column pairs ja0, ja0 + ja, ...
-    const int ja = EIG_THREADS / m, Ia = tid % m, ja0 = tid / m;
-    const int nka = ja0 < ja ? (m - ja0 + ja - 1) / ja : 0;
-    const int cap = (m + ja - 1) / ja;       // the most column pairs of any thread
+    // A: the thread's pair blocks (I, J), I <= J: b = tid + k EIG_THREADS in row order
+    const int nblk = m * (m + 1) / 2;
+    const int cap = (nblk + EIG_THREADS - 1) / EIG_THREADS;   // the most blocks of any thread
+    int bI[JS_SB], bJ[JS_SB], nb = 0;
+#pragma unroll
+    for (int k = 0; k < JS_SB; ++k) {
+        int b = tid + k * EIG_THREADS, I = 0;
+        if (b < nblk) {
+            while (b >= m - I) {
+                b -= m - I;
+                ++I;
+            }
+            nb = k + 1;
+        } else {
+            b = 0;
+        }
+        bI[k] = I;
+        bJ[k] = I + b;
+    }
     // V (waves 1..): thread owns row pair rp for the pairs jw0, jw0 + jw, ...
     const int tv = tid - 64;
     const int jw = JS_VTHREADS / m, rp = tv >= 0 ? tv % m : 0, jw0 = tv >= 0 ? tv / m : jw;
     const int nkw = (tv >= 0 && jw0 < jw) ? (m - jw0 + jw - 1) / jw : 0;
     double2 *V2 = reinterpret_cast<double2 *>(V);
     auto update_a = [&](int set) {
-        if (cap <= 2) jacobi_small_update_a<2>(A, ne, m, s_pq[set], s_cs[set], Ia, ja0, ja, nka);
-        else if (cap <= 4) jacobi_small_update_a<4>(A, ne, m, s_pq[set], s_cs[set], Ia, ja0, ja, nka);
-        else jacobi_small_update_a<8>(A, ne, m, s_pq[set], s_cs[set], Ia, ja0, ja, nka);
+        if (cap <= 1) jacobi_small_update_sym<1>(A, la, s_pq[set], s_cs[set], bI, bJ, nb);
+        else if (cap <= 2) jacobi_small_update_sym<2>(A, la, s_pq[set], s_cs[set], bI, bJ, nb);
+        else if (cap <= 3) jacobi_small_update_sym<3>(A, la, s_pq[set], s_cs[set], bI, bJ, nb);
+        else jacobi_small_update_sym<JS_SB>(A, la, s_pq[set], s_cs[set], bI, bJ, nb);
     };
     __syncthreads();
 
@@ -250,12 +277,12 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
     bool converged = false;
     double prev_off2 = -1.0;
     for (;;) {
-        double off = 0.0, fro = 0.0;
+        double off = 0.0, fro = 0.0;   // over the stored triangle, off-diagonal entries twice
         for (int j = 0; j < n; ++j)
-            for (int i = tid; i < n; i += EIG_THREADS) {
-                const double v = A[i + ne * j];
-                fro += v * v;
-                if (i != j) off += v * v;
+            for (int i = tid; i <= j; i += EIG_THREADS) {
+                const double v = A[i + la * j];
+                fro += (i == j ? 1.0 : 2.0) * v * v;
+                if (i != j) off += 2.0 * v * v;
             }
         for (int o = 32; o > 0; o >>= 1) {
             off += __shfl_xor(off, o);
@@ -300,7 +327,7 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
                         q = t;
                     }
                     double c, sn;
-                    rot = jacobi_rotation(A[p + ne * p], A[q + ne * q], A[p + ne * q], thresh, s_floor, c, sn);
+                    rot = jacobi_rotation(A[p + la * p], A[q + la * q], A[p + la * q], thresh, s_floor, c, sn);
                     s_pq[set][tid] = make_int2(p, q);
                     s_cs[set][tid] = make_double2(c, sn);
                 }
@@ -328,12 +355,12 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
     // (non-finite input) sorts last and raises flag 3, so that the ranks stay
     // a permutation of 0..n-1 and every selected column is in range.
     for (int i = tid; i < n; i += EIG_THREADS) {
-        const double di = A[i + ne * i];
+        const double di = A[i + la * i];
         const double li = (di == di) ? di : -HUGE_VAL;
         if (di != di && flag) flag[0] = 3;
         int rank = 0;
         for (int j = 0; j < n; ++j) {
-            const double dj = A[j + ne * j];
+            const double dj = A[j + la * j];
             const double lj = (dj == dj) ? dj : -HUGE_VAL;
             rank += (lj > li) || (lj == li && j < i);
         }
@@ -352,7 +379,7 @@ __device__ __forceinline__ void jacobi_small_body(const double *__restrict__ S, 
             }
         }
         s_sign[r] = V[arg + ne * col] < 0 ? -1.0 : 1.0;
-        if (lam) lam[r] = A[col + ne * col];
+        if (lam) lam[r] = A[col + la * col];
     }
     __syncthreads();
     for (int e = tid; e < n * R; e += EIG_THREADS) {
