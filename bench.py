@@ -40,8 +40,8 @@ T2_BAR = 1e-5
 # for a plain 512 MiB device copy of known size (fetch x 2.000, write x 1.000).
 # Source: profiles/ttm_mode1_512cubed_bf16x3_hbm_traffic.md.  Valid only for
 # that kernel as it is; None for any other TTM precision.
-TTM_PMC = {"ttm": "bf16x3", "fetch_kib": 262797.5, "fetch_scale": 2.000,
-           "write_kib": 65595.4, "write_scale": 1.000}
+TTM_PMC = {"ttm": "bf16x3", "fetch_kib": 262943.0, "fetch_scale": 2.000,
+           "write_kib": 66640.1, "write_scale": 1.000}
 
 
 def log(msg):
