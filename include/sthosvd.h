@@ -136,8 +136,9 @@ void sthosvd_plan_destroy(sth_plan *plan);
  * entry positive".  The EIG solver takes the R_n leading eigenvectors by
  * Jacobi up to I_n = 96 and by subspace iteration with Rayleigh-Ritz above
  * (block R_n + 16 rounded up to 8, at most 128 with at least 4 guard
- * vectors, and within the Gram's rank
- * bound; Jacobi otherwise), which yields the leading subspace to working
+ * vectors, and within the Gram's rank bound; Jacobi otherwise); FP32 data
+ * also takes the subspace iteration for I_n = 49..96 when the block is at
+ * most I_n / 2.  The iteration yields the leading subspace to working
  * accuracy when the spectrum has a gap after R_n. */
 sth_status sthosvd_run(const sth_plan *plan, const void *X, void *core, double *const *U,
                        double *const *eigvals, const double *const *als_init, uint64_t seed,

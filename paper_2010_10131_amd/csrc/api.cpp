@@ -70,6 +70,7 @@ static const int MAX_ORDER = 8;
 static const int64_t MAX_EIG_N = SEL_MAX_EIG_N;   // I_n x I_n Gram and eigensolver
 static const int64_t EIG_DIRECT_MAX_HOST = 128;
 static const int64_t EIG_LDS_DIRECT_MAX_HOST = 96;   // Jacobi with A and V in LDS
+static const int64_t EIG_SI_MIN_HOST = 48;   // FP32 data: subspace iteration above, block <= I / 2
 static const int64_t SI_BLOCK_MAX_HOST = 96;
 static int64_t si_block_host_api(int64_t n, int64_t R) {
     int64_t p = R + 16;   // the same rule as the device side
@@ -348,8 +349,10 @@ static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *s
     if (stp.solver == STH_SOLVER_EIG) {
         // Alg. 2 lines 6-8
         HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
-        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M,
-                          EIG_LDS_DIRECT_MAX_HOST), "eig");
+        // FP64 data keeps the exact Jacobi up to the LDS limit (order 96)
+        const int64_t si_min = p->dtype == STH_F64 ? EIG_LDS_DIRECT_MAX_HOST : EIG_SI_MIN_HOST;
+        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M, si_min),
+               "eig");
         HIPCHK(ttm_prep_u(Un, stp.I, stp.R, 0, tp, uq, s), "ttm prep");
         HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
         return STH_OK;
@@ -889,7 +892,11 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             if (b.R > 64) return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n > 64 in the batched path", t, s);
             b.sib = 0;
             const int64_t pb = si_block_host_api(b.I, b.R);
-            if (b.I > EIG_LDS_DIRECT_MAX_HOST && b.I <= EIG_DIRECT_MAX_HOST && pb <= SI_BLOCK_MAX_HOST &&
+            if (b.I > EIG_SI_MIN_HOST && b.I <= EIG_LDS_DIRECT_MAX_HOST && 2 * pb <= b.I && b.R <= P) {
+                // orders 49..96: the subspace iteration when its block is at
+                // most half the order (the rule of the single-tensor path)
+                b.sib = (int32_t)std::min<int64_t>(pb, P);
+            } else if (b.I > EIG_LDS_DIRECT_MAX_HOST && b.I <= EIG_DIRECT_MAX_HOST && pb <= SI_BLOCK_MAX_HOST &&
                 pb < b.I && b.R <= P) {
                 // orders 97..128: the subspace iteration when its block fits
                 // (the Jacobi would keep V in the workspace there)

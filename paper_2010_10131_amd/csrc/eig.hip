@@ -83,7 +83,7 @@ int64_t si_block(int64_t n, int64_t R) { return si_block_host(n, R); }
 // si_min: the order above which the subspace iteration may be used
 bool use_si(int64_t n, int64_t R, int64_t si_min) {
     const int64_t p = si_block(n, R);
-    return n > si_min && p <= SI_BLOCK_MAX && p < n;
+    return n > si_min && p <= SI_BLOCK_MAX && p < n && (n > EIG_LDS_DIRECT_MAX || 2 * p <= n);
 }
 
 struct SiWs {
@@ -177,7 +177,7 @@ size_t eig_ws_bytes(int64_t n) {
     size_t b = jacobi_ws(n);
     // subspace iteration for any R that selects it
     for (int64_t R = 1; R <= n; ++R)
-        if (use_si(n, R, EIG_LDS_DIRECT_MAX)) b = std::max(b, si_bytes(n, si_block(n, R)));
+        if (use_si(n, R, EIG_SI_MIN)) b = std::max(b, si_bytes(n, si_block(n, R)));
     return b;
 }
 

@@ -10,6 +10,10 @@ constexpr int64_t EIG_DIRECT_MAX = 128;  // Jacobi on the whole matrix up to thi
 // workspace above it).  The decompositions, which need the leading subspace
 // only, take the subspace iteration from the next order on when its block fits.
 constexpr int64_t EIG_LDS_DIRECT_MAX = 96;
+// FP32-data decompositions take the subspace iteration from order 49 when
+// its block is at most half the order (leading subspace to working accuracy
+// on a gapped spectrum at a fraction of the full Jacobi's sweeps).
+constexpr int64_t EIG_SI_MIN = 48;
 constexpr int64_t SI_BLOCK_MAX = 128;    // Rayleigh-Ritz block (Cholesky-QR and small Jacobi reach 128)
 constexpr int SI_ITERS_DEV = 3;          // subspace iterations before Rayleigh-Ritz
 constexpr int EIG_LDS_AV = 150 * 1024;   // LDS bytes available for Jacobi's A and V

@@ -325,6 +325,23 @@ def test_gram_rank_below_the_subspace_block(api, dims, ranks):
         np.testing.assert_allclose(Un[n].T @ Un[n], np.eye(ranks[n]), atol=1e-12)
 
 
+@pytest.mark.parametrize("dims,ranks", [
+    ((96, 64, 50), (24, 16, 8)),   # orders 96, 64, 50: blocks 40, 32, 24 <= I / 2 -> subspace iteration
+    ((90, 70, 60), (40, 30, 6)),   # orders 90, 70: blocks 56, 48 > I / 2 -> Jacobi; order 60: block 24
+    ((49, 81, 33), (8, 17, 4)),    # order 49: block 24 (the first order taken); order 81: block 40
+])
+def test_fp32_subspace_iteration_from_order_49(api, dims, ranks):
+    """FP32 data takes the subspace iteration for orders 49..96 when its
+    block is at most half the order; FP64 data keeps the exact Jacobi."""
+    X = wl.lowrank_plus_noise(dims, ranks, "0.9", 1e-4, 23, "float32")
+    Go, Uo, _ = oracle.sthosvd(X, ranks)
+    G, U, _ = api.sthosvd(api.to_device(X), ranks, "fp64", "fp32")
+    t1, t2, _, Un = t1_t2(api, X, G, U, Go, Uo)
+    assert t1 <= 1e-5 and t2 <= 1e-5, (t1, t2)
+    for n in range(3):
+        np.testing.assert_allclose(Un[n].T @ Un[n], np.eye(ranks[n]), atol=1e-12)
+
+
 @pytest.mark.parametrize("variant_dims,ranks,per_mode", [
     ((24, 20, 18), (4, 5, 3), ("als", "als", "als")),
     ((24, 20, 18), (4, 5, 3), ("eig", "als", "eig")),
