@@ -76,7 +76,8 @@ typedef enum {
 typedef enum {
     STH_SOLVER_EIG = 0,   /* Gram + FP64 eigensolver + TTM (Alg. 2 EIG branch) */
     STH_SOLVER_ALS = 1,   /* Alg. 3 + QR + TTM (Alg. 2 ALS branch) */
-    STH_SOLVER_AUTO = 2   /* per-mode choice by the learned cost model (Sec. IV analogue) */
+    STH_SOLVER_AUTO = 2,  /* per-mode choice by the learned cost model (Sec. IV analogue) */
+    STH_SOLVER_AUTO_TREE = 3   /* per-mode choice by the decision tree of Sec. IV-B */
 } sth_solver;
 
 /* Description of one decomposition.  Zero-initialize and fill. */
@@ -111,7 +112,8 @@ const char *sth_version(void);
 
 /* Validates d, fixes the per-mode shapes (L_n, I_n, M_n, J_n on the current
  * working tensor), the solver of every mode (the learned selector runs here,
- * on the host, for STH_SOLVER_AUTO) and the workspace layout.  Host work only.
+ * on the host, for STH_SOLVER_AUTO and STH_SOLVER_AUTO_TREE) and the workspace
+ * layout.  Host work only.
  * *plan receives a new plan (free with sthosvd_plan_destroy); *workspace_bytes
  * the device workspace sthosvd_run needs. */
 sth_status sthosvd_plan(const sth_desc *d, sth_plan **plan, size_t *workspace_bytes);
@@ -331,6 +333,14 @@ sth_status sth_selector_predict(const float *weights, int64_t I, int64_t R, int6
  * order 128 with R_n in 125..128, where EIG would run cyclic Jacobi on the
  * whole Gram, ALS). */
 sth_status sth_selector_choose(const float *weights, int64_t I, int64_t R, int64_t J, int32_t *solver_out);
+
+/* Host: the solver sthosvd_plan picks for a mode under STH_SOLVER_AUTO_TREE:
+ * the class of the compiled-in decision tree (Sec. IV-B: CART on the Table I
+ * features, depth and class weights by cross-validated grid search, trained
+ * on the same timing database as the MLP), then the same solver limits and
+ * whole-Gram rule as sth_selector_choose.  I, R, J >= 1, R <= I, else
+ * STH_ERR_INVALID. */
+sth_status sth_selector_tree_choose(int64_t I, int64_t R, int64_t J, int32_t *solver_out);
 
 /* Device training kernels.  X: device, 10 x B features (column per sample);
  * T: device, 2 x B targets; params: device packed floats; ws: device scratch

@@ -18,7 +18,7 @@ STATUS_NAMES = ["OK", "ERR_INVALID", "ERR_LAYOUT", "ERR_NOMEM", "ERR_HIP", "ERR_
 
 STH_F64, STH_F32 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
-SOLVER = {"eig": 0, "als": 1, "auto": 2}
+SOLVER = {"eig": 0, "als": 1, "auto": 2, "auto_tree": 3}
 
 
 class SthError(RuntimeError):
@@ -103,6 +103,7 @@ SIGNATURES = {
     "sth_selector_predict": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), _i64, _i64, _i64,
                                             ctypes.POINTER(ctypes.c_float)]),
     "sth_selector_choose": (ctypes.c_int, [ctypes.POINTER(ctypes.c_float), _i64, _i64, _i64, _i32p]),
+    "sth_selector_tree_choose": (ctypes.c_int, [_i64, _i64, _i64, _i32p]),
     "sth_mlp_workspace": (_sz, [_i64]),
     "sth_mlp_forward": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _sz, _vp]),
     "sth_mlp_loss_grad": (ctypes.c_int, [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _sz, _vp]),

@@ -406,6 +406,13 @@ def selector_choose(I: int, R: int, J: int, weights: Optional[np.ndarray] = None
     return "als" if out.value == SOLVER["als"] else "eig"
 
 
+def selector_tree_choose(I: int, R: int, J: int) -> str:
+    """The solver sthosvd_plan picks for a mode under solver="auto_tree"."""
+    out = ctypes.c_int32()
+    check(_lib.load().sth_selector_tree_choose(I, R, J, ctypes.byref(out)))
+    return "als" if out.value == SOLVER["als"] else "eig"
+
+
 def mlp_forward(params: torch.Tensor, X: torch.Tensor) -> torch.Tensor:
     """Y (2 x B) of the selector network on device features X (10 x B)."""
     L = _lib.load()

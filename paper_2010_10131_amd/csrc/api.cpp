@@ -184,7 +184,7 @@ static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_ou
     } else {
         for (int k = 0; k < N; ++k) order[k] = k;
     }
-    if (d->solver < STH_SOLVER_EIG || d->solver > STH_SOLVER_AUTO) return fail(STH_ERR_INVALID, "solver %d", d->solver);
+    if (d->solver < STH_SOLVER_EIG || d->solver > STH_SOLVER_AUTO_TREE) return fail(STH_ERR_INVALID, "solver %d", d->solver);
     if (d->als_iters < 0) return fail(STH_ERR_INVALID, "als_iters < 0");
     if (d->eig_max_sweeps < 0) return fail(STH_ERR_INVALID, "eig_max_sweeps < 0");
 
@@ -212,13 +212,16 @@ static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_ou
         int solver = d->solver;
         if (d->per_mode) {
             solver = d->per_mode[stp.n];
-            if (solver != STH_SOLVER_EIG && solver != STH_SOLVER_ALS && solver != STH_SOLVER_AUTO) {
+            if (solver != STH_SOLVER_EIG && solver != STH_SOLVER_ALS && solver != STH_SOLVER_AUTO &&
+                solver != STH_SOLVER_AUTO_TREE) {
                 delete p;
                 return fail(STH_ERR_INVALID, "per_mode[%d] = %d", stp.n, solver);
             }
         }
         if (solver == STH_SOLVER_AUTO) {
             solver = selector_choose(stp.I, stp.R, stp.L * stp.M, N, d->mlp_weights);
+        } else if (solver == STH_SOLVER_AUTO_TREE) {
+            solver = selector_tree_choose(stp.I, stp.R, stp.L * stp.M);
         }
         if (solver == STH_SOLVER_EIG && stp.I > MAX_EIG_N) {
             delete p;
@@ -728,6 +731,12 @@ extern "C" sth_status sth_selector_choose(const float *weights, int64_t I, int64
                                           int32_t *solver_out) {
     if (I < 1 || R < 1 || R > I || J < 1 || !solver_out) return fail(STH_ERR_INVALID, "bad selector input");
     *solver_out = selector_choose(I, R, J, 0, weights);
+    return STH_OK;
+}
+
+extern "C" sth_status sth_selector_tree_choose(int64_t I, int64_t R, int64_t J, int32_t *solver_out) {
+    if (I < 1 || R < 1 || R > I || J < 1 || !solver_out) return fail(STH_ERR_INVALID, "bad selector input");
+    *solver_out = selector_tree_choose(I, R, J);
     return STH_OK;
 }
 

@@ -9,6 +9,7 @@
 namespace sth {
 
 #include "selector_weights.inc"  // kSelectorWeights[SEL_NPARAM], kSelectorTrained
+#include "selector_tree.inc"     // kTreeNodes, kTreeFeature, kTreeThreshold, kTreeLeft, kTreeRight, kTreeClass
 
 void selector_features(int64_t I, int64_t R, int64_t J, float *f) {
     const double i = (double)I, r = (double)R, j = (double)J;
@@ -41,17 +42,29 @@ void selector_predict(const float *w, const float *x, float *y) {
     }
 }
 
-int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *weights) {
-    (void)order;
-    float f[SEL_IN], y[SEL_OUT];
-    selector_features(I, R, J, f);
-    selector_predict(weights, f, y);
-    int choice = (y[1] < y[0]) ? STH_SOLVER_ALS : STH_SOLVER_EIG;
+static int apply_limits(int choice, int64_t I, int64_t R) {
     if (choice == STH_SOLVER_ALS && R > SEL_MAX_ALS_R) choice = STH_SOLVER_EIG;
     if (choice == STH_SOLVER_EIG && I > SEL_EIG_DIRECT_MAX && R > SEL_EIG_SI_MAX_R && R <= SEL_MAX_ALS_R)
         choice = STH_SOLVER_ALS;
     if (choice == STH_SOLVER_EIG && I > SEL_MAX_EIG_N) choice = STH_SOLVER_ALS;
     return choice;
+}
+
+int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *weights) {
+    (void)order;
+    float f[SEL_IN], y[SEL_OUT];
+    selector_features(I, R, J, f);
+    selector_predict(weights, f, y);
+    return apply_limits((y[1] < y[0]) ? STH_SOLVER_ALS : STH_SOLVER_EIG, I, R);
+}
+
+int selector_tree_choose(int64_t I, int64_t R, int64_t J) {
+    float f[SEL_IN];
+    selector_features(I, R, J, f);
+    int k = 0;
+    for (int depth = 0; kTreeFeature[k] >= 0 && depth < kTreeNodes; ++depth)
+        k = (f[kTreeFeature[k]] <= kTreeThreshold[k]) ? kTreeLeft[k] : kTreeRight[k];
+    return apply_limits(kTreeClass[k] ? STH_SOLVER_ALS : STH_SOLVER_EIG, I, R);
 }
 
 }  // namespace sth

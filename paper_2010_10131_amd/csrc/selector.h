@@ -36,4 +36,8 @@ constexpr int64_t SEL_EIG_DIRECT_MAX = 128;
 // the whole-Gram Jacobi rule above.
 int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *weights);
 
+// 0 = EIG, 1 = ALS: the compiled-in decision tree's class, then the same
+// solver limits and whole-Gram rule.
+int selector_tree_choose(int64_t I, int64_t R, int64_t J);
+
 }  // namespace sth
