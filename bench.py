@@ -321,7 +321,8 @@ def bench_batched(args, api, torch, dev, gp, tp):
 
 def bench_selector(api, torch, dev, gp, tp, reps=3):
     """The 48^5 FP32 workload (ranks 8) under the learned per-mode solver
-    choice, against always-EIG, always-ALS and the exhaustive choice (each
+    choice (the MLP, "auto", and the decision tree, "auto_tree"), against
+    always-EIG, always-ALS and the exhaustive choice (each
     mode's two steps timed on the working tensor, the faster one kept)."""
     w = wl.C5
     t0 = time.time()
@@ -347,6 +348,7 @@ def bench_selector(api, torch, dev, gp, tp, reps=3):
         return ms, [names[v] for v in plan.solvers]
 
     auto_ms, auto_choice = timed(solver="auto")
+    tree_ms, tree_choice = timed(solver="auto_tree")
     eig_ms, _ = timed(solver="eig")
     als_ms, _ = timed(solver="als")
     # exhaustive: both steps of every mode on the working tensor, keep the faster
@@ -370,11 +372,14 @@ def bench_selector(api, torch, dev, gp, tp, reps=3):
         per_mode.append(row)
         Y = z_best
     exh_ms, _ = timed(per_mode=choice)
-    log(f"[bench] selector on {w.name}: auto {auto_choice} {auto_ms:.2f} ms, exhaustive {choice} "
+    log(f"[bench] selector on {w.name}: auto {auto_choice} {auto_ms:.2f} ms, "
+        f"auto_tree {tree_choice} {tree_ms:.2f} ms, exhaustive {choice} "
         f"{exh_ms:.2f} ms, always-eig {eig_ms:.2f} ms, always-als {als_ms:.2f} ms")
     return {"workload": w.name, "auto_ms": auto_ms, "auto_choice": auto_choice,
             "exhaustive_ms": exh_ms, "exhaustive_choice": choice, "always_eig_ms": eig_ms,
-            "always_als_ms": als_ms, "regret": auto_ms / exh_ms - 1.0, "per_mode_steps": per_mode,
+            "always_als_ms": als_ms, "regret": auto_ms / exh_ms - 1.0,
+            "auto_tree_ms": tree_ms, "auto_tree_choice": tree_choice,
+            "auto_tree_regret": tree_ms / exh_ms - 1.0, "per_mode_steps": per_mode,
             "data": "device-drawn low-rank + 1e-4 noise (same recipe as the host generator)"}
 
 
