@@ -238,6 +238,32 @@ def sthosvd(X, ranks, order=None, methods=None, L0=None, als_iters: int = 5,
     return G, U, lam
 
 
+def hooi(X, U0, sweeps: int = 1, jacobi_tol: float = 1e-15, jacobi_max_sweeps: int = 50):
+    """Higher-order orthogonal iteration (De Lathauwer, De Moor and
+    Vandewalle, 2000), the Tucker algorithm Sec. II-B names beside st-HOSVD
+    and initializes from it.  Each sweep updates the factors in mode order:
+    the tensor is projected onto the current factors of every other mode
+    (Y = X x_m U_m^T, m != n, increasing m), and U_n becomes the R_n leading
+    eigenvectors of the mode-n Gram of Y (the left singular vectors of
+    Y_(n)), by the same cyclic Jacobi and sign rule as sthosvd.  Returns
+    (G, [U_n]) with G = X x_1 U_1^T ... x_N U_N^T."""
+    X = _f(X)
+    N = X.ndim
+    U = [_f(u).copy(order="F") for u in U0]
+    for _ in range(sweeps):
+        for n in range(N):
+            Y = X
+            for m in range(N):
+                if m != n:
+                    Y = ttm_tensor(Y, U[m].T, m)
+            lam, V, _ = jacobi_eig(gram(unfold(Y, n)), jacobi_tol, jacobi_max_sweeps)
+            U[n] = np.asfortranarray(V[:, :U[n].shape[1]])
+    G = X
+    for m in range(N):
+        G = ttm_tensor(G, U[m].T, m)
+    return G, U
+
+
 def reconstruct(G, U) -> np.ndarray:
     """Tucker model X^ = G x_1 U1 ... x_N UN (Sec. II-B)."""
     G = _f(G)
