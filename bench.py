@@ -60,6 +60,8 @@ def main():
     ap.add_argument("--batch-reps", type=int, default=5)
     ap.add_argument("--no-selector", action="store_true",
                     help="skip the learned-selector measurement (5-way 48^5 workload)")
+    ap.add_argument("--no-hooi", action="store_true",
+                    help="skip the HOOI refinement measurement (512^3, from the headline factors)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -199,6 +201,10 @@ def main():
     if args.batch > 0:
         batched = bench_batched(args, api, torch, dev, gp, tp)
 
+    hooi = None
+    if not args.no_hooi:
+        hooi = bench_hooi(api, torch, Xd, G, U, gp, tp)
+
     selector = None
     if not args.no_selector:
         selector = bench_selector(api, torch, dev, gp, tp)
@@ -243,6 +249,7 @@ def main():
         "cpu_baseline": cpu,
         "batched": batched,
         "selector": selector,
+        "hooi": hooi,
     }
     print(json.dumps(out))
 
@@ -317,6 +324,29 @@ def bench_batched(args, api, torch, dev, gp, tp):
             "tiles": {"gram_wg_per_cu": tiles[0], "gram_wt_max": tiles[1], "ttm_rows_per_wave": tiles[2]},
             "eager_default_tiles_ms": default_ms, "autotune": table}
 
+
+
+def bench_hooi(api, torch, Xd, G0, U0, gp, tp, reps=3):
+    """HOOI refinement (sth_hooi) of the headline decomposition: the time of
+    one sweep (two sweeps minus the core-only call, averaged over reps) and
+    the core-norm gain over st-HOSVD after two sweeps."""
+    def run(sweeps):
+        U = [u.clone() for u in U0]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        G, _ = api.hooi(Xd, U, sweeps, gp, tp, check_flag=False)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3, G
+    run(2)
+    t2 = min(run(2)[0] for _ in range(reps))
+    t0 = min(run(0)[0] for _ in range(reps))
+    _, G2 = run(2)
+    n0 = float(torch.linalg.vector_norm(G0.double()))
+    n2 = float(torch.linalg.vector_norm(G2.double()))
+    per = (t2 - t0) / 2
+    log(f"[bench] hooi: {per:.2f} ms per sweep, core only {t0:.2f} ms, ||G|| gain after 2 sweeps {n2 / n0 - 1:.2e}")
+    return {"ms_per_sweep": per, "core_only_ms": t0, "core_norm_gain_2_sweeps": n2 / n0 - 1.0,
+            "start": "the headline st-HOSVD factors", "recipe": {"gram": gp, "ttm": tp}}
 
 
 def bench_selector(api, torch, dev, gp, tp, reps=3):

@@ -146,6 +146,29 @@ sth_status sthosvd_run(const sth_plan *plan, const void *X, void *core, double *
                        double *const *eigvals, const double *const *als_init, uint64_t seed,
                        void *workspace, size_t workspace_bytes, sth_stream_t stream);
 
+/* Higher-order orthogonal iteration (HOOI; Sec. II-B names it beside
+ * st-HOSVD as the Tucker algorithm st-HOSVD usually initializes): sweeps
+ * times, for n = 1..N, Y = X x_m U_m^T for every m != n (increasing m) and
+ * U_n <- the R_n leading eigenvectors of the mode-n Gram of Y (the EIG
+ * solver of sthosvd_run, same routing and sign rule); then core = X x_1
+ * U_1^T ... x_N U_N^T.  order >= 2, 1 <= R_n <= I_n <= 512.  X: device,
+ * column-major, dtype (STH_F32 / STH_F64); U: host array of N device
+ * pointers to I_n x R_n FP64 factors with orthonormal columns, read as the
+ * starting point (e.g. st-HOSVD's) and overwritten; core: device R_1 x ...
+ * x R_N of dtype; sweeps >= 0 (0: the core of the given factors only);
+ * gram_prec / ttm_prec as in sthosvd_desc.  workspace: device, >=
+ * sth_hooi_workspace(...) bytes (0 for invalid arguments).  Enqueue-only;
+ * sth_hooi_check reports numerical failures.  Errors: STH_ERR_INVALID,
+ * STH_ERR_UNSUPPORTED (I_n > 512), STH_ERR_NOMEM, STH_ERR_HIP. */
+size_t sth_hooi_workspace(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype,
+                          int32_t ttm_prec);
+sth_status sth_hooi(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype,
+                    int32_t gram_prec, int32_t ttm_prec, const void *X, double *const *U, void *core,
+                    int32_t sweeps, void *workspace, size_t workspace_bytes, sth_stream_t stream);
+/* Synchronizes the stream and reports the numerical flag of the last
+ * sth_hooi on this workspace (as sthosvd_check), then clears it. */
+sth_status sth_hooi_check(void *workspace, sth_stream_t stream);
+
 /* Synchronizes the stream and reports numerical failures recorded in the
  * workspace by the last run on it (STH_ERR_NUMERIC), then clears them. */
 sth_status sthosvd_check(const sth_plan *plan, void *workspace, sth_stream_t stream);

@@ -84,6 +84,9 @@ SIGNATURES = {
     "tucker_reconstruct_workspace": (_sz, [_i32, _i64p, _i64p, _i32]),
     "tucker_reconstruct": (ctypes.c_int, [_i32, _i64p, _i64p, _i32, _i32, _vp, _vpp, _vp, _vp, _sz, _vp]),
     "tucker_error_workspace": (_sz, [_i32, _i64p, _i64p, _i32]),
+    "sth_hooi_workspace": (_sz, [_i32, _i64p, _i64p, _i32, _i32]),
+    "sth_hooi": (ctypes.c_int, [_i32, _i64p, _i64p, _i32, _i32, _i32, _vp, _vpp, _vp, _i32, _vp, _sz, _vp]),
+    "sth_hooi_check": (ctypes.c_int, [_vp, _vp]),
     "tucker_error": (ctypes.c_int, [_i32, _i64p, _i64p, _i32, _i32, _vp, _vp, _vpp, _vp, _vp, _sz, _vp]),
     "sth_sumsq": (ctypes.c_int, [_i32, _vp, _i64, _vp, _vp, _sz, _vp]),
     "sthosvd_mode_step_workspace": (_sz, [_i32, _i64p, _i32, _i64, _i32, _i32, _i32, _i32, _i32]),

@@ -306,6 +306,26 @@ def tucker_reconstruct(G: torch.Tensor, U: List[torch.Tensor], prec="fp32") -> t
     return Xh
 
 
+def hooi(X: torch.Tensor, U: List[torch.Tensor], sweeps: int = 1, gram_prec="fp64", ttm_prec="fp32",
+         check_flag: bool = True):
+    """HOOI refinement in place: U (device FP64 I_n x R_n, orthonormal
+    columns, e.g. st-HOSVD's) are updated by `sweeps` sweeps; returns the
+    core X x_1 U_1^T ... x_N U_N^T (and the workspace)."""
+    _need(X, "X")
+    L = _lib.load()
+    ranks = [int(u.shape[1]) for u in U]
+    da, ra = i64arr(X.shape), i64arr(ranks)
+    G = fortran_empty(ranks, X.dtype, X.device)
+    ws = _ws(L.sth_hooi_workspace(X.dim(), da, ra, _dtype_code(X), _prec(ttm_prec)), X.device)
+    check(L.sth_hooi(X.dim(), da, ra, _dtype_code(X), _prec(gram_prec), _prec(ttm_prec),
+                     ctypes.c_void_p(X.data_ptr()), ptrarr([u.data_ptr() for u in U]),
+                     ctypes.c_void_p(G.data_ptr()), sweeps, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                     _stream()))
+    if check_flag:
+        check(L.sth_hooi_check(ctypes.c_void_p(ws.data_ptr()), _stream()))
+    return G, ws
+
+
 def tucker_error(X: torch.Tensor, G: torch.Tensor, U: List[torch.Tensor], prec="fp32"):
     """(||X - X^||^2, ||X||^2) accumulated in FP64 on the device."""
     _need(X, "X")

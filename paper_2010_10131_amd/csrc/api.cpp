@@ -558,6 +558,138 @@ extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double 
     return STH_OK;
 }
 
+// --------------------------------------------------------------- HOOI ----
+// Higher-order orthogonal iteration, the Tucker algorithm Sec. II-B names
+// beside st-HOSVD and seeds from it: per sweep and mode n, Y = X x_m U_m^T
+// for every m != n (increasing m), U_n = the R_n leading eigenvectors of the
+// mode-n Gram of Y; finally G = X x_1 U_1^T ... x_N U_N^T.  The same Gram,
+// eigensolver and TTM launches as the decomposition, on caller buffers.
+
+namespace {
+struct HooiWs {
+    size_t flag, bufA, bufB, part, S, eig, uq, total;
+};
+
+HooiWs hooi_layout(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype, int tp) {
+    size_t maxY = 0, maxPart = 0, maxS = 0, maxEig = 0, maxUq = 0;
+    for (int n = 0; n <= order; ++n) {   // n = order: the core chain
+        std::vector<int64_t> cur(dims, dims + order);
+        for (int m = 0; m < order; ++m) {
+            if (m == n) continue;
+            cur[m] = ranks[m];
+            size_t e = 1;
+            for (int k = 0; k < order; ++k) e *= (size_t)cur[k];
+            maxY = std::max(maxY, e);
+            maxUq = std::max(maxUq, ttm_prep_bytes(dims[m], ranks[m], tp));
+        }
+        if (n < order) {
+            int64_t L, I, M;
+            lim(order, cur.data(), n, L, I, M);
+            maxPart = std::max(maxPart, gram_ws_bytes(I, I, L * M, true));
+            maxS = std::max(maxS, (size_t)(I * I) * sizeof(double));
+            maxEig = std::max(maxEig, eig_ws_bytes(I));
+        }
+    }
+    HooiWs w;
+    Arena a;
+    w.flag = a.take(256);
+    w.bufA = a.take(maxY * esize(dtype));
+    w.bufB = a.take(maxY * esize(dtype));
+    w.part = a.take(maxPart);
+    w.S = a.take(maxS);
+    w.eig = a.take(maxEig);
+    w.uq = a.take(maxUq);
+    w.total = a.off;
+    return w;
+}
+
+sth_status flag_check(int64_t *dflag, hipStream_t s) {
+    int64_t flag = 0;
+    HIPCHK(hipStreamSynchronize(s), "sync");
+    HIPCHK(hipMemcpy(&flag, dflag, sizeof(flag), hipMemcpyDeviceToHost), "flag read");
+    int64_t zero = 0;
+    HIPCHK(hipMemcpy(dflag, &zero, sizeof(zero), hipMemcpyHostToDevice), "flag clear");
+    if (flag == 1) return fail(STH_ERR_NUMERIC, "eigensolver hit its sweep cap");
+    if (flag == 2) return fail(STH_ERR_NUMERIC, "Cholesky met a non-positive pivot");
+    if (flag == 3) return fail(STH_ERR_NUMERIC, "NaN or Inf met");
+    if (flag) return fail(STH_ERR_NUMERIC, "numeric flag %lld", (long long)flag);
+    return STH_OK;
+}
+}  // namespace
+
+extern "C" size_t sth_hooi_workspace(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype,
+                                     int32_t ttm_prec) {
+    if (check_shape(order, dims) || !ranks) return 0;
+    for (int k = 0; k < order; ++k)
+        if (ranks[k] < 1 || ranks[k] > dims[k]) return 0;
+    return hooi_layout(order, dims, ranks, dtype, ttm_prec).total;
+}
+
+extern "C" sth_status sth_hooi(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype,
+                               int32_t gram_prec, int32_t ttm_prec, const void *X, double *const *U,
+                               void *core, int32_t sweeps, void *ws, size_t ws_bytes, sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (order < 2) return fail(STH_ERR_INVALID, "HOOI needs order >= 2");
+    if (!ranks || !U) return fail(STH_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < order; ++k) {
+        if (ranks[k] < 1 || ranks[k] > dims[k]) return fail(STH_ERR_INVALID, "ranks[%d] out of range", k);
+        if (dims[k] > MAX_EIG_N)
+            return fail(STH_ERR_UNSUPPORTED, "I_%d = %lld exceeds the eigensolver limit %lld", k, (long long)dims[k], (long long)MAX_EIG_N);
+        if ((st = check_ptr(U[k], "U[n]"))) return st;
+    }
+    if (sweeps < 0) return fail(STH_ERR_INVALID, "sweeps = %d < 0", sweeps);
+    if ((st = check_dtype_prec(dtype, gram_prec, "gram_prec"))) return st;
+    if ((st = check_dtype_prec(dtype, ttm_prec, "ttm_prec"))) return st;
+    if ((st = check_ptr(X, "X")) || (st = check_ptr(core, "core")) || (st = check_ptr(ws, "ws"))) return st;
+    const HooiWs L = hooi_layout(order, dims, ranks, dtype, ttm_prec);
+    if (ws_bytes < L.total) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    int64_t *flag = (int64_t *)(w + L.flag);
+    void *uq = w + L.uq;
+    HIPCHK(zero_words(flag, 2, s), "flag clear");
+    const int64_t si_min = dtype == STH_F64 ? EIG_LDS_DIRECT_MAX_HOST : EIG_SI_MIN_HOST;
+    // X x_m U_m^T for every m != skip, increasing m; the last product goes to
+    // last_dst (or a buffer); returns the result and its dims in cur
+    auto chain = [&](int skip, void *last_dst, std::vector<int64_t> &cur, const void *&res) -> sth_status {
+        cur.assign(dims, dims + order);
+        const void *src = X;
+        int k = 0, nprod = order - (skip < order ? 1 : 0);
+        for (int m = 0; m < order; ++m) {
+            if (m == skip) continue;
+            int64_t Lm, Im, Mm;
+            lim(order, cur.data(), m, Lm, Im, Mm);
+            void *dst = (k == nprod - 1 && last_dst) ? last_dst : (void *)(w + (k % 2 == 0 ? L.bufA : L.bufB));
+            HIPCHK(ttm_prep_u(U[m], dims[m], ranks[m], 0, ttm_prec, uq, s), "hooi prep");
+            HIPCHK(ttm_launch(dtype, ttm_prec, src, uq, dst, Lm, Im, ranks[m], Mm, s), "hooi ttm");
+            cur[m] = ranks[m];
+            src = dst;
+            ++k;
+        }
+        res = src;
+        return STH_OK;
+    };
+    std::vector<int64_t> cur;
+    const void *Y = nullptr;
+    for (int sw = 0; sw < sweeps; ++sw)
+        for (int n = 0; n < order; ++n) {
+            if ((st = chain(n, nullptr, cur, Y))) return st;
+            int64_t Ln, In, Mn;
+            lim(order, cur.data(), n, Ln, In, Mn);
+            double *S = (double *)(w + L.S);
+            HIPCHK(gram_launch(dtype, gram_prec, Y, Y, Ln, In, In, Mn, true, (double *)(w + L.part), S, s), "hooi gram");
+            HIPCHK(eig_launch(In, ranks[n], S, U[n], nullptr, 1e-15, 60, w + L.eig, flag, s, Ln * Mn, si_min),
+                   "hooi eig");
+        }
+    return chain(order, core, cur, Y);
+}
+
+extern "C" sth_status sth_hooi_check(void *ws, sth_stream_t stream) {
+    if (!ws) return fail(STH_ERR_INVALID, "NULL argument");
+    return flag_check((int64_t *)ws, (hipStream_t)stream);
+}
+
 // -------------------------------------------------------- reconstruct ----
 
 static void recon_sizes(int32_t order, const int64_t *dims, const int64_t *ranks, size_t &maxA, size_t &maxB) {

@@ -184,3 +184,22 @@ def test_batched_plan_rejects_rank_above_the_gram_rank_bound():
         api.BatchPlan([((33, 20, 150), (5, 3, 24))])
     assert e.value.status == STH_ERR_UNSUPPORTED
     assert api.BatchPlan([((33, 20, 150), (5, 4, 18))]).workspace_bytes > 0
+
+
+def test_hooi_rejects_bad_arguments_before_launch(lib):
+    from paper_2010_10131_amd import _lib
+    vp = ctypes.c_void_p
+    dims, ranks = _lib.i64arr([8, 8, 8]), _lib.i64arr([2, 3, 2])
+    U = _lib.ptrarr([0x1000, 0x2000, 0x3000])
+    need = lib.sth_hooi_workspace(3, dims, ranks, 1, 1)
+    assert need > 0
+    assert lib.sth_hooi_workspace(3, dims, _lib.i64arr([9, 2, 2]), 1, 1) == 0
+    args = (vp(0x4000), U, vp(0x5000))
+    assert lib.sth_hooi(3, _lib.i64arr([8, 600, 8]), ranks, 1, 1, 1, *args, 1, vp(0x6000), 1 << 40,
+                        None) == _lib.STH_ERR_UNSUPPORTED
+    assert lib.sth_hooi(3, dims, ranks, 1, 1, 1, *args, 1, vp(0x6000), need - 1, None) == _lib.STH_ERR_NOMEM
+    assert lib.sth_hooi(3, dims, ranks, 1, 1, 1, *args, -1, vp(0x6000), need, None) == _lib.STH_ERR_INVALID
+    assert lib.sth_hooi(1, dims, ranks, 1, 1, 1, *args, 1, vp(0x6000), need, None) == _lib.STH_ERR_INVALID
+    assert lib.sth_hooi(3, dims, ranks, 0, 1, 1, *args, 1, vp(0x6000), need, None) == _lib.STH_ERR_INVALID
+    assert lib.sth_hooi(3, dims, ranks, 1, 1, 1, vp(0x4000), None, vp(0x5000), 1, vp(0x6000), need,
+                        None) == _lib.STH_ERR_INVALID
