@@ -365,6 +365,25 @@ def test_als_fp64_matches_oracle(api, variant_dims, ranks, per_mode):
         np.testing.assert_allclose(Un[n] @ Un[n].T, Uo[n] @ Uo[n].T, atol=1e-9)
 
 
+def test_large_first_mode_takes_als_and_matches_oracle(api):
+    """An Air-Quality-like first mode (I_1 = 30648, beyond the eigensolver's
+    512): the plan takes ALS there under either selector and EIG for the
+    small modes; FP32 data, FP64 products, same initial guess as the oracle."""
+    import torch
+    dims, ranks = (30648, 12, 10), (6, 5, 4)
+    for solver in ("auto", "auto_tree"):
+        p = api.Plan(dims, ranks, torch.float32, "fp64", "fp32", solver)
+        assert p.solvers[0] == 1
+    X = wl.lowrank_plus_noise(dims, ranks, "none", 1e-4, 41, "float32")
+    L0 = [wl.gaussian_init(d, r, 9, n) for n, (d, r) in enumerate(zip(dims, ranks))]
+    per_mode = ("als", "eig", "eig")
+    G, U, _ = api.sthosvd(api.to_device(X), ranks, "fp64", "fp32", per_mode=per_mode, als_init=L0)
+    Go, Uo, _ = oracle.sthosvd(X, ranks, methods=[1, 0, 0], L0=L0, als_variant=1)
+    t1, t2, _, Un = t1_t2(api, X, G, U, Go, Uo)
+    assert t1 <= 1e-5 and t2 <= 1e-5, (t1, t2)
+    np.testing.assert_allclose(Un[0].T @ Un[0], np.eye(ranks[0]), atol=1e-10)
+
+
 def test_als_device_initial_guess_runs(api):
     X = wl.lowrank_plus_noise((30, 20, 10), (3, 3, 3), "none", 0.0, 3, "float64")
     G, U, _ = api.sthosvd(api.to_device(X), (3, 3, 3), "fp64", "fp64", solver="als", seed=5)
