@@ -256,6 +256,22 @@ sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, int64_t R, 
                       int32_t prec, const void *Y, const double *U, int32_t transpose_u, void *Z,
                       void *ws, size_t ws_bytes, sth_stream_t stream);
 
+/* ttm_mode_n for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same bits as ttm_mode_n, with the pre-split factor kept in
+ * a scratch array inside the library instead of a caller workspace.  The
+ * library allocates nothing here; each device it runs on holds one array of
+ * ttm_mode_n_noalloc_max_bytes() bytes (4 MiB) until the process ends.  A
+ * factor whose split needs more (ttm_factor_bytes(I_n, R, prec)) is
+ * STH_ERR_NOMEM with nothing launched.  All calls on one device share that
+ * array: calls that can overlap on one device (several streams or host
+ * threads) race and must be serialized by the caller.  Other arguments and
+ * errors as in ttm_mode_n. */
+size_t ttm_mode_n_noalloc_max_bytes(void);
+sth_status ttm_mode_n_noalloc(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                              int32_t dtype, int32_t prec, const void *Y, const double *U,
+                              int32_t transpose_u, void *Z, sth_stream_t stream);
+
 /* Device bytes of a prepared (pre-split) I_n x R factor for precision prec. */
 size_t ttm_factor_bytes(int64_t I, int64_t R, int32_t prec);
 

@@ -76,6 +76,8 @@ SIGNATURES = {
     "ttt_mode_n": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _vp, _vp, _sz, _vp]),
     "ttm_mode_n_workspace": (_sz, [_i64, _i64]),
     "ttm_mode_n": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _sz, _vp]),
+    "ttm_mode_n_noalloc_max_bytes": (_sz, []),
+    "ttm_mode_n_noalloc": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _i32, _vp, _vp]),
     "ttm_factor_bytes": (_sz, [_i64, _i64, _i32]),
     "ttm_factor_prepare": (ctypes.c_int, [_i64, _i64, _i32, _vp, _i32, _vp, _sz, _vp]),
     "ttm_mode_n_prepared": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]),

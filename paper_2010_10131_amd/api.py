@@ -18,7 +18,7 @@ from ._lib import PREC, SOLVER, check, i32arr, i64arr, ptrarr
 
 __all__ = [
     "fortran_empty", "to_device", "to_numpy", "Plan", "sthosvd", "gram_mode_n", "ttt_mode_n",
-    "ttm_mode_n", "ttm_factor_prepare", "ttm_mode_n_prepared", "eig_leading", "tucker_reconstruct", "tucker_error", "sumsq", "mode_step",
+    "ttm_mode_n", "ttm_mode_n_noalloc", "ttm_factor_prepare", "ttm_mode_n_prepared", "eig_leading", "tucker_reconstruct", "tucker_error", "sumsq", "mode_step",
     "selector_features", "selector_predict", "mlp_forward", "mlp_loss_grad", "mlp_adam",
     "BatchPlan",
 ]
@@ -239,6 +239,32 @@ def ttm_mode_n(Y: torch.Tensor, U: torch.Tensor, n: int, prec="fp32",
                        ctypes.c_void_p(U.data_ptr()), 1 if transpose_u else 0,
                        ctypes.c_void_p(Z.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                        _stream()))
+    return Z
+
+
+def ttm_mode_n_noalloc(Y: torch.Tensor, U: torch.Tensor, n: int, prec="fp32",
+                       transpose_u: bool = False, out: torch.Tensor = None) -> torch.Tensor:
+    """ttm_mode_n without a workspace: the library keeps the pre-split factor in
+    its own per-device scratch.  `out` (column-major, the dims of Y with
+    dims[n] = R) is written when given, so a caller can allocate nothing."""
+    _need(Y, "Y")
+    _need(U, "U")
+    if U.dtype != torch.float64:
+        raise TypeError("factors are FP64")
+    In = Y.shape[n]
+    R, k = U.shape if transpose_u else U.shape[::-1]
+    if k != In:
+        raise ValueError("factor does not match mode n")
+    L = _lib.load()
+    oshape = list(Y.shape)
+    oshape[n] = R
+    Z = out if out is not None else fortran_empty(oshape, Y.dtype, Y.device)
+    if list(Z.shape) != oshape or Z.dtype != Y.dtype:
+        raise ValueError("out has the wrong shape or dtype")
+    _need(Z, "out")
+    check(L.ttm_mode_n_noalloc(Y.dim(), i64arr(Y.shape), n, R, _dtype_code(Y), _prec(prec),
+                               ctypes.c_void_p(Y.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                               1 if transpose_u else 0, ctypes.c_void_p(Z.data_ptr()), _stream()))
     return Z
 
 

@@ -508,6 +508,31 @@ extern "C" sth_status ttm_mode_n(int32_t order, const int64_t *dims, int32_t n, 
     return STH_OK;
 }
 
+extern "C" size_t ttm_mode_n_noalloc_max_bytes(void) { return ttm_scratch_bytes(); }
+
+extern "C" sth_status ttm_mode_n_noalloc(int32_t order, const int64_t *dims, int32_t n, int64_t R,
+                                         int32_t dtype, int32_t prec, const void *Y, const double *U,
+                                         int32_t transpose_u, void *Z, sth_stream_t stream) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (n < 0 || n >= order) return fail(STH_ERR_INVALID, "mode %d outside 0..%d", n, order - 1);
+    if (R < 1) return fail(STH_ERR_INVALID, "R < 1");
+    if ((st = check_dtype_prec(dtype, prec, "prec"))) return st;
+    if ((st = check_ptr(Y, "Y")) || (st = check_ptr(U, "U")) || (st = check_ptr(Z, "Z"))) return st;
+    int64_t L, I, M;
+    lim(order, dims, n, L, I, M);
+    const size_t need = ttm_prep_bytes(I, R, prec);
+    if (need > ttm_scratch_bytes())
+        return fail(STH_ERR_NOMEM, "the pre-split %lld x %lld factor needs %zu bytes, above the library scratch of %zu bytes (use ttm_mode_n)",
+                    (long long)I, (long long)R, need, ttm_scratch_bytes());
+    void *scr = nullptr;
+    HIPCHK(ttm_scratch_ptr(&scr), "scratch address");
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(ttm_prep_u(U, I, R, transpose_u ? 1 : 0, prec, scr, s), "ttm prep");
+    HIPCHK(ttm_launch(dtype, prec, Y, scr, Z, L, I, R, M, s), "ttm");
+    return STH_OK;
+}
+
 extern "C" size_t ttm_factor_bytes(int64_t I, int64_t R, int32_t prec) {
     if (I < 1 || R < 1 || prec < STH_PREC_FP64 || prec > STH_PREC_BF16X6) return 0;
     return ttm_prep_bytes(I, R, prec);

@@ -23,6 +23,10 @@ hipError_t ttm_prep_u(const double *U, int64_t K, int64_t Rout, int transpose, i
                       hipStream_t s);
 hipError_t ttm_launch(int dtype, int prec, const void *Y, const void *Uq, void *Z, int64_t L,
                       int64_t K, int64_t Rout, int64_t M, hipStream_t s);
+// the library-held scratch of ttm_mode_n_noalloc (its size, and its address on
+// the current device)
+size_t ttm_scratch_bytes();
+hipError_t ttm_scratch_ptr(void **out);
 
 // Gram / TTT (gram.hip)
 size_t gram_ws_bytes(int64_t IA, int64_t IB, int64_t P, bool sym);

@@ -29,6 +29,8 @@
 #include "internal.h"
 #include "ttm_body.h"
 
+#include <mutex>
+
 namespace sth {
 
 // V (K x Rout) -> quads [c][rt][q][lane] (16 bytes each), zero padded.
@@ -78,12 +80,45 @@ __global__ __launch_bounds__(64 * KS_WAVES) void ttm_ks_kernel(
                                             gridDim.x, blockIdx.y);
 }
 
+// Scratch for callers that cannot allocate (ttm_mode_n_noalloc): the
+// pre-split factor of one call lives here instead of in a caller workspace.
+// Each device that runs the library holds its own copy until the process
+// ends.  Host code must never pass `scratch` itself to a kernel (on the host
+// it names a stand-in, not a device address); it uses the address that
+// ttm_scratch_ptr() looked up for the current device.
+constexpr size_t TTM_SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) unsigned char scratch[TTM_SCRATCH_BYTES];
+
 // ---------------------------------------------------------------- host ----
 
 size_t ttm_prep_bytes(int64_t K, int64_t Rout, int prec) {
     int64_t nchunks = (K + KC - 1) / KC;
     int64_t ntiles = (Rout + 15) / 16;
     return (size_t)(nchunks * ntiles * 64 * 16 * prec_nq(prec));
+}
+
+size_t ttm_scratch_bytes() { return TTM_SCRATCH_BYTES; }
+
+// Device address of `scratch` on the current device, looked up once per
+// device with that device current and kept for later calls.
+hipError_t ttm_scratch_ptr(void **out) {
+    static std::mutex mu;
+    static void *addr[64] = {nullptr};
+    *out = nullptr;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *out = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t ttm_prep_u(const double *U, int64_t K, int64_t Rout, int transpose, int prec,

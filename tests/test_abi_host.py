@@ -141,6 +141,16 @@ def test_entry_points_reject_bad_arguments_before_launch(lib):
     st = lib.ttm_mode_n_prepared(3, dims, 1, 8, 0, 2, ctypes.c_void_p(0x1000),
                                  ctypes.c_void_p(0x2000), 1 << 20, ctypes.c_void_p(0x3000), None)
     assert st == _lib.STH_ERR_INVALID      # FP64 data needs FP64 products
+    # the entry point that allocates nothing: a factor whose split exceeds the
+    # library scratch is refused before any device call
+    assert lib.ttm_mode_n_noalloc_max_bytes() == 4 << 20
+    big = _lib.i64arr([2, 4096])
+    st = lib.ttm_mode_n_noalloc(2, big, 1, 512, 0, 0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), 0,
+                                ctypes.c_void_p(0x3000), None)
+    assert st == _lib.STH_ERR_NOMEM and b"scratch" in lib.sth_last_error()
+    st = lib.ttm_mode_n_noalloc(3, dims, 1, 4, 1, 2, ctypes.c_void_p(0x1008), ctypes.c_void_p(0x2000), 0,
+                                ctypes.c_void_p(0x3000), None)
+    assert st == _lib.STH_ERR_LAYOUT
 
 
 def test_batched_plan_validation():
