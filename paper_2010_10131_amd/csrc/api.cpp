@@ -68,15 +68,6 @@ int device_cu_count() {
 
 static const int MAX_ORDER = 8;
 static const int64_t MAX_EIG_N = SEL_MAX_EIG_N;   // I_n x I_n Gram and eigensolver
-static const int64_t EIG_DIRECT_MAX_HOST = 128;
-static const int64_t EIG_LDS_DIRECT_MAX_HOST = 96;   // Jacobi with A and V in LDS
-static const int64_t EIG_SI_MIN_HOST = 48;   // FP32 data: subspace iteration above, block <= I / 2
-static const int64_t SI_BLOCK_MAX_HOST = 96;
-static int64_t si_block_host_api(int64_t n, int64_t R) {
-    int64_t p = R + 16;   // the same rule as the device side
-    p = (p + 7) / 8 * 8;
-    return std::min(p, n);
-}
 static const int64_t MAX_ALS_R = SEL_MAX_ALS_R;   // R x R Cholesky in LDS
 
 static size_t esize(int dtype) { return dtype == STH_F64 ? 8 : 4; }
@@ -352,9 +343,7 @@ static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *s
     if (stp.solver == STH_SOLVER_EIG) {
         // Alg. 2 lines 6-8
         HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
-        // FP64 data keeps the exact Jacobi up to the LDS limit (order 96)
-        const int64_t si_min = p->dtype == STH_F64 ? EIG_LDS_DIRECT_MAX_HOST : EIG_SI_MIN_HOST;
-        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M, si_min),
+        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M, false),
                "eig");
         HIPCHK(ttm_prep_u(Un, stp.I, stp.R, 0, tp, uq, s), "ttm prep");
         HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
@@ -578,8 +567,9 @@ extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double 
     sth_status st;
     if ((st = check_ptr(S, "S")) || (st = check_ptr(U, "U")) || (st = check_ptr(lam, "lam", true)) || (st = check_ptr(ws, "ws"))) return st;
     if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
+    HIPCHK(zero_words(ws, 2, (hipStream_t)stream), "flag clear");
     HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (int64_t *)ws,
-                      (hipStream_t)stream, n, EIG_DIRECT_MAX_HOST), "eig");
+                      (hipStream_t)stream, n, true), "eig");
     return STH_OK;
 }
 
@@ -674,7 +664,6 @@ extern "C" sth_status sth_hooi(int32_t order, const int64_t *dims, const int64_t
     int64_t *flag = (int64_t *)(w + L.flag);
     void *uq = w + L.uq;
     HIPCHK(zero_words(flag, 2, s), "flag clear");
-    const int64_t si_min = dtype == STH_F64 ? EIG_LDS_DIRECT_MAX_HOST : EIG_SI_MIN_HOST;
     // X x_m U_m^T for every m != skip, increasing m; the last product goes to
     // last_dst (or a buffer); returns the result and its dims in cur
     auto chain = [&](int skip, void *last_dst, std::vector<int64_t> &cur, const void *&res) -> sth_status {
@@ -704,7 +693,7 @@ extern "C" sth_status sth_hooi(int32_t order, const int64_t *dims, const int64_t
             lim(order, cur.data(), n, Ln, In, Mn);
             double *S = (double *)(w + L.S);
             HIPCHK(gram_launch(dtype, gram_prec, Y, Y, Ln, In, In, Mn, true, (double *)(w + L.part), S, s), "hooi gram");
-            HIPCHK(eig_launch(In, ranks[n], S, U[n], nullptr, 1e-15, 60, w + L.eig, flag, s, Ln * Mn, si_min),
+            HIPCHK(eig_launch(In, ranks[n], S, U[n], nullptr, 1e-15, 60, w + L.eig, flag, s, Ln * Mn, false),
                    "hooi eig");
         }
     return chain(order, core, cur, Y);
@@ -1053,29 +1042,10 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             maxPart = std::max(maxPart, (size_t)nkc * nblocks * (32 * wt) * (32 * wt) * 8);
             maxS = std::max(maxS, (size_t)(b.I * b.I) * 8);
             maxUq = std::max(maxUq, ttm_prep_bytes(b.I, b.R, d0.ttm_prec));
-            if (b.I > EIG_DIRECT_MAX_HOST && si_block_host_api(b.I, b.R) > SI_BLOCK_MAX_HOST)
-                return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n = %lld too large for the batched eigensolver", t, s, (long long)b.R);
-            if (b.R > 64) return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n > 64 in the batched path", t, s);
-            b.sib = 0;
-            const int64_t pb = si_block_host_api(b.I, b.R);
-            if (b.I > EIG_SI_MIN_HOST && b.I <= EIG_LDS_DIRECT_MAX_HOST && 2 * pb <= b.I && b.R <= P) {
-                // orders 49..96: the subspace iteration when its block is at
-                // most half the order (the rule of the single-tensor path)
-                b.sib = (int32_t)std::min<int64_t>(pb, P);
-            } else if (b.I > EIG_LDS_DIRECT_MAX_HOST && b.I <= EIG_DIRECT_MAX_HOST && pb <= SI_BLOCK_MAX_HOST &&
-                pb < b.I && b.R <= P) {
-                // orders 97..128: the subspace iteration when its block fits
-                // (the Jacobi would keep V in the workspace there)
-                b.sib = (int32_t)std::min<int64_t>(pb, P);
-            } else if (b.I > EIG_DIRECT_MAX_HOST) {
-                // the Gram of this step has rank <= L * M: the subspace block
-                // is capped there, and more vectors than that need the direct
-                // solver, which the batched eigen kernel has only for I <= 128
-                if (b.R > P)
-                    return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n = %lld exceeds the rank bound %lld of the mode-%d Gram (I_n > 128; use single runs)", t, s, (long long)b.R, (long long)P, s + 1);
-                b.sib = (int32_t)std::min<int64_t>(si_block_host_api(b.I, b.R), P);
-            }
-            maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.sib));
+            if (b.I > MAX_EIG_N)
+                return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: I_n = %lld exceeds the eigensolver limit %lld", t, s, (long long)b.I, (long long)MAX_EIG_N);
+            b.sib = 0;   // the direct solver for every order
+            maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.R));
             b.nchunks = (int)((b.I + 31) / 32);
             b.ntiles = (int)((b.R + 15) / 16);
             b.rtb = b.ntiles <= 1 ? 1 : (b.ntiles <= 2 ? 2 : 4);
@@ -1108,7 +1078,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
         T.eig_lds = 0;
         T.max_nchunks = 0;
         for (int t = 0; t < count; ++t) {
-            T.eig_lds = std::max(T.eig_lds, batch_eig_lds(sd[s][t].I, sd[s][t].sib));
+            T.eig_lds = std::max(T.eig_lds, batch_eig_lds(sd[s][t].I, sd[s][t].R));
             T.max_nchunks = std::max(T.max_nchunks, sd[s][t].nchunks);
         }
         auto make = [&](const std::vector<int32_t> &list, const std::vector<int64_t> &units, int cls) {

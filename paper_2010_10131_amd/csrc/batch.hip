@@ -3,29 +3,26 @@
 //   grouped Gram      every (tensor, row range, output block) workgroup of
 //                     one tile class in one grid, XCD-aware ids;
 //   grouped reduce    the FP64 partial blocks of every tensor;
-//   batched eigen     one workgroup per tensor: cyclic Jacobi (n <= 128) or
-//                     subspace iteration + Rayleigh-Ritz (n > 128), all in the
-//                     workgroup (small FP64 GEMMs, Cholesky-QR, Jacobi);
+//   batched eigen     one workgroup per tensor: the direct solver of
+//                     teig_body.h (tridiagonalization, bisection, inverse
+//                     iteration), the matrix in LDS up to order 128;
 //   grouped split     every factor into matrix-core quads;
 //   grouped TTM       workgroups assigned to tensors in proportion to rows.
 // Shapes, workspace offsets and launch prefix sums are fixed at plan time
 // and copied into the workspace at the start of a run; the caller's tensors
 // are reached through device arrays of pointers.  The run is enqueue-only
 // and graph-capturable.
-#include "chol_body.h"
 #include "common.h"
-#include "eig_body.h"
 #include "gram_body.h"
 #include "internal.h"
+#include "teig_body.h"
 #include "ttm_body.h"
 
 namespace sth {
 
-constexpr int BE_THREADS = 512;  // batched eigen workgroup (matches the Jacobi body)
-// Dynamic LDS for Jacobi's A and V in the batched eigen kernel: the kernel's
-// static LDS (Jacobi, Cholesky and selection arrays, about 11.3 KiB) must fit
-// beside it in the 160 KiB of a workgroup; batch_step_launch checks the sum.
-constexpr int BATCH_LDS_AV = 148 * 1024;
+constexpr int BE_THREADS = TE_T;  // batched eigen workgroup (the direct solver's)
+// the eigen kernel's dynamic and static LDS must fit the 160 KiB of a
+// workgroup; batch_step_launch checks the sum
 constexpr size_t WG_LDS_MAX = 160 * 1024;
 
 __device__ __forceinline__ int find_segment(const int64_t *__restrict__ pref, int len, int64_t x) {
@@ -104,125 +101,23 @@ __global__ void batch_reduce_kernel(const BatchStep *__restrict__ descs,
 
 // C (m x n, ldc) = op(A) op(B) by one workgroup, 32 x 32 output tiles with
 // 32-deep LDS slabs (tile storage in the dynamic LDS).
-__device__ void wg_gemm(int ta, int tb, int m, int n, int k, const double *__restrict__ A,
-                        int64_t lda, const double *__restrict__ B, int64_t ldb,
-                        double *__restrict__ C, int64_t ldc) {
-    extern __shared__ __align__(16) double s_dyn[];
-    double *sA = s_dyn;             // [kk][33]
-    double *sB = s_dyn + 32 * 33;   // [kk][33]
-    const int tid = threadIdx.x;
-    const int tx = tid % 32, ty = tid / 32;  // 512 threads: ty in 0..15, two columns each
-    for (int r0 = 0; r0 < m; r0 += 32)
-        for (int c0 = 0; c0 < n; c0 += 32) {
-            double acc0 = 0.0, acc1 = 0.0;
-            for (int kc = 0; kc < k; kc += 32) {
-                __syncthreads();
-                for (int e = tid; e < 32 * 32; e += BE_THREADS) {
-                    const int a = e % 32, b = e / 32;
-                    {
-                        int r, kk;
-                        if (ta) { kk = a; r = b; } else { r = a; kk = b; }
-                        const int gr = r0 + r, gk = kc + kk;
-                        double v = 0.0;
-                        if (gr < m && gk < k) v = ta ? A[gk + lda * gr] : A[gr + lda * gk];
-                        sA[kk * 33 + r] = v;
-                    }
-                    {
-                        int cc, kk;
-                        if (tb) { cc = a; kk = b; } else { kk = a; cc = b; }
-                        const int gc = c0 + cc, gk = kc + kk;
-                        double v = 0.0;
-                        if (gc < n && gk < k) v = tb ? B[gc + ldb * gk] : B[gk + ldb * gc];
-                        sB[kk * 33 + cc] = v;
-                    }
-                }
-                __syncthreads();
-#pragma unroll 8
-                for (int kk = 0; kk < 32; ++kk) {
-                    const double a = sA[kk * 33 + tx];
-                    acc0 += a * sB[kk * 33 + ty];
-                    acc1 += a * sB[kk * 33 + ty + 16];
-                }
-            }
-            const int r = r0 + tx;
-            if (r < m) {
-                if (c0 + ty < n) C[r + ldc * (c0 + ty)] = acc0;
-                if (c0 + ty + 16 < n) C[r + ldc * (c0 + ty + 16)] = acc1;
-            }
-        }
-    __syncthreads();
-}
-
-// Cholesky-QR pass of the n x p matrix A into Q (one workgroup).
-__device__ void wg_cholqr(const double *A, double *Q, int n, int p, double shift_rel, double *G,
-                          double *Rinv, int64_t *flag) {
-    wg_gemm(1, 0, p, p, n, A, n, A, n, G, p);
-    chol_body<BE_THREADS>(G, p, p, shift_rel, nullptr, Rinv, flag);
-    __syncthreads();
-    wg_gemm(0, 0, n, p, p, A, n, Rinv, p, Q, n);
-}
-
-__device__ void wg_orth(double *A, double *Q, double *Z2, int n, int p, int passes, double *G,
-                        double *Rinv, int64_t *flag) {
-    const double shift = 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16;
-    wg_cholqr(A, Z2, n, p, shift * p, G, Rinv, flag);
-    if (passes == 2) {
-        wg_cholqr(Z2, Q, n, p, 0.0, G, Rinv, flag);
-        return;
-    }
-    wg_cholqr(Z2, A, n, p, 0.0, G, Rinv, flag);
-    wg_cholqr(A, Q, n, p, 0.0, G, Rinv, flag);
-}
-
 __global__ __launch_bounds__(BE_THREADS) void batch_eig_kernel(const BatchStep *__restrict__ descs,
                                                                char *__restrict__ ws,
                                                                double *const *__restrict__ Up,
                                                                int order, int mode,
-                                                               int64_t *__restrict__ flag,
-                                                               double tol, int max_sweeps) {
+                                                               int64_t *__restrict__ flag) {
     const BatchStep &d = descs[blockIdx.x];
     const int n = (int)d.I, R = (int)d.R;
     const double *S = (const double *)(ws + d.S_off);
     double *U = Up[(int64_t)d.tensor * order + mode];
-    double *scr = (double *)(ws + d.eig_off);
-    if (d.sib == 0) {   // direct Jacobi
-        if (jacobi_small_lds(n, true) <= (size_t)BATCH_LDS_AV)
-            jacobi_small_body<true>(S, n, R, scr, U, nullptr, tol, max_sweeps, flag);
-        else
-            jacobi_small_body<false>(S, n, R, scr, U, nullptr, tol, max_sweeps, flag);
-        return;
-    }
-    const int p = d.sib;
-    double *Q = scr, *Z = Q + (int64_t)n * p, *Z2 = Z + (int64_t)n * p, *G = Z2 + (int64_t)n * p;
-    double *Rinv = G + p * p, *T = Rinv + p * p, *W = T + p * p, *jac = W + p * p;
-    for (int e = threadIdx.x; e < n * p; e += BE_THREADS)
-        Q[e] = gaussian_value(0x5EED5EEDull, (uint64_t)n * 1000 + p, (uint64_t)e);
-    __syncthreads();
-    for (int it = 0; it < SI_ITERS_DEV; ++it) {
-        wg_gemm(0, 0, n, p, n, S, n, Q, n, Z, n);
-        wg_orth(Z, Q, Z2, n, p, it + 1 == SI_ITERS_DEV ? 3 : 2, G, Rinv, flag);
-    }
-    wg_gemm(0, 0, n, p, n, S, n, Q, n, Z, n);
-    wg_gemm(1, 0, p, p, n, Q, n, Z, n, T, p);
-    if (jacobi_small_lds(p, true) <= (size_t)BATCH_LDS_AV)
-        jacobi_small_body<true>(T, p, R, jac, W, nullptr, tol, max_sweeps, flag);
-    else
-        jacobi_small_body<false>(T, p, R, jac, W, nullptr, tol, max_sweeps, flag);
-    __syncthreads();
-    wg_gemm(0, 0, n, R, p, Q, n, W, p, U, n);
-    // sign rule on the columns of U
-    for (int r = threadIdx.x; r < R; r += BE_THREADS) {
-        int arg = 0;
-        double best = fabs(U[(int64_t)n * r]);
-        for (int i = 1; i < n; ++i) {
-            const double v = fabs(U[i + (int64_t)n * r]);
-            if (v > best) {
-                best = v;
-                arg = i;
-            }
-        }
-        if (U[arg + (int64_t)n * r] < 0.0)
-            for (int i = 0; i < n; ++i) U[i + (int64_t)n * r] = -U[i + (int64_t)n * r];
+    const bool alds = n <= TE_LDS_N, zlds = teig_z_fits(n, R, alds);
+    const TeScratch sc = teig_scratch_layout((double *)(ws + d.eig_off), n, R, alds);
+    if (alds) {
+        if (zlds) teig_body<true, true>(S, n, n, R, U, n, nullptr, true, sc, flag);
+        else teig_body<true, false>(S, n, n, R, U, n, nullptr, true, sc, flag);
+    } else {
+        if (zlds) teig_body<false, true>(S, n, n, R, U, n, nullptr, true, sc, flag);
+        else teig_body<false, false>(S, n, n, R, U, n, nullptr, true, sc, flag);
     }
 }
 
@@ -289,19 +184,12 @@ size_t batch_gram_lds(int prec, int wt) {
     return std::max(l1, gen);
 }
 
-size_t batch_eig_lds(int64_t n, int64_t p) {
-    auto jac = [](int64_t m) -> size_t {
-        const size_t both = jacobi_small_lds(m, true);
-        return both <= (size_t)BATCH_LDS_AV ? both : jacobi_small_lds(m, false);
-    };
-    if (p == 0) return jac(n);
-    return std::max({jac(p), chol_lds_bytes(p), (size_t)2 * 32 * 33 * 8});
+size_t batch_eig_lds(int64_t n, int64_t R) {
+    const bool alds = n <= TE_LDS_N;
+    return teig_lds_bytes(n, R, alds, teig_z_fits(n, R, alds));
 }
 
-size_t batch_eig_scratch(int64_t n, int64_t p) {
-    if (p == 0) return std::max((size_t)2 * n * n * 8, jacobi_small_vg(n));
-    return (size_t)(3 * n * p + 4 * p * p + 2 * p * p) * 8;
-}
+size_t batch_eig_scratch(int64_t n, int64_t R) { return teig_scratch_doubles(n, R, n <= TE_LDS_N) * 8; }
 
 namespace {
 template <int PREC, int WT>
@@ -387,7 +275,7 @@ hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int 
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(batch_eig_kernel, dim3((unsigned)sp.count), dim3(BE_THREADS), lds, s, t.descs, ws, Up,
-                           order, mode, flag, 1e-15, max_sweeps);
+                           order, mode, flag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {

@@ -1,21 +1,30 @@
 // FP64 symmetric eigensolver for the EIG branch of Alg. 2: the R_n leading
 // eigenvectors of the mode-n Gram matrix.
 //
-// Two-sided cyclic Jacobi with a parallel (round-robin tournament) ordering,
-// run by one 512-thread workgroup.  In every round the n/2 disjoint
-// rotations are computed first; then A <- J^T A J is applied block-wise
-// (each thread transforms whole 2x2 blocks (pair I, pair J), which are
-// independent within a round) and V <- V J.  After each sweep the
-// off-diagonal mass is measured and the iteration stops when
-// off(A) <= tol * ||A||_F.  A and V live in LDS when they fit and in the
-// workspace otherwise.
+// Routes (eig_launch):
+//   * eig_leading up to order 128: two-sided cyclic Jacobi with a parallel
+//     (round-robin) ordering in one 512-thread workgroup, A and V in LDS when
+//     they fit (jacobi_*_kernel; relative accuracy, sweep cap reported).
+//   * decompositions up to order 128, and every order where the subspace
+//     iteration does not apply: the direct solver of teig_body.h
+//     (tridiagonalization, bisection, inverse iteration) in one workgroup.
+//   * above order 128 with a block p = R + 16 (rounded to 8) <= 128: subspace
+//     iteration Q <- orth(S Q) from a seeded Gaussian block (3 products;
+//     orth = shifted Cholesky-QR), Rayleigh-Ritz with the direct solver on
+//     T = Q^T S Q, then a residual test: the R Ritz pairs are accepted when
+//     every ||S u - theta u|| <= 16 sqrt(n) eps |theta_1| (the accuracy of a
+//     backward-stable direct solver).  Otherwise the direct solver runs on S
+//     itself (one launch that returns at once when the test passed), so the
+//     result is the leading eigenpairs on every spectrum, with or without a
+//     gap after R.
 //
-// Selection: eigenvalues sorted in descending order (ties by index), the R
-// leading eigenvectors signed so that their entry of largest magnitude is
-// positive (first index on ties).
+// Selection: eigenvalues in descending order, the R leading eigenvectors
+// signed so that their entry of largest magnitude is positive (first index
+// on ties).
 #include "common.h"
 #include "eig_body.h"
 #include "internal.h"
+#include "teig_body.h"
 
 namespace sth {
 
@@ -75,25 +84,130 @@ __global__ void sign_fix_kernel(double *__restrict__ U, int n, int R) {
         for (int i = threadIdx.x; i < n; i += blockDim.x) U[i + (int64_t)n * r] = -U[i + (int64_t)n * r];
 }
 
+template <bool ALDS, bool ZLDS>
+__global__ __launch_bounds__(TE_T) void teig_kernel(const double *__restrict__ S, int64_t lds, int n, int R,
+                                                   double *__restrict__ U, int64_t ldu,
+                                                   double *__restrict__ lam, int sign_rule, TeScratch sc,
+                                                   int64_t *__restrict__ flag, const double *__restrict__ chk,
+                                                   double chk_tol) {
+    if (chk) {
+        // after the subspace iteration: run only when a Ritz residual
+        // chk[r] exceeds chk_tol * chk[R] (chk[R] = |theta_1|) or is not finite
+        __shared__ int s_run;
+        if (threadIdx.x < 64) {
+            const double thr = chk_tol * chk[R];
+            int run = 0;
+            for (int r = threadIdx.x; r < R; r += 64)
+                if (!(chk[r] <= thr)) run = 1;
+            const bool any = __ballot(run) != 0;
+            if (threadIdx.x == 0) s_run = any ? 1 : 0;
+        }
+        __syncthreads();
+        if (!s_run) return;
+        if (threadIdx.x == 0 && flag) flag[1] += 1;   // direct solves taken (diagnostic)
+    }
+    teig_body<ALDS, ZLDS>(S, lds, n, R, U, ldu, lam, sign_rule != 0, sc, flag);
+}
+
+// Rayleigh-Ritz finish, one workgroup per Ritz vector r:
+//   U(:, r) = Q W(:, r), then the sign rule on it;
+//   res[r] = ||Z W(:, r) - theta_r U(:, r)|| with Z = S Q (the Ritz residual);
+//   lam[r] = theta_r; res[R] = |theta_1| (workgroup 0).
+__global__ __launch_bounds__(256) void rr_finish_kernel(const double *__restrict__ Q, const double *__restrict__ Zs,
+                                                        int n, int p, const double *__restrict__ W,
+                                                        const double *__restrict__ th, int R,
+                                                        double *__restrict__ U, double *__restrict__ lam,
+                                                        double *__restrict__ res) {
+    const int r = blockIdx.x, tid = threadIdx.x;
+    __shared__ double s_w[SI_BLOCK_MAX];
+    __shared__ double s_ss[4], s_bv[4], s_vv[4];
+    __shared__ int s_bi[4];
+    __shared__ double s_sign;
+    for (int k = tid; k < p; k += 256) s_w[k] = W[k + (int64_t)p * r];
+    __syncthreads();
+    const double t = th[r];
+    double ss = 0.0, best = -1.0, bval = 0.0;
+    int arg = 0;
+    for (int i = tid; i < n; i += 256) {
+        double u = 0.0, z = 0.0;
+        for (int k = 0; k < p; ++k) {
+            u += Q[i + (int64_t)n * k] * s_w[k];
+            z += Zs[i + (int64_t)n * k] * s_w[k];
+        }
+        const double d = z - t * u;
+        ss += d * d;
+        U[i + (int64_t)n * r] = u;
+        if (fabs(u) > best) {
+            best = fabs(u);
+            arg = i;
+            bval = u;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        ss += __shfl_xor(ss, o);
+        const double b2 = __shfl_xor(best, o), v2 = __shfl_xor(bval, o);
+        const int a2 = __shfl_xor(arg, o);
+        if (b2 > best || (b2 == best && a2 < arg)) {
+            best = b2;
+            arg = a2;
+            bval = v2;
+        }
+    }
+    if ((tid & 63) == 0) {
+        s_ss[tid >> 6] = ss;
+        s_bv[tid >> 6] = best;
+        s_bi[tid >> 6] = arg;
+        s_vv[tid >> 6] = bval;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double tot = 0.0, b = s_bv[0], v = s_vv[0];
+        int a = s_bi[0];
+        for (int w = 0; w < 4; ++w) tot += s_ss[w];
+        for (int w = 1; w < 4; ++w)
+            if (s_bv[w] > b || (s_bv[w] == b && s_bi[w] < a)) {
+                b = s_bv[w];
+                a = s_bi[w];
+                v = s_vv[w];
+            }
+        s_sign = v < 0.0 ? -1.0 : 1.0;
+        res[r] = sqrt(tot);
+        if (lam) lam[r] = t;
+        if (r == 0) res[R] = fabs(t);
+    }
+    __syncthreads();
+    if (s_sign < 0.0)
+        for (int i = tid; i < n; i += 256) U[i + (int64_t)n * r] = -U[i + (int64_t)n * r];
+}
+
 namespace {
 
 constexpr int SI_ITERS = SI_ITERS_DEV;
 int64_t si_block(int64_t n, int64_t R) { return si_block_host(n, R); }
 
-// si_min: the order above which the subspace iteration may be used
-bool use_si(int64_t n, int64_t R, int64_t si_min) {
+// The subspace iteration applies above order 128 when its block fits and
+// leaves a guard (p < n) and R is within the Gram's rank bound.
+bool use_si(int64_t n, int64_t R, int64_t rank_bound) {
     const int64_t p = si_block(n, R);
-    return n > si_min && p <= SI_BLOCK_MAX && p < n && (n > EIG_LDS_DIRECT_MAX || 2 * p <= n);
+    return n > EIG_DIRECT_MAX && p <= SI_BLOCK_MAX && p < n && R <= rank_bound;
 }
 
+// residual test of the Ritz pairs: ||S u - theta u|| <= SI_RES_C sqrt(n) eps |theta_1|
+constexpr double SI_RES_C = 16.0;
+
 struct SiWs {
-    double *Q, *Z, *Z2, *G, *Rf, *Rinv, *T, *W, *gws;
-    char *jac;
+    double *Q, *Z, *Z2, *G, *Rf, *Rinv, *T, *W, *th, *res, *gws;
+    double *te;   // teig scratch of the p x p Rayleigh-Ritz problem
+    double *fb;   // teig scratch of the direct solve of S (fallback)
 };
 
 size_t jacobi_ws(int64_t n) { return (size_t)(256 + 2 * n * n * sizeof(double)); }
 
-SiWs si_layout(char *ws, int64_t n, int64_t p) {
+size_t si_gemm_doubles(int64_t n, int64_t p) {
+    return std::max<size_t>(gemm_ws_bytes((int)p, (int)p, (int)n), gemm_ws_bytes((int)n, (int)p, (int)n)) / 8 + 1;
+}
+
+SiWs si_layout(char *ws, int64_t n, int64_t p, int64_t R) {
     SiWs w;
     double *d = (double *)(ws + 256);
     w.Q = d; d += n * p;
@@ -104,16 +218,20 @@ SiWs si_layout(char *ws, int64_t n, int64_t p) {
     w.Rinv = d; d += p * p;
     w.T = d; d += p * p;
     w.W = d; d += p * p;
-    w.gws = d; d += std::max<size_t>(gemm_ws_bytes((int)p, (int)p, (int)n), gemm_ws_bytes((int)n, (int)p, (int)n)) / 8 + 1;
-    w.jac = (char *)(((uintptr_t)d + 255) & ~(uintptr_t)255);   // 16-byte accesses in the Jacobi
+    w.th = d; d += p;
+    w.res = d; d += p + 1;
+    w.gws = d; d += si_gemm_doubles(n, p);
+    w.te = d; d += teig_scratch_doubles(p, R, true);
+    w.fb = d;
     return w;
 }
 
-size_t si_bytes(int64_t n, int64_t p) {
-    return 256 + (size_t)(3 * n * p + 5 * p * p) * 8 +
-           std::max<size_t>(gemm_ws_bytes((int)p, (int)p, (int)n), gemm_ws_bytes((int)n, (int)p, (int)n)) + 8 +
-           jacobi_ws(p) + 256;
+size_t si_bytes(int64_t n, int64_t p, int64_t R) {
+    return 256 + (size_t)(3 * n * p + 5 * p * p + 2 * p + 1) * 8 + si_gemm_doubles(n, p) * 8 +
+           teig_scratch_doubles(p, R, true) * 8 + teig_scratch_doubles(n, R, n <= TE_LDS_N) * 8 + 256;
 }
+
+size_t teig_bytes(int64_t n, int64_t R) { return 256 + teig_scratch_doubles(n, R, n <= TE_LDS_N) * 8; }
 
 // Cholesky-QR of the n x p matrix A into Q; shift_rel > 0 gives the shifted
 // first pass of the shifted Cholesky-QR3 scheme (stable for condition numbers
@@ -171,36 +289,60 @@ hipError_t jacobi_launch(int64_t n, int64_t R, const double *S, double *U, doubl
     return hipGetLastError();
 }
 
+template <bool ALDS, bool ZLDS>
+hipError_t teig_go(const double *S, int64_t lds, int64_t n, int64_t R, double *U, int64_t ldu, double *lam,
+                   bool sign_rule, TeScratch sc, int64_t *flag, const double *chk, double chk_tol, size_t lds_b,
+                   hipStream_t s) {
+    auto k = teig_kernel<ALDS, ZLDS>;
+    if (hipError_t ea = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_b))
+        return ea;
+    hipLaunchKernelGGL(k, dim3(1), dim3(TE_T), lds_b, s, S, lds, (int)n, (int)R, U, ldu, lam, sign_rule ? 1 : 0, sc,
+                       flag, chk, chk_tol);
+    return hipGetLastError();
+}
+
 }  // namespace
 
+// Direct solver (teig_body.h) on the n x n matrix S: the matrix in LDS up to
+// order TE_LDS_N, in the scratch above; scratch holds teig_bytes(n, R).
+hipError_t teig_launch(const double *S, int64_t lds, int64_t n, int64_t R, double *U, int64_t ldu, double *lam,
+                       bool sign_rule, void *scratch, int64_t *flag, const double *chk, double chk_tol,
+                       hipStream_t s) {
+    const bool alds = n <= TE_LDS_N;
+    const bool zlds = teig_z_fits(n, R, alds);
+    const TeScratch sc = teig_scratch_layout((double *)scratch, n, R, alds);
+    const size_t lb = teig_lds_bytes(n, R, alds, zlds);
+    if (alds) {
+        return zlds ? teig_go<true, true>(S, lds, n, R, U, ldu, lam, sign_rule, sc, flag, chk, chk_tol, lb, s)
+                    : teig_go<true, false>(S, lds, n, R, U, ldu, lam, sign_rule, sc, flag, chk, chk_tol, lb, s);
+    }
+    return zlds ? teig_go<false, true>(S, lds, n, R, U, ldu, lam, sign_rule, sc, flag, chk, chk_tol, lb, s)
+                : teig_go<false, false>(S, lds, n, R, U, ldu, lam, sign_rule, sc, flag, chk, chk_tol, lb, s);
+}
+
 size_t eig_ws_bytes(int64_t n) {
-    size_t b = jacobi_ws(n);
-    // subspace iteration for any R that selects it
+    // every R <= n: the direct solver, the subspace iteration, or Jacobi
+    size_t b = std::max(jacobi_ws(n), teig_bytes(n, n));
     for (int64_t R = 1; R <= n; ++R)
-        if (use_si(n, R, EIG_SI_MIN)) b = std::max(b, si_bytes(n, si_block(n, R)));
+        if (use_si(n, R, n)) b = std::max(b, si_bytes(n, si_block(n, R), R));
     return b;
 }
 
-// R leading eigenpairs of the symmetric n x n matrix S.
-//   n <= si_min (128 for eig_leading, 96 for the decompositions, which need
-//   the leading subspace only): cyclic Jacobi on S itself (one workgroup,
-//   LDS; V in the workspace above order 96).
-//   n > si_min with a block p = R + 16 (rounded up to 8) <= 96, p < n: subspace iteration
-//     Q <- orth(S Q) from a seeded Gaussian block (SI_ITERS = 3 times; orth is
-//     shifted Cholesky-QR, three passes for the last basis, two before), then
-//     Rayleigh-Ritz: Jacobi on T = Q^T S Q and U = Q W(:, :R), with the sign
-//     rule applied to U.
-//   otherwise (large R, or R above the rank bound of S): Jacobi on S with A
-//   and V in the workspace.
+// R leading eigenpairs of the symmetric n x n matrix S (routes: see the top
+// of this file).  jacobi_small: eig_leading's route for n <= 128 (Jacobi);
+// otherwise the direct solver there.  rank_bound: rank(S) <= rank_bound (the
+// subspace block is capped at it, and more vectors than that need the direct
+// solver).
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
                       int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound,
-                      int64_t si_min) {
-    // rank(S) <= rank_bound: a block wider than that would be rank deficient
-    // (Cholesky-QR breaks down), so the block shrinks to the bound, and a
-    // request of more than rank_bound vectors goes to the direct solver
-    if (!use_si(n, R, si_min) || R > rank_bound) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
+                      bool jacobi_small) {
+    if (n <= EIG_DIRECT_MAX) {
+        if (jacobi_small) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
+        return teig_launch(S, n, n, R, U, n, lam, true, (char *)ws + 256, flag, nullptr, 0.0, s);
+    }
+    if (!use_si(n, R, rank_bound)) return teig_launch(S, n, n, R, U, n, lam, true, (char *)ws + 256, flag, nullptr, 0.0, s);
     const int64_t p = std::min(si_block(n, R), rank_bound);
-    SiWs w = si_layout((char *)ws, n, p);
+    SiWs w = si_layout((char *)ws, n, p, R);
     const int ni = (int)n, pi = (int)p;
     hipError_t e;
     // start block: seeded Gaussian, used as it is (its span is all that
@@ -210,13 +352,16 @@ hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *
         if ((e = gemm_f64(0, 0, ni, pi, ni, 1.0, S, n, w.Q, n, 0.0, w.Z, n, w.gws, s))) return e;
         if ((e = orth(w.Z, w.Q, ni, pi, it + 1 == SI_ITERS ? 3 : 2, w, flag, s))) return e;
     }
-    // Rayleigh-Ritz
+    // Rayleigh-Ritz: T = Q^T S Q, its R leading pairs (W, theta), U = Q W
     if ((e = gemm_f64(0, 0, ni, pi, ni, 1.0, S, n, w.Q, n, 0.0, w.Z, n, w.gws, s))) return e;
     if ((e = gemm_f64(1, 0, pi, pi, ni, 1.0, w.Q, n, w.Z, n, 0.0, w.T, p, w.gws, s))) return e;
-    if ((e = jacobi_launch(p, R, w.T, w.W, lam, tol, max_sweeps, w.jac, flag, s))) return e;
-    if ((e = gemm_f64(0, 0, ni, (int)R, pi, 1.0, w.Q, n, w.W, p, 0.0, U, n, w.gws, s))) return e;
-    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)R), dim3(256), 0, s, U, ni, (int)R);
-    return hipGetLastError();
+    if ((e = teig_launch(w.T, p, p, R, w.W, p, w.th, false, w.te, flag, nullptr, 0.0, s))) return e;
+    hipLaunchKernelGGL(rr_finish_kernel, dim3((unsigned)R), dim3(256), 0, s, w.Q, w.Z, ni, pi, w.W, w.th, (int)R, U,
+                       lam, w.res);
+    if ((e = hipGetLastError())) return e;
+    // residual test; the direct solver on S when it fails
+    const double tol_res = SI_RES_C * std::sqrt((double)n) * 2.220446049250313e-16;
+    return teig_launch(S, n, n, R, U, n, lam, true, w.fb, flag, w.res, tol_res, s);
 }
 
 }  // namespace sth

@@ -36,10 +36,15 @@ hipError_t gram_launch(int dtype, int prec, const void *A, const void *B, int64_
 
 // Eigensolver (eig.hip)
 size_t eig_ws_bytes(int64_t n);
-// si_min: the order above which the subspace iteration may replace Jacobi
+// jacobi_small: Jacobi up to order 128 (eig_leading), else the direct solver
+// there (decompositions); rank_bound: rank(S) <= rank_bound
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
                       int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound,
-                      int64_t si_min);
+                      bool jacobi_small);
+// the direct solver alone (scratch: teig_scratch_doubles(n, R, n <= 128) doubles)
+hipError_t teig_launch(const double *S, int64_t lds, int64_t n, int64_t R, double *U, int64_t ldu, double *lam,
+                       bool sign_rule, void *scratch, int64_t *flag, const double *chk, double chk_tol,
+                       hipStream_t s);
 
 // Small FP64 LA and reductions (la.hip)
 int gemm_splits(int m, int n, int k);
@@ -70,7 +75,7 @@ struct BatchStep {
     int64_t kper, gram_wg;
     int32_t nkc, nbi, nblocks, wt;
     int32_t nchunks, ntiles, rtb, contig;
-    int32_t tensor, sib;   // sib: subspace-iteration block (I > 128), capped at L * M
+    int32_t tensor, sib;   // sib: unused (0)
 };
 struct BatchLaunch {
     const int32_t *list;  // device: indices into the step's descriptors
@@ -90,8 +95,8 @@ struct BatchStepPlan {
     BatchLaunch prep;
 };
 size_t batch_gram_lds(int prec, int wt);
-size_t batch_eig_lds(int64_t n, int64_t p);   // p: the step's subspace block (0: direct Jacobi)
-size_t batch_eig_scratch(int64_t n, int64_t p);
+size_t batch_eig_lds(int64_t n, int64_t R);      // dynamic LDS of the batched eigen workgroup
+size_t batch_eig_scratch(int64_t n, int64_t R);  // its global scratch (bytes)
 hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int gram_prec,
                              int ttm_prec, int order, int mode, char *ws, const void *const *Xp,
                              void *const *Cp, double *const *Up, int64_t *flag, int max_sweeps,
