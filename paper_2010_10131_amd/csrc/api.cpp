@@ -343,7 +343,8 @@ static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *s
     if (stp.solver == STH_SOLVER_EIG) {
         // Alg. 2 lines 6-8
         HIPCHK(gram_launch(p->dtype, gp, src, src, stp.L, stp.I, stp.I, stp.M, true, part, S, s), "gram");
-        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M, false),
+        HIPCHK(eig_launch(stp.I, stp.R, S, Un, lam, 1e-15, p->max_sweeps, eigws, flag, s, stp.L * stp.M, false,
+                          gram_unit(gp)),
                "eig");
         HIPCHK(ttm_prep_u(Un, stp.I, stp.R, 0, tp, uq, s), "ttm prep");
         HIPCHK(ttm_launch(p->dtype, tp, src, uq, dst, stp.L, stp.I, stp.R, stp.M, s), "ttm");
@@ -569,7 +570,7 @@ extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double 
     if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
     HIPCHK(zero_words(ws, 2, (hipStream_t)stream), "flag clear");
     HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (int64_t *)ws,
-                      (hipStream_t)stream, n, true), "eig");
+                      (hipStream_t)stream, n, true, 0.0), "eig");
     return STH_OK;
 }
 
@@ -693,7 +694,8 @@ extern "C" sth_status sth_hooi(int32_t order, const int64_t *dims, const int64_t
             lim(order, cur.data(), n, Ln, In, Mn);
             double *S = (double *)(w + L.S);
             HIPCHK(gram_launch(dtype, gram_prec, Y, Y, Ln, In, In, Mn, true, (double *)(w + L.part), S, s), "hooi gram");
-            HIPCHK(eig_launch(In, ranks[n], S, U[n], nullptr, 1e-15, 60, w + L.eig, flag, s, Ln * Mn, false),
+            HIPCHK(eig_launch(In, ranks[n], S, U[n], nullptr, 1e-15, 60, w + L.eig, flag, s, Ln * Mn, false,
+                              gram_unit(gram_prec)),
                    "hooi eig");
         }
     return chain(order, core, cur, Y);

@@ -186,7 +186,7 @@ size_t batch_gram_lds(int prec, int wt) {
 
 size_t batch_eig_lds(int64_t n, int64_t R) {
     const bool alds = n <= TE_LDS_N;
-    return teig_lds_bytes(n, R, alds, teig_z_fits(n, R, alds));
+    return teig_lds_bytes(n, R, alds, teig_z_fits(n, R, alds), teig_v_keep(n, R, alds));
 }
 
 size_t batch_eig_scratch(int64_t n, int64_t R) { return teig_scratch_doubles(n, R, n <= TE_LDS_N) * 8; }

@@ -12,11 +12,14 @@
 //     iteration Q <- orth(S Q) from a seeded Gaussian block (3 products;
 //     orth = shifted Cholesky-QR), Rayleigh-Ritz with the direct solver on
 //     T = Q^T S Q, then a residual test: the R Ritz pairs are accepted when
-//     every ||S u - theta u|| <= 16 sqrt(n) eps |theta_1| (the accuracy of a
-//     backward-stable direct solver).  Otherwise the direct solver runs on S
-//     itself (one launch that returns at once when the test passed), so the
-//     result is the leading eigenpairs on every spectrum, with or without a
-//     gap after R.
+//     every ||S u - theta u|| <= max(16 sqrt(n) eps, u_S) |theta_1|, i.e. when
+//     they are exact eigenpairs of a perturbation of S no larger than that of
+//     a backward-stable direct solver or than the rounding S already carries
+//     (u_S: the unit roundoff of the products that formed S, eps for FP64
+//     products, 2^-24 for FP32 and bf16x6, 2^-17 for bf16x3).  Otherwise the
+//     direct solver runs on S itself (one launch that returns at once when
+//     the test passed), so the result is the leading eigenpairs on every
+//     spectrum, with or without a gap after R.
 //
 // Selection: eigenvalues in descending order, the R leading eigenvectors
 // signed so that their entry of largest magnitude is positive (first index
@@ -192,7 +195,7 @@ bool use_si(int64_t n, int64_t R, int64_t rank_bound) {
     return n > EIG_DIRECT_MAX && p <= SI_BLOCK_MAX && p < n && R <= rank_bound;
 }
 
-// residual test of the Ritz pairs: ||S u - theta u|| <= SI_RES_C sqrt(n) eps |theta_1|
+// residual test of the Ritz pairs: ||S u - theta u|| <= max(SI_RES_C sqrt(n) eps, u_S) |theta_1|
 constexpr double SI_RES_C = 16.0;
 
 struct SiWs {
@@ -311,7 +314,7 @@ hipError_t teig_launch(const double *S, int64_t lds, int64_t n, int64_t R, doubl
     const bool alds = n <= TE_LDS_N;
     const bool zlds = teig_z_fits(n, R, alds);
     const TeScratch sc = teig_scratch_layout((double *)scratch, n, R, alds);
-    const size_t lb = teig_lds_bytes(n, R, alds, zlds);
+    const size_t lb = teig_lds_bytes(n, R, alds, zlds, teig_v_keep(n, R, alds));
     if (alds) {
         return zlds ? teig_go<true, true>(S, lds, n, R, U, ldu, lam, sign_rule, sc, flag, chk, chk_tol, lb, s)
                     : teig_go<true, false>(S, lds, n, R, U, ldu, lam, sign_rule, sc, flag, chk, chk_tol, lb, s);
@@ -332,10 +335,11 @@ size_t eig_ws_bytes(int64_t n) {
 // of this file).  jacobi_small: eig_leading's route for n <= 128 (Jacobi);
 // otherwise the direct solver there.  rank_bound: rank(S) <= rank_bound (the
 // subspace block is capped at it, and more vectors than that need the direct
-// solver).
+// solver).  s_unit: unit roundoff of the products that formed S (0 when S is
+// exact data).
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
                       int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound,
-                      bool jacobi_small) {
+                      bool jacobi_small, double s_unit) {
     if (n <= EIG_DIRECT_MAX) {
         if (jacobi_small) return jacobi_launch(n, R, S, U, lam, tol, max_sweeps, ws, flag, s);
         return teig_launch(S, n, n, R, U, n, lam, true, (char *)ws + 256, flag, nullptr, 0.0, s);
@@ -360,7 +364,7 @@ hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *
                        lam, w.res);
     if ((e = hipGetLastError())) return e;
     // residual test; the direct solver on S when it fails
-    const double tol_res = SI_RES_C * std::sqrt((double)n) * 2.220446049250313e-16;
+    const double tol_res = std::max(SI_RES_C * std::sqrt((double)n) * 2.220446049250313e-16, s_unit);
     return teig_launch(S, n, n, R, U, n, lam, true, w.fb, flag, w.res, tol_res, s);
 }
 

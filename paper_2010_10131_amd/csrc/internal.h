@@ -37,10 +37,14 @@ hipError_t gram_launch(int dtype, int prec, const void *A, const void *B, int64_
 // Eigensolver (eig.hip)
 size_t eig_ws_bytes(int64_t n);
 // jacobi_small: Jacobi up to order 128 (eig_leading), else the direct solver
-// there (decompositions); rank_bound: rank(S) <= rank_bound
+// there (decompositions); rank_bound: rank(S) <= rank_bound; s_unit: unit
+// roundoff of the products that formed S (gram_unit(prec); 0 for exact data)
 hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *lam, double tol,
                       int max_sweeps, void *ws, int64_t *flag, hipStream_t s, int64_t rank_bound,
-                      bool jacobi_small);
+                      bool jacobi_small, double s_unit);
+inline double gram_unit(int prec) {
+    return prec == 0 ? 1.1102230246251565e-16 : (prec == 2 ? 7.62939453125e-06 : 5.9604644775390625e-08);
+}
 // the direct solver alone (scratch: teig_scratch_doubles(n, R, n <= 128) doubles)
 hipError_t teig_launch(const double *S, int64_t lds, int64_t n, int64_t R, double *U, int64_t ldu, double *lam,
                        bool sign_rule, void *scratch, int64_t *flag, const double *chk, double chk_tol,

@@ -14,10 +14,12 @@
 //      the leading principal minors p_i of T - sigma I, taken with the
 //      three-term recurrence p_i = (d_i - sigma) p_{i-1} - e_{i-1}^2 p_{i-2}
 //      (no division; the pair is rescaled by a power of two when it leaves
-//      [2^-200, 2^200], which keeps every sign).  A minor that vanishes is
-//      replaced by -pivmin times its predecessor (the pivot -pivmin of the
-//      LDL^T form of the count).  Each eigenvalue is searched by a group of
-//      lanes that splits its interval into (group size + 1) parts per round.
+//      [2^-100, 2^100], which keeps every sign).  e^2 is floored at
+//      (2^-60 ||T||)^2, so a vanishing minor is never followed by another
+//      and counts as positive (the LDL^T count with a negative-zero pivot).
+//      Each eigenvalue is searched by a group of
+//      lanes, each lane counting at 4 points at once (independent chains),
+//      which splits the bracket into (4 x group size + 1) parts per round.
 //   3. Eigenvectors of T by inverse iteration: two solves of
 //      (T - lambda I) x = b by Gaussian elimination with partial pivoting,
 //      from a pseudo-random start vector of each eigenvector's own.
@@ -61,14 +63,19 @@ struct TeScratch {
 __host__ __device__ inline int64_t te_part_doubles(int64_t n) { return 16 * n > 1024 ? 16 * n : 1024; }
 // dynamic LDS of teig_body: the main region (A while tridiagonalizing, then
 // the eigenvector block), the partial sums and the vectors.
-__host__ __device__ inline size_t teig_lds_bytes(int64_t n, int64_t R, bool alds, bool zlds) {
+__host__ __device__ inline size_t teig_lds_bytes(int64_t n, int64_t R, bool alds, bool zlds, bool vkeep = false) {
     int64_t main = 0;
     if (alds) main = n * n;
     if (zlds && n * R > main) main = n * R;
-    return (size_t)(main + te_part_doubles(n) + 6 * n + R) * 8 + (size_t)R * 4 + 16;
+    if (alds && vkeep) main = n * n + n * R;   // reflectors stay in A's lower part, Z beside them
+    return (size_t)(main + te_part_doubles(n) + 8 * n + R) * 8 + (size_t)R * 4 + 16;
 }
 __host__ __device__ inline bool teig_z_fits(int64_t n, int64_t R, bool alds) {
     return teig_lds_bytes(n, R, alds, true) <= (size_t)TE_LDS_BUDGET;
+}
+// the reflectors can stay in LDS through the back-transformation
+__host__ __device__ inline bool teig_v_keep(int64_t n, int64_t R, bool alds) {
+    return alds && teig_lds_bytes(n, R, true, true, true) <= (size_t)TE_LDS_BUDGET;
 }
 __host__ __device__ inline size_t teig_scratch_doubles(int64_t n, int64_t R, bool alds) {
     return (size_t)((alds ? n * n : 0) + 3 * n * R + R * R + n * R + (alds ? 0 : n * n)) + 64;
@@ -89,10 +96,26 @@ __host__ __device__ inline TeScratch teig_scratch_layout(double *base, int64_t n
     return t;
 }
 
+// DPP move of both halves of a double (lanes the pattern leaves out read 0)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double te_dpp(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, true);
+    return __hiloint2double(hi, lo);
+}
+// Sum over the 64 lanes of a wave, returned in every lane: row_shr 1, 2, 4, 8
+// leave each 16-lane row's sum in its last lane, row_bcast 15 and 31 carry
+// them into lane 63, read back with readlane (register moves only, no LDS).
 __device__ __forceinline__ double te_wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    v += te_dpp<0x111, 0xf>(v);   // row_shr:1
+    v += te_dpp<0x112, 0xf>(v);   // row_shr:2
+    v += te_dpp<0x114, 0xf>(v);   // row_shr:4
+    v += te_dpp<0x118, 0xf>(v);   // row_shr:8
+    v += te_dpp<0x142, 0xa>(v);   // row_bcast:15 into rows 1 and 3
+    v += te_dpp<0x143, 0xc>(v);   // row_bcast:31 into rows 2 and 3
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double te_wave_max(double v) {
 #pragma unroll
@@ -105,26 +128,61 @@ __device__ __forceinline__ double te_wave_min(double v) {
     return v;
 }
 
-// Number of eigenvalues of the tridiagonal (d, e2 = e^2) below sig.
-__device__ __forceinline__ int te_sturm(const double *__restrict__ d, const double *__restrict__ e2, int n,
-                                        double sig, double pivmin) {
-    double p0 = 1.0, p1 = d[0] - sig;
-    if (fabs(p1) < pivmin) p1 = -pivmin;
-    int cnt = p1 < 0.0;
-    for (int i = 1; i < n; ++i) {
-        double p2 = (d[i] - sig) * p1 - e2[i - 1] * p0;
-        if (fabs(p2) < pivmin * fabs(p1)) p2 = -pivmin * p1;
-        cnt += (p2 < 0.0) != (p1 < 0.0);
-        const double m = fmax(fabs(p1), fabs(p2));
-        if (m > 0x1p200 || m < 0x1p-200) {
-            const int ex = ilogb(m);
-            p1 = ldexp(p1, -ex);
-            p2 = ldexp(p2, -ex);
-        }
-        p0 = p1;
-        p1 = p2;
+// value of v in lane src (src uniform across the wave)
+__device__ __forceinline__ double te_lane(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
+// 1 / x: the hardware reciprocal refined by one Newton step
+__device__ __forceinline__ double te_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    const double e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Numbers of eigenvalues of the tridiagonal (d, e2 = e^2) below sig[c],
+// TE_NC independent counts interleaved: the sign changes of the leading
+// principal minors p_i of T - sigma I (a zero minor counts as positive; the
+// caller floors e^2 at a tiny positive value, so that a zero minor is never
+// followed by another and the count equals the LDL^T count of T - sigma I
+// with a negative-zero pivot).  The pair (p_{i-1}, p_i) of each count is
+// rescaled by a power of two every 4 steps: between checks the larger of the
+// pair grows by at most (|d - sigma| + e^2)^4 and shrinks by at most
+// (e^2 floor)^2, which the window [2^-100, 2^100] keeps within the normal range.
+constexpr int TE_NC = 4;
+__device__ __forceinline__ void te_sturm(const double *__restrict__ d, const double *__restrict__ e2, int n,
+                                         const double (&sig)[TE_NC], int (&cnt)[TE_NC]) {
+    double p0[TE_NC], p1[TE_NC];
+#pragma unroll
+    for (int c = 0; c < TE_NC; ++c) {
+        p0[c] = 1.0;
+        p1[c] = d[0] - sig[c];
+        cnt[c] = p1[c] < 0.0;
     }
-    return cnt;
+#pragma unroll 4
+    for (int i = 1; i < n; ++i) {
+        const double di = d[i], ei = e2[i - 1];
+#pragma unroll
+        for (int c = 0; c < TE_NC; ++c) {
+            const double p2 = fma(di - sig[c], p1[c], -ei * p0[c]);
+            cnt[c] += (p2 < 0.0) != (p1[c] < 0.0);
+            p0[c] = p1[c];
+            p1[c] = p2;
+        }
+        if ((i & 3) == 0) {
+#pragma unroll
+            for (int c = 0; c < TE_NC; ++c) {
+                const double m = fmax(fabs(p0[c]), fabs(p1[c]));
+                if (m > 0x1p100 || m < 0x1p-100) {
+                    const int ex = ilogb(m);
+                    p0[c] = ldexp(p0[c], -ex);
+                    p1[c] = ldexp(p1[c], -ex);
+                }
+            }
+        }
+    }
 }
 
 // Start vector entry of eigenvector r: uniform in [-1, 1).
@@ -147,19 +205,25 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
     __shared__ int s_bad;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t nn = (int64_t)n * n;
+    const bool vkeep = teig_v_keep(n, R, ALDS);   // uniform
     int64_t main_sz = ALDS ? nn : 0;
     if (ZLDS && (int64_t)n * R > main_sz) main_sz = (int64_t)n * R;
+    if (vkeep) main_sz = nn + (int64_t)n * R;
     double *const A = ALDS ? te_dyn : sc.Ag;            // column-major, leading dimension n
     double *const part = te_dyn + main_sz;              // te_part_doubles(n)
     double *const s_v = part + te_part_doubles(n);      // 2 n (double-buffered reflector)
-    double *const s_p = s_v + 2 * n;                    // n (p of the last step; later e^2)
+    double2 *const s_vw = (double2 *)(s_v + 2 * n);     // n pairs (v, w) of the last step
+    double *const s_p = s_v + 4 * n;                    // n (p of the last step; later e^2)
     double *const s_d = s_p + n;                        // n
     double *const s_e = s_d + n;                        // n
     double *const s_tau = s_e + n;                      // n
     double *const s_lam = s_tau + n;                    // R
     int *const s_cs = (int *)(s_lam + R);               // R cluster starts
-    double *const Z = ZLDS ? te_dyn : sc.Zg;            // row-major n x R (after step 1)
-    double *const Vr = ALDS ? sc.Vr : sc.Ag;            // reflectors
+    double *const Z = ZLDS ? (vkeep ? te_dyn + nn : te_dyn) : sc.Zg;   // row-major n x R (after step 1)
+    // reflectors: column k of A holds v_k below the diagonal (LDS or the
+    // scratch copy of A); without vkeep an LDS A is copied to sc.Vr after
+    // step 1, because Z then takes its place
+    const double *const Vr = (ALDS && !vkeep) ? sc.Vr : A;
 
     // ---- scale by a power of two, load (S + S^T) / 2 --------------------
     double mx = 0.0;
@@ -197,29 +261,50 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
     __syncthreads();
 
     // ---- 1. tridiagonalization -------------------------------------------
+    // Per step k two barriers: wave 0 first turns the partial sums of step
+    // k - 1 into p = tau A v and K = (tau / 2) p^T v, forms (v, w) of step
+    // k - 1, updates column k and builds H_k; then every wave applies step
+    // k - 1's update to the trailing block and accumulates A v_k.
+    constexpr int TU = 4;   // columns per thread whose loads are issued together
     double Kprev = 0.0;
     for (int k = 0; k + 2 < n; ++k) {
         double *const vc = s_v + (k & 1) * n;
         const double *const vp = s_v + ((k & 1) ^ 1) * n;
         if (wave == 0) {
-            // column k with the pending update of step k - 1, then H_k
-            const double vpk = k > 0 ? vp[k] : 0.0;
-            const double wpk = k > 0 ? s_p[k] - Kprev * vpk : 0.0;
-            double sig = 0.0, x0 = 0.0, akk = 0.0;
+            if (k > 0) {
+                const double taup = s_tau[k - 1];
+                double t = 0.0;
+                for (int i = k + lane; i < n; i += 64) {
+                    double sp = 0.0;
+#pragma unroll
+                    for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
+                    const double p = taup * sp;
+                    s_p[i] = p;
+                    t += p * vp[i];
+                }
+                Kprev = 0.5 * taup * te_wave_sum(t);
+            }
+            // (v, w) of step k - 1 for rows >= k, column k with that step's
+            // pending update, then H_k
+            double sig = 0.0, a0 = 0.0;
+            double wpk = 0.0, vpk = 0.0;
+            if (k > 0) {
+                vpk = vp[k];
+                wpk = s_p[k] - Kprev * vpk;
+            }
             for (int i = k + lane; i < n; i += 64) {
                 double a = A[i + (int64_t)n * k];
                 if (k > 0) {
                     const double vpi = vp[i], wpi = s_p[i] - Kprev * vpi;
+                    s_vw[i] = make_double2(vpi, wpi);
                     a -= vpi * wpk + wpi * vpk;
                 }
-                if (i == k) akk = a;
-                else if (i == k + 1) x0 = a;
-                else sig += a * a;
+                if (i >= k + 2) sig += a * a;
+                if (i == k + lane && lane < 2) a0 = a;
                 part[i] = a;
             }
             sig = te_wave_sum(sig);
-            x0 = te_wave_sum(x0);
-            akk = te_wave_sum(akk);
+            const double akk = te_lane(a0, 0), x0 = te_lane(a0, 1);
             double beta = x0, tau = 0.0, scl = 0.0;
             if (sig > 0.0) {
                 const double nrm = sqrt(x0 * x0 + sig);
@@ -227,11 +312,10 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
                 tau = (beta - x0) / beta;
                 scl = 1.0 / (x0 - beta);
             }
-            for (int i = k + lane; i < n; i += 64) {
-                if (i == k) continue;
-                const double v = (i == k + 1) ? 1.0 : part[i] * scl;
+            for (int i = k + 1 + lane; i < n; i += 64) {
+                const double v = (i == k + 1) ? 1.0 : (tau == 0.0 ? 0.0 : part[i] * scl);
                 vc[i] = v;
-                Vr[i + (int64_t)n * k] = v;
+                A[i + (int64_t)n * k] = v;   // column k is not read again by the reduction
             }
             if (lane == 0) {
                 s_d[k] = akk;
@@ -240,45 +324,53 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
             }
         }
         __syncthreads();
-        const double tau = s_tau[k];
-        // trailing block: pending update of step k - 1, and partial sums of A v
+        // trailing block: pending update of step k - 1, and partial sums of A v_k
         for (int i0 = k + 1; i0 < n; i0 += 64) {
             const int i = i0 + lane;
             if (i < n) {
-                double acc = 0.0, vpi = 0.0, wpi = 0.0;
-                if (k > 0) {
-                    vpi = vp[i];
-                    wpi = s_p[i] - Kprev * vpi;
-                }
-                for (int j = k + 1 + wave; j < n; j += TE_W) {
-                    double a = A[i + (int64_t)n * j];
-                    if (k > 0) {
-                        const double vpj = vp[j], wpj = s_p[j] - Kprev * vpj;
-                        a -= vpi * wpj + wpi * vpj;
-                        A[i + (int64_t)n * j] = a;
+                double acc = 0.0;
+                double2 pwi = make_double2(0.0, 0.0);
+                if (k > 0) pwi = s_vw[i];
+                for (int jb = k + 1 + wave; jb < n; jb += TE_W * TU) {
+                    double a[TU], vcj[TU];
+                    double2 pw[TU];
+#pragma unroll
+                    for (int u = 0; u < TU; ++u) {
+                        const int j = jb + TE_W * u;
+                        const int jc = j < n ? j : n - 1;
+                        a[u] = A[i + (int64_t)n * jc];
+                        vcj[u] = j < n ? vc[jc] : 0.0;
+                        pw[u] = (k > 0) ? s_vw[jc] : make_double2(0.0, 0.0);
                     }
-                    acc += a * vc[j];
+#pragma unroll
+                    for (int u = 0; u < TU; ++u) {
+                        const int j = jb + TE_W * u;
+                        if (k > 0) {
+                            a[u] -= pwi.x * pw[u].y + pwi.y * pw[u].x;
+                            if (j < n) A[i + (int64_t)n * j] = a[u];
+                        }
+                        acc += a[u] * vcj[u];
+                    }
                 }
                 part[wave * n + i] = acc;
             }
         }
         __syncthreads();
+    }
+    if (n >= 3 && wave == 0) {
+        // p and K of the last step (n - 3)
+        const double taup = s_tau[n - 3];
+        const double *vp = s_v + ((n - 3) & 1) * n;
         double t = 0.0;
-        for (int i = k + 1 + tid; i < n; i += TE_T) {
-            double s = 0.0;
+        for (int i = n - 2 + lane; i < n; i += 64) {
+            double sp = 0.0;
 #pragma unroll
-            for (int w = 0; w < TE_W; ++w) s += part[w * n + i];
-            const double p = tau * s;
+            for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
+            const double p = taup * sp;
             s_p[i] = p;
-            t += p * vc[i];
+            t += p * vp[i];
         }
-        t = te_wave_sum(t);
-        if (lane == 0) s_red[wave] = t;
-        __syncthreads();
-        double pv = 0.0;
-#pragma unroll
-        for (int w = 0; w < TE_W; ++w) pv += s_red[w];
-        Kprev = 0.5 * tau * pv;
+        Kprev = 0.5 * taup * te_wave_sum(t);
     }
     if (tid == 0) {
         if (n >= 3) {
@@ -299,6 +391,9 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
     }
     __syncthreads();
 
+    if (ALDS && !vkeep)
+        for (int64_t e = tid; e < nn; e += TE_T) sc.Vr[e] = A[e];
+
     // ---- 2. bisection for the R largest eigenvalues ----------------------
     double glo = 1e300, ghi = -1e300;
     for (int i = tid; i < n; i += TE_T) {
@@ -312,7 +407,6 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
         s_red[wave] = glo;
         s_red2[wave] = ghi;
     }
-    for (int i = tid; i + 1 < n; i += TE_T) s_p[i] = s_e[i] * s_e[i];
     __syncthreads();
     glo = s_red[0];
     ghi = s_red2[0];
@@ -321,25 +415,44 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
         ghi = fmax(ghi, s_red2[w]);
     }
     const double tnorm = fmax(fmax(fabs(glo), fabs(ghi)), 1e-300);
-    const double pivmin = 1e-80;
     glo -= 4.0 * 2.220446049250313e-16 * tnorm;
     ghi += 4.0 * 2.220446049250313e-16 * tnorm;
     {
+        // e^2, floored at (2^-60 ||T||)^2: a change of the off-diagonal below
+        // 1e-18 ||T||, far under the eps ||T|| accuracy of the eigenvalues
+        const double e2min = 0x1p-120 * tnorm * tnorm;
+        for (int i = tid; i + 1 < n; i += TE_T) s_p[i] = fmax(s_e[i] * s_e[i], e2min);
+    }
+    __syncthreads();
+    {
+        // a group of tpe lanes searches one eigenvalue, TE_NC points per lane:
+        // each round splits the bracket into tpe * TE_NC + 1 parts.  Groups
+        // cover at most 256 lanes (one wave per SIMD) at a time: more lanes
+        // would only add FP64 work per round (the counts, not their latency,
+        // bound the search)
         int tpe = 64;
-        while (tpe > 1 && tpe * R > TE_T) tpe >>= 1;
+        while (tpe > 1 && tpe * R > 256) tpe >>= 1;   // at most four waves: the counts are FP64-throughput bound
         const int ngroups = TE_T / tpe, g = tid / tpe, t = tid % tpe;
+        const double npts1 = (double)(tpe * TE_NC + 1);
         const int rounds_r = (R + ngroups - 1) / ngroups;
         for (int rr = 0; rr < rounds_r; ++rr) {
             const int r = g + rr * ngroups;
             if (r < R) {   // uniform within the group
                 const int kk = n - 1 - r;   // the kk-th smallest, 0-based
                 double lo = glo, hi = ghi;
-                for (int round = 0; round < 96; ++round) {
+                for (int round = 0; round < 64; ++round) {
                     if (!(hi - lo > 2.220446049250313e-16 * (tnorm + fabs(lo) + fabs(hi)))) break;
-                    const double sig = lo + (hi - lo) * (double)(t + 1) / (double)(tpe + 1);
-                    const int c = te_sturm(s_d, s_p, n, sig, pivmin);
-                    double nlo = c <= kk ? sig : -HUGE_VAL;
-                    double nhi = c > kk ? sig : HUGE_VAL;
+                    double sig[TE_NC];
+                    int cnt[TE_NC];
+#pragma unroll
+                    for (int c = 0; c < TE_NC; ++c) sig[c] = lo + (hi - lo) * (double)(t * TE_NC + c + 1) / npts1;
+                    te_sturm(s_d, s_p, n, sig, cnt);
+                    double nlo = -HUGE_VAL, nhi = HUGE_VAL;
+#pragma unroll
+                    for (int c = 0; c < TE_NC; ++c) {
+                        if (cnt[c] <= kk) nlo = fmax(nlo, sig[c]);
+                        else nhi = fmin(nhi, sig[c]);
+                    }
                     for (int o = 1; o < tpe; o <<= 1) {
                         nlo = fmax(nlo, __shfl_xor(nlo, o));
                         nhi = fmin(nhi, __shfl_xor(nhi, o));
@@ -354,64 +467,81 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
     __syncthreads();
 
     // ---- 3. inverse iteration, one thread per eigenvector ----------------
-    const double tiny = 2.220446049250313e-16 * tnorm;
-    for (int r = tid; r < R; r += TE_T) {
-        const double lm = s_lam[r];
-        double nrm2 = 0.0;
-        for (int i = 0; i < n; ++i) {
-            const double b = te_start(r, i);
-            Z[(int64_t)i * R + r] = b;
-            nrm2 += b * b;
-        }
-        for (int s = 0; s < 2; ++s) {
-            const double inv = 1.0 / sqrt(nrm2);
-            double cd = s_d[0] - lm, cu = n > 1 ? s_e[0] : 0.0, cb = Z[r] * inv;
-            for (int i = 0; i + 1 < n; ++i) {
-                const double sub = s_e[i], nd = s_d[i + 1] - lm, nu = i + 2 < n ? s_e[i + 1] : 0.0;
-                const double nb = Z[(int64_t)(i + 1) * R + r] * inv;
-                double u0, u1, u2, y;
-                if (fabs(cd) >= fabs(sub)) {
-                    if (cd == 0.0) cd = tiny;
-                    const double ml = sub / cd;
-                    u0 = cd;
-                    u1 = cu;
-                    u2 = 0.0;
-                    y = cb;
-                    cd = nd - ml * cu;
-                    cu = nu;
-                    cb = nb - ml * cb;
-                } else {
-                    const double ml = cd / sub;
-                    u0 = sub;
-                    u1 = nd;
-                    u2 = nu;
-                    y = nb;
-                    cd = cu - ml * nd;
-                    cu = -ml * nu;
-                    cb = cb - ml * nb;
-                }
-                sc.F[(int64_t)(3 * i) * R + r] = 1.0 / u0;
-                sc.F[(int64_t)(3 * i + 1) * R + r] = u1;
-                sc.F[(int64_t)(3 * i + 2) * R + r] = u2;
-                Z[(int64_t)i * R + r] = y;
+    {
+        const double tiny = 2.220446049250313e-16 * tnorm;
+        double *__restrict__ F = sc.F;
+        double *__restrict__ Zr = Z;
+        for (int r = tid; r < R; r += TE_T) {
+            const double lm = s_lam[r];
+            double nrm2 = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double b = te_start(r, i);
+                Zr[(int64_t)i * R + r] = b;
+                nrm2 += b * b;
             }
-            if (cd == 0.0) cd = tiny;
-            double x1 = cb / cd, x2 = 0.0;
-            Z[(int64_t)(n - 1) * R + r] = x1;
-            nrm2 = x1 * x1;
+            for (int pass = 0; pass < 2; ++pass) {
+                const double inv = te_rcp(sqrt(nrm2));
+                // forward elimination with partial pivoting: U rows (1 / u0, u1, u2) to F, y to Z
+                double cd = s_d[0] - lm, cu = n > 1 ? s_e[0] : 0.0, cb = Zr[r] * inv;
 #pragma unroll 4
-            for (int i = n - 2; i >= 0; --i) {
-                const double x = (Z[(int64_t)i * R + r] - sc.F[(int64_t)(3 * i + 1) * R + r] * x1 -
-                                  sc.F[(int64_t)(3 * i + 2) * R + r] * x2) *
-                                 sc.F[(int64_t)(3 * i) * R + r];
-                Z[(int64_t)i * R + r] = x;
-                nrm2 += x * x;
-                x2 = x1;
-                x1 = x;
+                for (int i = 0; i + 1 < n; ++i) {
+                    const double sub = s_e[i], nd = s_d[i + 1] - lm, nu = i + 2 < n ? s_e[i + 1] : 0.0;
+                    const double nb = Zr[(int64_t)(i + 1) * R + r] * inv;
+                    double ru0, u1, u2, y;
+                    if (fabs(cd) >= fabs(sub)) {
+                        if (cd == 0.0) cd = tiny;
+                        ru0 = te_rcp(cd);
+                        const double ml = sub * ru0;
+                        u1 = cu;
+                        u2 = 0.0;
+                        y = cb;
+                        cd = nd - ml * cu;
+                        cu = nu;
+                        cb = nb - ml * cb;
+                    } else {
+                        ru0 = te_rcp(sub);
+                        const double ml = cd * ru0;
+                        u1 = nd;
+                        u2 = nu;
+                        y = nb;
+                        cd = cu - ml * nd;
+                        cu = -ml * nu;
+                        cb = cb - ml * nb;
+                    }
+                    F[(int64_t)(3 * i) * R + r] = ru0;
+                    F[(int64_t)(3 * i + 1) * R + r] = u1;
+                    F[(int64_t)(3 * i + 2) * R + r] = u2;
+                    Zr[(int64_t)i * R + r] = y;
+                }
+                if (cd == 0.0) cd = tiny;
+                // back substitution, the factors of 4 rows loaded ahead
+                double x1 = cb * te_rcp(cd), x2 = 0.0;
+                Zr[(int64_t)(n - 1) * R + r] = x1;
+                nrm2 = x1 * x1;
+                for (int i0 = n - 2; i0 >= 0; i0 -= 4) {
+                    double f0[4], f1[4], f2[4], y[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int i = i0 - u >= 0 ? i0 - u : 0;
+                        f0[u] = F[(int64_t)(3 * i) * R + r];
+                        f1[u] = F[(int64_t)(3 * i + 1) * R + r];
+                        f2[u] = F[(int64_t)(3 * i + 2) * R + r];
+                        y[u] = Zr[(int64_t)i * R + r];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        if (i0 - u < 0) break;
+                        const double x = (y[u] - f1[u] * x1 - f2[u] * x2) * f0[u];
+                        Zr[(int64_t)(i0 - u) * R + r] = x;
+                        nrm2 += x * x;
+                        x2 = x1;
+                        x1 = x;
+                    }
+                }
             }
+            const double inv = te_rcp(sqrt(nrm2));
+            for (int i = 0; i < n; ++i) Zr[(int64_t)i * R + r] *= inv;
         }
-        const double inv = 1.0 / sqrt(nrm2);
-        for (int i = 0; i < n; ++i) Z[(int64_t)i * R + r] *= inv;
     }
     __syncthreads();
 
@@ -507,32 +637,100 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
 
     // ---- 5. back-transformation ------------------------------------------
     // Each wave owns the rows i = wave (mod 8) of Z, so the only exchange is
-    // the partial dot products, double-buffered by the parity of the applied
-    // reflectors (skipped identity reflectors do not flip it).
-    for (int rc = 0; rc < R; rc += 64) {
-        const int r = rc + lane;
-        const bool rv = r < R;
-        int par = 0;
-        for (int k = n - 3; k >= 0; --k) {
-            const double tau = s_tau[k];
-            if (tau == 0.0) continue;   // uniform
-            const int i0 = k + 1 + (((wave - k - 1) % TE_W) + TE_W) % TE_W;
-            const double *v = Vr + (int64_t)n * k;
-            double s = 0.0;
-            if (rv)
-                for (int i = i0; i < n; i += TE_W) s += v[i] * Z[(int64_t)i * R + r];
-            double *pb = part + par * (TE_W * 64);
-            par ^= 1;
-            pb[wave * 64 + lane] = s;
-            __syncthreads();
-            double c = 0.0;
+    // the partial dot products (double-buffered).  With the reflectors in
+    // LDS (vkeep) they are read in place.  Otherwise the reflectors of the
+    // applied steps k_0 > k_1 > ... (tau != 0) are staged from the scratch
+    // into three LDS buffers two steps ahead: step t issues the loads of
+    // v_{k_{t+2}} right after its barrier and stores them after its update
+    // (so their latency overlaps the update and the next step's dot products;
+    // a barrier waits for every load in flight), the barrier of step t + 1
+    // orders the stores before their use, and the buffer they overwrite was
+    // last read in step t - 1, which every wave finished before the barrier
+    // of step t.
+    {
+        double *const s_vb = s_v;   // 3 n doubles (the vectors of step 1 are dead)
+        auto next_k = [&](int k) {
+            while (k >= 0 && s_tau[k] == 0.0) --k;
+            return k;
+        };
+        const int nper = (n + TE_T - 1) / TE_T;   // staged entries per thread (n <= 4 * TE_T)
+        for (int rc = 0; rc < R; rc += 64) {
+            const int r = rc + lane;
+            const bool rv = r < R;
+            int kc = next_k(n - 3);
+            int kn = kc >= 0 ? next_k(kc - 1) : -1;
+            int kf = kn >= 0 ? next_k(kn - 1) : -1;   // staged two steps ahead
+            if (!vkeep) {
+                if (kc >= 0)
+                    for (int i = kc + 1 + tid; i < n; i += TE_T) s_vb[i] = Vr[i + (int64_t)n * kc];
+                if (kn >= 0)
+                    for (int i = kn + 1 + tid; i < n; i += TE_T) s_vb[n + i] = Vr[i + (int64_t)n * kn];
+                __syncthreads();
+            }
+            int buf = 0, par = 0;
+            while (kc >= 0) {
+                const double *v = vkeep ? Vr + (int64_t)n * kc : s_vb + buf * n;
+                const double tau = s_tau[kc];
+                const int i0 = kc + 1 + (((wave - kc - 1) % TE_W) + TE_W) % TE_W;
+                // rows i0, i0 + 8, ... in batches of 4 whose loads are issued
+                // together (indices clamped; the extra terms are multiplied by 0)
+                double sacc = 0.0;
+                if (rv)
+                    for (int i = i0; i < n; i += 4 * TE_W) {
+                        double vv[4], zz[4];
 #pragma unroll
-            for (int w = 0; w < TE_W; ++w) c += pb[w * 64 + lane];
-            c *= tau;
-            if (rv)
-                for (int i = i0; i < n; i += TE_W) Z[(int64_t)i * R + r] -= c * v[i];
+                        for (int u = 0; u < 4; ++u) {
+                            const int ii = i + u * TE_W, ic = ii < n ? ii : n - 1;
+                            vv[u] = ii < n ? v[ic] : 0.0;
+                            zz[u] = Z[(int64_t)ic * R + r];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) sacc += vv[u] * zz[u];
+                    }
+                double *pb = part + par * (TE_W * 64);
+                pb[wave * 64 + lane] = sacc;
+                __syncthreads();
+                double pre[4];
+                if (!vkeep && kf >= 0) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = tid + q * TE_T;
+                        pre[q] = (q < nper && i > kf && i < n) ? Vr[i + (int64_t)n * kf] : 0.0;
+                    }
+                }
+                double c = 0.0;
+#pragma unroll
+                for (int w = 0; w < TE_W; ++w) c += pb[w * 64 + lane];
+                c *= tau;
+                if (rv)
+                    for (int i = i0; i < n; i += 4 * TE_W) {
+                        double vv[4], zz[4];
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) {
+                            const int ii = i + u * TE_W, ic = ii < n ? ii : n - 1;
+                            vv[u] = v[ic];
+                            zz[u] = Z[(int64_t)ic * R + r];
+                        }
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (i + u * TE_W < n) Z[(int64_t)(i + u * TE_W) * R + r] = zz[u] - c * vv[u];
+                    }
+                if (!vkeep && kf >= 0) {
+                    double *vf = s_vb + ((buf + 2) % 3) * n;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int i = tid + q * TE_T;
+                        if (q < nper && i > kf && i < n) vf[i] = pre[q];
+                    }
+                }
+                kc = kn;
+                kn = kf;
+                kf = kf >= 0 ? next_k(kf - 1) : -1;
+                buf = (buf + 1) % 3;
+                par ^= 1;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 
     // ---- 6. sign rule and output -----------------------------------------
