@@ -13,8 +13,8 @@
 //      The count of eigenvalues below sigma is the number of sign changes in
 //      the leading principal minors p_i of T - sigma I, taken with the
 //      three-term recurrence p_i = (d_i - sigma) p_{i-1} - e_{i-1}^2 p_{i-2}
-//      (no division; the pair is rescaled by a power of two when it leaves
-//      [2^-100, 2^100], which keeps every sign).  e^2 is floored at
+//      (no division; every 8 steps the pair is rescaled by a power of two,
+//      which keeps every sign).  e^2 is floored at
 //      (2^-60 ||T||)^2, so a vanishing minor is never followed by another
 //      and counts as positive (the LDL^T count with a negative-zero pivot).
 //      Each eigenvalue is searched by a group of
@@ -144,43 +144,58 @@ __device__ __forceinline__ double te_rcp(double x) {
 
 // Numbers of eigenvalues of the tridiagonal (d, e2 = e^2) below sig[c],
 // TE_NC independent counts interleaved: the sign changes of the leading
-// principal minors p_i of T - sigma I (a zero minor counts as positive; the
-// caller floors e^2 at a tiny positive value, so that a zero minor is never
-// followed by another and the count equals the LDL^T count of T - sigma I
-// with a negative-zero pivot).  The pair (p_{i-1}, p_i) of each count is
-// rescaled by a power of two every 4 steps: between checks the larger of the
-// pair grows by at most (|d - sigma| + e^2)^4 and shrinks by at most
-// (e^2 floor)^2, which the window [2^-100, 2^100] keeps within the normal range.
+// principal minors p_i of T - sigma I.  A zero minor counts as positive (the
+// LDL^T count with a negative-zero pivot): adding +0 turns -0 into +0, and
+// the caller floors e^2 at a tiny positive value so that a zero minor is
+// never followed by another.  Every 8 steps the pair (p_{i-1}, p_i) of each
+// count is multiplied by the power of two that brings the exponent of the
+// larger one to zero (exact, signs kept): the entries of T are at most
+// 2 n <= 2^10 after scaling, so the larger one grows by less than 2^22 per step
+// and shrinks by less than the e^2 floor (2^-120 ||T||^2) per two steps,
+// which keeps every value normal between normalizations.
 constexpr int TE_NC = 4;
+__device__ __forceinline__ double te_pow2_inv(double m) {
+    // 2^-e with e the unbiased exponent of the normal number m > 0
+    const int e = (__double2hiint(m) >> 20) & 0x7ff;
+    return __hiloint2double((2046 - e) << 20, 0);
+}
 __device__ __forceinline__ void te_sturm(const double *__restrict__ d, const double *__restrict__ e2, int n,
                                          const double (&sig)[TE_NC], int (&cnt)[TE_NC]) {
     double p0[TE_NC], p1[TE_NC];
 #pragma unroll
     for (int c = 0; c < TE_NC; ++c) {
         p0[c] = 1.0;
-        p1[c] = d[0] - sig[c];
-        cnt[c] = p1[c] < 0.0;
+        p1[c] = (d[0] - sig[c]) + 0.0;
+        cnt[c] = (int)((unsigned)__double2hiint(p1[c]) >> 31);
     }
-#pragma unroll 4
-    for (int i = 1; i < n; ++i) {
+    int i = 1;
+    for (; i + 8 <= n; i += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double di = d[i + u], ei = e2[i + u - 1];
+#pragma unroll
+            for (int c = 0; c < TE_NC; ++c) {
+                const double p2 = fma(di - sig[c], p1[c], -ei * p0[c]) + 0.0;
+                cnt[c] += (int)((unsigned)(__double2hiint(p2) ^ __double2hiint(p1[c])) >> 31);
+                p0[c] = p1[c];
+                p1[c] = p2;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < TE_NC; ++c) {
+            const double sc = te_pow2_inv(fmax(fabs(p0[c]), fabs(p1[c])));
+            p0[c] *= sc;
+            p1[c] *= sc;
+        }
+    }
+    for (; i < n; ++i) {
         const double di = d[i], ei = e2[i - 1];
 #pragma unroll
         for (int c = 0; c < TE_NC; ++c) {
-            const double p2 = fma(di - sig[c], p1[c], -ei * p0[c]);
-            cnt[c] += (p2 < 0.0) != (p1[c] < 0.0);
+            const double p2 = fma(di - sig[c], p1[c], -ei * p0[c]) + 0.0;
+            cnt[c] += (int)((unsigned)(__double2hiint(p2) ^ __double2hiint(p1[c])) >> 31);
             p0[c] = p1[c];
             p1[c] = p2;
-        }
-        if ((i & 3) == 0) {
-#pragma unroll
-            for (int c = 0; c < TE_NC; ++c) {
-                const double m = fmax(fabs(p0[c]), fabs(p1[c]));
-                if (m > 0x1p100 || m < 0x1p-100) {
-                    const int ex = ilogb(m);
-                    p0[c] = ldexp(p0[c], -ex);
-                    p1[c] = ldexp(p1[c], -ex);
-                }
-            }
         }
     }
 }
@@ -254,142 +269,348 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
     }
     const int sexp = (mx > 0.0 && !nonfinite) ? ilogb(mx) : 0;
     const double sc_in = ldexp(1.0, -sexp), sc_out = ldexp(1.0, sexp);
-    for (int64_t e = tid; e < nn; e += TE_T) {
-        const int i = (int)(e % n), j = (int)(e / n);
-        A[e] = 0.5 * (S[i + lds * j] + S[j + lds * i]) * sc_in;
+    if (!ALDS) {
+        for (int64_t e = tid; e < nn; e += TE_T) {
+            const int i = (int)(e % n), j = (int)(e / n);
+            A[e] = 0.5 * (S[i + lds * j] + S[j + lds * i]) * sc_in;
+        }
+        __syncthreads();
     }
-    __syncthreads();
 
     // ---- 1. tridiagonalization -------------------------------------------
-    // Per step k two barriers: wave 0 first turns the partial sums of step
-    // k - 1 into p = tau A v and K = (tau / 2) p^T v, forms (v, w) of step
-    // k - 1, updates column k and builds H_k; then every wave applies step
-    // k - 1's update to the trailing block and accumulates A v_k.
-    constexpr int TU = 4;   // columns per thread whose loads are issued together
-    double Kprev = 0.0;
-    for (int k = 0; k + 2 < n; ++k) {
-        double *const vc = s_v + (k & 1) * n;
-        const double *const vp = s_v + ((k & 1) ^ 1) * n;
-        if (wave == 0) {
-            if (k > 0) {
-                const double taup = s_tau[k - 1];
-                double t = 0.0;
-                for (int i = k + lane; i < n; i += 64) {
-                    double sp = 0.0;
+    if constexpr (ALDS) {
+        // A in registers: thread (wave w, lane l) holds rows l and l + 64 of
+        // the columns w + 8 q, q < 16.  Step k: the wave owning column k turns
+        // the partial sums of step k - 1 into p and K, publishes (v, w) of step
+        // k - 1, applies that step's update to column k and builds H_k
+        // (v_k goes to column k of the LDS matrix area); after a barrier every
+        // wave applies step k - 1's update to its columns j > k and
+        // accumulates A v_k, the column operands taken from LDS once per wave
+        // and broadcast with readlane.  Only vectors cross LDS.
+        constexpr int NQ = TE_LDS_N / TE_W;   // 16
+        double ar[2][NQ];
 #pragma unroll
-                    for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
-                    const double p = taup * sp;
-                    s_p[i] = p;
-                    t += p * vp[i];
-                }
-                Kprev = 0.5 * taup * te_wave_sum(t);
+        for (int h = 0; h < 2; ++h) {
+            // all 32 pairs of loads issued before any use (indices clamped)
+            double x[NQ], y[NQ];
+            const int i = lane + 64 * h, ic = i < n ? i : n - 1;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int j = wave + TE_W * q, jc = j < n ? j : n - 1;
+                x[q] = S[ic + lds * jc];
+                y[q] = S[jc + lds * ic];
             }
-            // (v, w) of step k - 1 for rows >= k, column k with that step's
-            // pending update, then H_k
-            double sig = 0.0, a0 = 0.0;
-            double wpk = 0.0, vpk = 0.0;
-            if (k > 0) {
-                vpk = vp[k];
-                wpk = s_p[k] - Kprev * vpk;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int j = wave + TE_W * q;
+                ar[h][q] = (i < n && j < n) ? 0.5 * (x[q] + y[q]) * sc_in : 0.0;
             }
-            for (int i = k + lane; i < n; i += 64) {
-                double a = A[i + (int64_t)n * k];
+        }
+        for (int i = tid; i < 2 * n; i += TE_T) s_v[i] = 0.0;
+        for (int i = tid; i < n; i += TE_T) s_vw[i] = make_double2(0.0, 0.0);
+        __syncthreads();
+        double Kprev = 0.0;
+        for (int k = 0; k + 2 < n; ++k) {
+            double *const vc = s_v + (k & 1) * n;
+            const double *const vp = s_v + ((k & 1) ^ 1) * n;
+            if (wave == k % TE_W) {
+                const int qk = k / TE_W;
+                double pr[2] = {0.0, 0.0}, vpr[2] = {0.0, 0.0}, wr[2] = {0.0, 0.0};
                 if (k > 0) {
-                    const double vpi = vp[i], wpi = s_p[i] - Kprev * vpi;
-                    s_vw[i] = make_double2(vpi, wpi);
-                    a -= vpi * wpk + wpi * vpk;
-                }
-                if (i >= k + 2) sig += a * a;
-                if (i == k + lane && lane < 2) a0 = a;
-                part[i] = a;
-            }
-            sig = te_wave_sum(sig);
-            const double akk = te_lane(a0, 0), x0 = te_lane(a0, 1);
-            double beta = x0, tau = 0.0, scl = 0.0;
-            if (sig > 0.0) {
-                const double nrm = sqrt(x0 * x0 + sig);
-                beta = x0 >= 0.0 ? -nrm : nrm;
-                tau = (beta - x0) / beta;
-                scl = 1.0 / (x0 - beta);
-            }
-            for (int i = k + 1 + lane; i < n; i += 64) {
-                const double v = (i == k + 1) ? 1.0 : (tau == 0.0 ? 0.0 : part[i] * scl);
-                vc[i] = v;
-                A[i + (int64_t)n * k] = v;   // column k is not read again by the reduction
-            }
-            if (lane == 0) {
-                s_d[k] = akk;
-                s_e[k] = beta;
-                s_tau[k] = tau;
-            }
-        }
-        __syncthreads();
-        // trailing block: pending update of step k - 1, and partial sums of A v_k
-        for (int i0 = k + 1; i0 < n; i0 += 64) {
-            const int i = i0 + lane;
-            if (i < n) {
-                double acc = 0.0;
-                double2 pwi = make_double2(0.0, 0.0);
-                if (k > 0) pwi = s_vw[i];
-                for (int jb = k + 1 + wave; jb < n; jb += TE_W * TU) {
-                    double a[TU], vcj[TU];
-                    double2 pw[TU];
+                    const double taup = s_tau[k - 1];
+                    double t = 0.0;
 #pragma unroll
-                    for (int u = 0; u < TU; ++u) {
-                        const int j = jb + TE_W * u;
-                        const int jc = j < n ? j : n - 1;
-                        a[u] = A[i + (int64_t)n * jc];
-                        vcj[u] = j < n ? vc[jc] : 0.0;
-                        pw[u] = (k > 0) ? s_vw[jc] : make_double2(0.0, 0.0);
-                    }
+                    for (int h = 0; h < 2; ++h) {
+                        const int i = lane + 64 * h;
+                        if (i >= k && i < n) {
+                            double sp = 0.0;
 #pragma unroll
-                    for (int u = 0; u < TU; ++u) {
-                        const int j = jb + TE_W * u;
-                        if (k > 0) {
-                            a[u] -= pwi.x * pw[u].y + pwi.y * pw[u].x;
-                            if (j < n) A[i + (int64_t)n * j] = a[u];
+                            for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
+                            pr[h] = taup * sp;
+                            vpr[h] = vp[i];
+                            t += pr[h] * vpr[h];
                         }
-                        acc += a[u] * vcj[u];
+                    }
+                    Kprev = 0.5 * taup * te_wave_sum(t);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        const int i = lane + 64 * h;
+                        wr[h] = pr[h] - Kprev * vpr[h];
+                        if (i >= k && i < n) s_vw[i] = make_double2(vpr[h], wr[h]);
                     }
                 }
-                part[wave * n + i] = acc;
+                const int hk = k >> 6, lk = k & 63;
+                const double vpk = te_lane(hk ? vpr[1] : vpr[0], lk);
+                const double wpk = te_lane(hk ? wr[1] : wr[0], lk);
+                double col[2];
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    double c = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (q == qk) c = ar[h][q];
+                    col[h] = c - (vpr[h] * wpk + wr[h] * vpk);
+                }
+                double sig = 0.0;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = lane + 64 * h;
+                    if (i >= k + 2 && i < n) sig += col[h] * col[h];
+                }
+                sig = te_wave_sum(sig);
+                const double akk = te_lane(hk ? col[1] : col[0], lk);
+                const int h1 = (k + 1) >> 6, l1 = (k + 1) & 63;
+                const double x0 = te_lane(h1 ? col[1] : col[0], l1);
+                double beta = x0, tau = 0.0, scl = 0.0;
+                if (sig > 0.0) {
+                    const double nrm = sqrt(x0 * x0 + sig);
+                    beta = x0 >= 0.0 ? -nrm : nrm;
+                    tau = (beta - x0) / beta;
+                    scl = 1.0 / (x0 - beta);
+                }
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = lane + 64 * h;
+                    if (i >= k + 1 && i < n) {
+                        const double v = (i == k + 1) ? 1.0 : (tau == 0.0 ? 0.0 : col[h] * scl);
+                        vc[i] = v;
+                        A[i + (int64_t)n * k] = v;
+                    }
+                }
+                if (lane == 0) {
+                    s_d[k] = akk;
+                    s_e[k] = beta;
+                    s_tau[k] = tau;
+                }
+            }
+            __syncthreads();
+            // column operands of this wave's columns (lane q < 16 loads column
+            // wave + 8 q), row operands of this thread's rows
+            double2 cvw = make_double2(0.0, 0.0);
+            double cvc = 0.0;
+            if (lane < NQ) {
+                const int j = wave + TE_W * lane;
+                if (j < n) {
+                    cvw = s_vw[j];
+                    cvc = vc[j];
+                }
+            }
+            double2 rvw[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = lane + 64 * h;
+                rvw[h] = i < n ? s_vw[i] : make_double2(0.0, 0.0);
+            }
+            double acc[2] = {0.0, 0.0};
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int j = wave + TE_W * q;
+                if (j >= k + 1 && j < n) {   // uniform within the wave
+                    const double vpj = te_lane(cvw.x, q), wj = te_lane(cvw.y, q), vcj = te_lane(cvc, q);
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        double a = ar[h][q];
+                        if (k > 0) {
+                            a -= rvw[h].x * wj + rvw[h].y * vpj;
+                            ar[h][q] = a;
+                        }
+                        acc[h] += a * vcj;
+                    }
+                }
+            }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = lane + 64 * h;
+                if (i < n) part[wave * n + i] = acc[h];
+            }
+            __syncthreads();
+        }
+        // the last 2 x 2 block (or the whole matrix when n <= 2): raw entries
+        // from their owners, p and K of step n - 3 from the partial sums
+        double *const s_fin = s_red2;   // 6 doubles
+        if (n >= 2) {
+            const int c0 = n - 2, c1 = n - 1;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int i = lane + 64 * h;
+                double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    if (q == c0 / TE_W) a0 = ar[h][q];
+                    if (q == c1 / TE_W) a1 = ar[h][q];
+                }
+                if (wave == c0 % TE_W && i == n - 2) s_fin[0] = a0;
+                if (wave == c0 % TE_W && i == n - 1) s_fin[1] = a0;
+                if (wave == c1 % TE_W && i == n - 1) s_fin[2] = a1;
+            }
+        } else if (tid == 0) {
+            s_fin[0] = ar[0][0];
+        }
+        if (n >= 3 && wave == 0) {
+            const double taup = s_tau[n - 3];
+            const double *vq = s_v + ((n - 3) & 1) * n;
+            double t = 0.0, pl = 0.0;
+            const int i = n - 2 + lane;
+            if (lane < 2) {
+                double sp = 0.0;
+#pragma unroll
+                for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
+                pl = taup * sp;
+                t = pl * vq[i];
+            }
+            const double K = 0.5 * taup * te_wave_sum(t);
+            if (lane < 2) s_fin[3 + lane] = pl;
+            if (lane == 0) s_fin[5] = K;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            if (n >= 3) {
+                const double *v = s_v + ((n - 3) & 1) * n;
+                const double v1 = v[n - 2], v2 = v[n - 1], K = s_fin[5];
+                const double w1 = s_fin[3] - K * v1, w2 = s_fin[4] - K * v2;
+                s_d[n - 2] = s_fin[0] - 2.0 * v1 * w1;
+                s_e[n - 2] = s_fin[1] - (v2 * w1 + w2 * v1);
+                s_d[n - 1] = s_fin[2] - 2.0 * v2 * w2;
+            } else if (n == 2) {
+                s_d[0] = s_fin[0];
+                s_e[0] = s_fin[1];
+                s_d[1] = s_fin[2];
+            } else {
+                s_d[0] = s_fin[0];
+            }
+        }
+        __syncthreads();
+    } else {
+        // Per step k two barriers: wave 0 first turns the partial sums of step
+        // k - 1 into p = tau A v and K = (tau / 2) p^T v, forms (v, w) of step
+        // k - 1, updates column k and builds H_k; then every wave applies step
+        // k - 1's update to the trailing block and accumulates A v_k.
+        constexpr int TU = 4;   // columns per thread whose loads are issued together
+        double Kprev = 0.0;
+        for (int k = 0; k + 2 < n; ++k) {
+            double *const vc = s_v + (k & 1) * n;
+            const double *const vp = s_v + ((k & 1) ^ 1) * n;
+            if (wave == 0) {
+                if (k > 0) {
+                    const double taup = s_tau[k - 1];
+                    double t = 0.0;
+                    for (int i = k + lane; i < n; i += 64) {
+                        double sp = 0.0;
+#pragma unroll
+                        for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
+                        const double p = taup * sp;
+                        s_p[i] = p;
+                        t += p * vp[i];
+                    }
+                    Kprev = 0.5 * taup * te_wave_sum(t);
+                }
+                // (v, w) of step k - 1 for rows >= k, column k with that step's
+                // pending update, then H_k
+                double sig = 0.0, a0 = 0.0;
+                double wpk = 0.0, vpk = 0.0;
+                if (k > 0) {
+                    vpk = vp[k];
+                    wpk = s_p[k] - Kprev * vpk;
+                }
+                for (int i = k + lane; i < n; i += 64) {
+                    double a = A[i + (int64_t)n * k];
+                    if (k > 0) {
+                        const double vpi = vp[i], wpi = s_p[i] - Kprev * vpi;
+                        s_vw[i] = make_double2(vpi, wpi);
+                        a -= vpi * wpk + wpi * vpk;
+                    }
+                    if (i >= k + 2) sig += a * a;
+                    if (i == k + lane && lane < 2) a0 = a;
+                    part[i] = a;
+                }
+                sig = te_wave_sum(sig);
+                const double akk = te_lane(a0, 0), x0 = te_lane(a0, 1);
+                double beta = x0, tau = 0.0, scl = 0.0;
+                if (sig > 0.0) {
+                    const double nrm = sqrt(x0 * x0 + sig);
+                    beta = x0 >= 0.0 ? -nrm : nrm;
+                    tau = (beta - x0) / beta;
+                    scl = 1.0 / (x0 - beta);
+                }
+                for (int i = k + 1 + lane; i < n; i += 64) {
+                    const double v = (i == k + 1) ? 1.0 : (tau == 0.0 ? 0.0 : part[i] * scl);
+                    vc[i] = v;
+                    A[i + (int64_t)n * k] = v;   // column k is not read again by the reduction
+                }
+                if (lane == 0) {
+                    s_d[k] = akk;
+                    s_e[k] = beta;
+                    s_tau[k] = tau;
+                }
+            }
+            __syncthreads();
+            // trailing block: pending update of step k - 1, and partial sums of A v_k
+            for (int i0 = k + 1; i0 < n; i0 += 64) {
+                const int i = i0 + lane;
+                if (i < n) {
+                    double acc = 0.0;
+                    double2 pwi = make_double2(0.0, 0.0);
+                    if (k > 0) pwi = s_vw[i];
+                    for (int jb = k + 1 + wave; jb < n; jb += TE_W * TU) {
+                        double a[TU], vcj[TU];
+                        double2 pw[TU];
+#pragma unroll
+                        for (int u = 0; u < TU; ++u) {
+                            const int j = jb + TE_W * u;
+                            const int jc = j < n ? j : n - 1;
+                            a[u] = A[i + (int64_t)n * jc];
+                            vcj[u] = j < n ? vc[jc] : 0.0;
+                            pw[u] = (k > 0) ? s_vw[jc] : make_double2(0.0, 0.0);
+                        }
+#pragma unroll
+                        for (int u = 0; u < TU; ++u) {
+                            const int j = jb + TE_W * u;
+                            if (k > 0) {
+                                a[u] -= pwi.x * pw[u].y + pwi.y * pw[u].x;
+                                if (j < n) A[i + (int64_t)n * j] = a[u];
+                            }
+                            acc += a[u] * vcj[u];
+                        }
+                    }
+                    part[wave * n + i] = acc;
+                }
+            }
+            __syncthreads();
+        }
+        if (n >= 3 && wave == 0) {
+            // p and K of the last step (n - 3)
+            const double taup = s_tau[n - 3];
+            const double *vp = s_v + ((n - 3) & 1) * n;
+            double t = 0.0;
+            for (int i = n - 2 + lane; i < n; i += 64) {
+                double sp = 0.0;
+#pragma unroll
+                for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
+                const double p = taup * sp;
+                s_p[i] = p;
+                t += p * vp[i];
+            }
+            Kprev = 0.5 * taup * te_wave_sum(t);
+        }
+        if (tid == 0) {
+            if (n >= 3) {
+                // the last 2 x 2 block with the update of step n - 3
+                const double *v = s_v + ((n - 3) & 1) * n;
+                const double v1 = v[n - 2], v2 = v[n - 1];
+                const double w1 = s_p[n - 2] - Kprev * v1, w2 = s_p[n - 1] - Kprev * v2;
+                s_d[n - 2] = A[(n - 2) + (int64_t)n * (n - 2)] - 2.0 * v1 * w1;
+                s_e[n - 2] = A[(n - 1) + (int64_t)n * (n - 2)] - (v2 * w1 + w2 * v1);
+                s_d[n - 1] = A[(n - 1) + (int64_t)n * (n - 1)] - 2.0 * v2 * w2;
+            } else if (n == 2) {
+                s_d[0] = A[0];
+                s_e[0] = A[1];
+                s_d[1] = A[3];
+            } else {
+                s_d[0] = A[0];
             }
         }
         __syncthreads();
     }
-    if (n >= 3 && wave == 0) {
-        // p and K of the last step (n - 3)
-        const double taup = s_tau[n - 3];
-        const double *vp = s_v + ((n - 3) & 1) * n;
-        double t = 0.0;
-        for (int i = n - 2 + lane; i < n; i += 64) {
-            double sp = 0.0;
-#pragma unroll
-            for (int w = 0; w < TE_W; ++w) sp += part[w * n + i];
-            const double p = taup * sp;
-            s_p[i] = p;
-            t += p * vp[i];
-        }
-        Kprev = 0.5 * taup * te_wave_sum(t);
-    }
-    if (tid == 0) {
-        if (n >= 3) {
-            // the last 2 x 2 block with the update of step n - 3
-            const double *v = s_v + ((n - 3) & 1) * n;
-            const double v1 = v[n - 2], v2 = v[n - 1];
-            const double w1 = s_p[n - 2] - Kprev * v1, w2 = s_p[n - 1] - Kprev * v2;
-            s_d[n - 2] = A[(n - 2) + (int64_t)n * (n - 2)] - 2.0 * v1 * w1;
-            s_e[n - 2] = A[(n - 1) + (int64_t)n * (n - 2)] - (v2 * w1 + w2 * v1);
-            s_d[n - 1] = A[(n - 1) + (int64_t)n * (n - 1)] - 2.0 * v2 * w2;
-        } else if (n == 2) {
-            s_d[0] = A[0];
-            s_e[0] = A[1];
-            s_d[1] = A[3];
-        } else {
-            s_d[0] = A[0];
-        }
-    }
-    __syncthreads();
 
     if (ALDS && !vkeep)
         for (int64_t e = tid; e < nn; e += TE_T) sc.Vr[e] = A[e];
@@ -636,100 +857,155 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
     }
 
     // ---- 5. back-transformation ------------------------------------------
-    // Each wave owns the rows i = wave (mod 8) of Z, so the only exchange is
-    // the partial dot products (double-buffered).  With the reflectors in
-    // LDS (vkeep) they are read in place.  Otherwise the reflectors of the
-    // applied steps k_0 > k_1 > ... (tau != 0) are staged from the scratch
-    // into three LDS buffers two steps ahead: step t issues the loads of
-    // v_{k_{t+2}} right after its barrier and stores them after its update
-    // (so their latency overlaps the update and the next step's dot products;
-    // a barrier waits for every load in flight), the barrier of step t + 1
-    // orders the stores before their use, and the buffer they overwrite was
-    // last read in step t - 1, which every wave finished before the barrier
-    // of step t.
-    {
-        double *const s_vb = s_v;   // 3 n doubles (the vectors of step 1 are dead)
+    if constexpr (ALDS) {
+        // Z in registers: lane r (of each 64-column chunk) of wave w holds
+        // rows w + 8 q, q < 16, of column r.  Per applied reflector: lanes
+        // q < 16 load v(w + 8 q) (LDS, or the scratch with the load issued a
+        // step ahead), readlane broadcasts them, the partial dot products are
+        // summed over the waves in LDS (double-buffered, one barrier per step).
+        constexpr int NQ = TE_LDS_N / TE_W;
         auto next_k = [&](int k) {
             while (k >= 0 && s_tau[k] == 0.0) --k;
             return k;
         };
-        const int nper = (n + TE_T - 1) / TE_T;   // staged entries per thread (n <= 4 * TE_T)
+        auto vload = [&](int k) -> double {
+            const int i = wave + TE_W * lane;
+            return (k >= 0 && lane < NQ && i > k && i < n) ? Vr[i + (int64_t)n * k] : 0.0;
+        };
         for (int rc = 0; rc < R; rc += 64) {
             const int r = rc + lane;
             const bool rv = r < R;
-            int kc = next_k(n - 3);
-            int kn = kc >= 0 ? next_k(kc - 1) : -1;
-            int kf = kn >= 0 ? next_k(kn - 1) : -1;   // staged two steps ahead
-            if (!vkeep) {
-                if (kc >= 0)
-                    for (int i = kc + 1 + tid; i < n; i += TE_T) s_vb[i] = Vr[i + (int64_t)n * kc];
-                if (kn >= 0)
-                    for (int i = kn + 1 + tid; i < n; i += TE_T) s_vb[n + i] = Vr[i + (int64_t)n * kn];
-                __syncthreads();
+            double zr[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = wave + TE_W * q;
+                zr[q] = (rv && i < n) ? Z[(int64_t)i * R + r] : 0.0;
             }
-            int buf = 0, par = 0;
+            int kc = next_k(n - 3);
+            double vl = vload(kc);
+            int par = 0;
             while (kc >= 0) {
-                const double *v = vkeep ? Vr + (int64_t)n * kc : s_vb + buf * n;
-                const double tau = s_tau[kc];
-                const int i0 = kc + 1 + (((wave - kc - 1) % TE_W) + TE_W) % TE_W;
-                // rows i0, i0 + 8, ... in batches of 4 whose loads are issued
-                // together (indices clamped; the extra terms are multiplied by 0)
+                const int kn = next_k(kc - 1);
                 double sacc = 0.0;
-                if (rv)
-                    for (int i = i0; i < n; i += 4 * TE_W) {
-                        double vv[4], zz[4];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int ii = i + u * TE_W, ic = ii < n ? ii : n - 1;
-                            vv[u] = ii < n ? v[ic] : 0.0;
-                            zz[u] = Z[(int64_t)ic * R + r];
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) sacc += vv[u] * zz[u];
-                    }
+                for (int q = 0; q < NQ; ++q) sacc += te_lane(vl, q) * zr[q];
                 double *pb = part + par * (TE_W * 64);
                 pb[wave * 64 + lane] = sacc;
                 __syncthreads();
-                double pre[4];
-                if (!vkeep && kf >= 0) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int i = tid + q * TE_T;
-                        pre[q] = (q < nper && i > kf && i < n) ? Vr[i + (int64_t)n * kf] : 0.0;
-                    }
-                }
+                const double vnext = vload(kn);   // in flight during the update
                 double c = 0.0;
 #pragma unroll
                 for (int w = 0; w < TE_W; ++w) c += pb[w * 64 + lane];
-                c *= tau;
-                if (rv)
-                    for (int i = i0; i < n; i += 4 * TE_W) {
-                        double vv[4], zz[4];
+                c *= s_tau[kc];
 #pragma unroll
-                        for (int u = 0; u < 4; ++u) {
-                            const int ii = i + u * TE_W, ic = ii < n ? ii : n - 1;
-                            vv[u] = v[ic];
-                            zz[u] = Z[(int64_t)ic * R + r];
-                        }
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-                            if (i + u * TE_W < n) Z[(int64_t)(i + u * TE_W) * R + r] = zz[u] - c * vv[u];
-                    }
-                if (!vkeep && kf >= 0) {
-                    double *vf = s_vb + ((buf + 2) % 3) * n;
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const int i = tid + q * TE_T;
-                        if (q < nper && i > kf && i < n) vf[i] = pre[q];
-                    }
-                }
+                for (int q = 0; q < NQ; ++q) zr[q] -= c * te_lane(vl, q);
+                vl = vnext;
                 kc = kn;
-                kn = kf;
-                kf = kf >= 0 ? next_k(kf - 1) : -1;
-                buf = (buf + 1) % 3;
                 par ^= 1;
             }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = wave + TE_W * q;
+                if (rv && i < n) Z[(int64_t)i * R + r] = zr[q];
+            }
             __syncthreads();
+        }
+    } else {
+        // Each wave owns the rows i = wave (mod 8) of Z, so the only exchange is
+        // the partial dot products (double-buffered).  With the reflectors in
+        // LDS (vkeep) they are read in place.  Otherwise the reflectors of the
+        // applied steps k_0 > k_1 > ... (tau != 0) are staged from the scratch
+        // into three LDS buffers two steps ahead: step t issues the loads of
+        // v_{k_{t+2}} right after its barrier and stores them after its update
+        // (so their latency overlaps the update and the next step's dot products;
+        // a barrier waits for every load in flight), the barrier of step t + 1
+        // orders the stores before their use, and the buffer they overwrite was
+        // last read in step t - 1, which every wave finished before the barrier
+        // of step t.
+        {
+            double *const s_vb = s_v;   // 3 n doubles (the vectors of step 1 are dead)
+            auto next_k = [&](int k) {
+                while (k >= 0 && s_tau[k] == 0.0) --k;
+                return k;
+            };
+            const int nper = (n + TE_T - 1) / TE_T;   // staged entries per thread (n <= 4 * TE_T)
+            for (int rc = 0; rc < R; rc += 64) {
+                const int r = rc + lane;
+                const bool rv = r < R;
+                int kc = next_k(n - 3);
+                int kn = kc >= 0 ? next_k(kc - 1) : -1;
+                int kf = kn >= 0 ? next_k(kn - 1) : -1;   // staged two steps ahead
+                if (!vkeep) {
+                    if (kc >= 0)
+                        for (int i = kc + 1 + tid; i < n; i += TE_T) s_vb[i] = Vr[i + (int64_t)n * kc];
+                    if (kn >= 0)
+                        for (int i = kn + 1 + tid; i < n; i += TE_T) s_vb[n + i] = Vr[i + (int64_t)n * kn];
+                    __syncthreads();
+                }
+                int buf = 0, par = 0;
+                while (kc >= 0) {
+                    const double *v = vkeep ? Vr + (int64_t)n * kc : s_vb + buf * n;
+                    const double tau = s_tau[kc];
+                    const int i0 = kc + 1 + (((wave - kc - 1) % TE_W) + TE_W) % TE_W;
+                    // rows i0, i0 + 8, ... in batches of 4 whose loads are issued
+                    // together (indices clamped; the extra terms are multiplied by 0)
+                    double sacc = 0.0;
+                    if (rv)
+                        for (int i = i0; i < n; i += 4 * TE_W) {
+                            double vv[4], zz[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int ii = i + u * TE_W, ic = ii < n ? ii : n - 1;
+                                vv[u] = ii < n ? v[ic] : 0.0;
+                                zz[u] = Z[(int64_t)ic * R + r];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) sacc += vv[u] * zz[u];
+                        }
+                    double *pb = part + par * (TE_W * 64);
+                    pb[wave * 64 + lane] = sacc;
+                    __syncthreads();
+                    double pre[4];
+                    if (!vkeep && kf >= 0) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int i = tid + q * TE_T;
+                            pre[q] = (q < nper && i > kf && i < n) ? Vr[i + (int64_t)n * kf] : 0.0;
+                        }
+                    }
+                    double c = 0.0;
+#pragma unroll
+                    for (int w = 0; w < TE_W; ++w) c += pb[w * 64 + lane];
+                    c *= tau;
+                    if (rv)
+                        for (int i = i0; i < n; i += 4 * TE_W) {
+                            double vv[4], zz[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u) {
+                                const int ii = i + u * TE_W, ic = ii < n ? ii : n - 1;
+                                vv[u] = v[ic];
+                                zz[u] = Z[(int64_t)ic * R + r];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (i + u * TE_W < n) Z[(int64_t)(i + u * TE_W) * R + r] = zz[u] - c * vv[u];
+                        }
+                    if (!vkeep && kf >= 0) {
+                        double *vf = s_vb + ((buf + 2) % 3) * n;
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const int i = tid + q * TE_T;
+                            if (q < nper && i > kf && i < n) vf[i] = pre[q];
+                        }
+                    }
+                    kc = kn;
+                    kn = kf;
+                    kf = kf >= 0 ? next_k(kf - 1) : -1;
+                    buf = (buf + 1) % 3;
+                    par ^= 1;
+                }
+                __syncthreads();
+            }
         }
     }
 
