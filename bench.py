@@ -350,7 +350,7 @@ def bench_ablation(api, torch, Xd, ranks, reps=3):
             I = Y.shape[n]
             Yn = Y.movedim(n, 0).reshape(I, -1)          # copies unless it is a view already
             S = torch.matmul(Yn, Yn.t()).double().t()      # symmetric: the column-major view
-            U, _, _ = api.eig_leading(S, ranks[n])
+            U, _, _ = api.eig_leading(S, ranks[n], s_unit=2.0 ** -24)   # S from FP32 products
             Z = torch.matmul(U.t().float(), Yn)          # R x J_n
             others = [Y.shape[m] for m in range(N) if m != n]
             Y = Z.reshape(ranks[n], *others).movedim(0, n)

@@ -57,8 +57,12 @@ typedef enum {
 typedef enum { STH_F64 = 0, STH_F32 = 1 } sth_dtype;
 
 /* Arithmetic of a contraction (Gram, TTT or TTM).  Products are formed as
- * stated and accumulated in FP32 within a chunk of at most 128 contraction
- * steps, then in FP64 across chunks (FP64: FP64 throughout).
+ * stated.  Gram and TTT accumulate in FP32 within a chunk of at most 128
+ * contraction steps, then in FP64 across chunks.  The TTM accumulates each
+ * output in FP32 over its whole contraction (K = I_n terms; the K-split
+ * kernel of contiguous rows with 256 < K <= 512: K / 8 terms per wave, then
+ * the eight partial sums in FP32), and rounds it to the data type.  FP64:
+ * FP64 throughout.
  *   STH_PREC_FP64   FP64 products (FP32 data is widened exactly)
  *   STH_PREC_FP32   FP32 products on the FP32 matrix cores
  *   STH_PREC_BF16X3 x = hi + mid (two bf16, round to nearest even);
@@ -179,7 +183,12 @@ sth_status sthosvd_check(const sth_plan *plan, void *workspace, sth_stream_t str
  * exactly as a single run would).  One launch per phase of a mode step
  * covers the whole batch; the run is enqueue-only and may be captured in a
  * HIP graph.  The plan owns pinned host memory holding the shape/offset
- * tables (copied into the workspace by every run).
+ * tables, allocated and filled when the plan is made on a machine with a
+ * usable device (a run then allocates nothing; without one the first run
+ * makes it) and copied into the workspace by every run; a captured graph
+ * reads that memory, so it must not outlive its plan.  The eigen phase runs
+ * the library's direct solver for every order (exact leading eigenpairs on
+ * every spectrum, R_n above the Gram's rank included).
  * ------------------------------------------------------------------------- */
 sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count, sth_batch_plan **plan,
                                 size_t *workspace_bytes);
@@ -214,7 +223,8 @@ void sthosvd_plan_batched_destroy(sth_batch_plan *plan);
 sth_status sthosvd_run_batched(const sth_batch_plan *plan, const void *const *X_dev,
                                void *const *core_dev, double *const *U_dev, void *workspace,
                                size_t workspace_bytes, sth_stream_t stream);
-/* Synchronizes and reports device-side numerical flags of the last batched run. */
+/* Synchronizes, reports the device-side numerical flag of the batched runs
+ * since the last check (non-finite values met: STH_ERR_NUMERIC) and clears it. */
 sth_status sthosvd_check_batched(const sth_batch_plan *plan, void *workspace, sth_stream_t stream);
 
 /* ---------------------------------------------------------------------------
@@ -277,8 +287,9 @@ size_t ttm_factor_bytes(int64_t I, int64_t R, int32_t prec);
 
 /* Splits the FP64 factor U (device, I_n x R, or R x I_n with transpose_u = 1,
  * as in ttm_mode_n) once into the matrix-core operand layout that the TTM
- * kernels read for precision prec (one, two, three or six bf16/FP32/FP64
- * pieces per entry, Section IV's split of the factor).  out: device buffer
+ * kernels read for precision prec (one FP64 or FP32 value, or the two or
+ * three bf16 pieces of the split precisions, per entry; the split is this
+ * library's precision recipe, the contraction is Eq. 2).  out: device buffer
  * of ttm_factor_bytes(I, R, prec) bytes, owned by the caller, opaque; it stays
  * valid for any tensor whose mode n has I_n entries, as long as U does not
  * change.  For callers that apply one factor to many tensors.  Errors:
@@ -296,19 +307,32 @@ sth_status ttm_mode_n_prepared(int32_t order, const int64_t *dims, int32_t n, in
                                int32_t dtype, int32_t prec, const void *Y, const void *Uprep,
                                size_t uprep_bytes, void *Z, sth_stream_t stream);
 
-/* R leading eigenpairs of a symmetric n x n FP64 matrix S (device), in FP64:
+/* R leading eigenpairs of a symmetric n x n FP64 matrix S (device), in FP64
+ * (Alg. 2, EIG branch, line 7: the leading eigenvectors of the mode-n Gram):
  * U (device, n x R FP64, orthonormal, largest-magnitude entry of each column
- * positive) and lam (device, R values, descending; may be NULL).  n <= 128:
- * parallel cyclic Jacobi on S; n > 128 with a subspace block
- * p = R + 16 (rounded up to 8; down to R + 4 near the cap) <= 128: subspace iteration on a
- * seeded Gaussian block with Rayleigh-Ritz (S must then have rank >= p; a
- * Gram matrix of rank below p goes through sthosvd_run, which passes the rank
- * bound of each mode); otherwise Jacobi on S in the workspace.  ws: device
- * scratch of eig_leading_workspace(n) bytes; an exceeded sweep cap or a
- * breakdown is recorded in the first 8 bytes of ws as a non-zero int64. */
+ * positive) and lam (device, R values, descending; may be NULL).
+ * n <= 128: parallel cyclic Jacobi on S (relative accuracy; max_sweeps caps
+ * its sweeps, 0 = 60).  n > 128: subspace iteration on a seeded Gaussian
+ * block of p = R + 16 (rounded up to 8, at most 128) columns with
+ * Rayleigh-Ritz, accepted only when every Ritz residual
+ * ||S u - theta u|| <= max(16 sqrt(n) eps, s_unit) |theta_1|; otherwise (and
+ * when no such block exists) the direct solver of the library
+ * (tridiagonalization, bisection, inverse iteration) runs on S, so the
+ * result is the leading eigenpairs on every spectrum.  eig_leading_ex takes
+ * s_unit, the unit roundoff with which S was formed (0 for exact data, e.g.
+ * 2^-24 for a Gram of FP32 products), so that the iteration is not asked to
+ * resolve S beyond its own accuracy; eig_leading uses s_unit = 0.
+ * ws: device scratch of eig_leading_workspace(n) bytes; the first 8 bytes
+ * receive a non-zero int64 when Jacobi hit its sweep cap (1) or S was not
+ * finite (3); bytes 8..15 count the direct solves that replaced the subspace
+ * iteration (a diagnostic, not an error).  s_unit outside [0, 1) is
+ * STH_ERR_INVALID. */
 size_t eig_leading_workspace(int64_t n);
 sth_status eig_leading(int64_t n, int64_t R, const double *S, double *U, double *lam,
                        int32_t max_sweeps, void *ws, size_t ws_bytes, sth_stream_t stream);
+sth_status eig_leading_ex(int64_t n, int64_t R, const double *S, double *U, double *lam,
+                          int32_t max_sweeps, double s_unit, void *ws, size_t ws_bytes,
+                          sth_stream_t stream);
 
 /* Tucker reconstruction X^ = G x_1 U1 x_2 ... x_N UN (Sec. II-B).
  * G: device, prod ranks, dtype.  U: host array of N device pointers to

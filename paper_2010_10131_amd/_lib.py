@@ -83,6 +83,7 @@ SIGNATURES = {
     "ttm_mode_n_prepared": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _vp, _vp, _sz, _vp, _vp]),
     "eig_leading_workspace": (_sz, [_i64]),
     "eig_leading": (ctypes.c_int, [_i64, _i64, _vp, _vp, _vp, _i32, _vp, _sz, _vp]),
+    "eig_leading_ex": (ctypes.c_int, [_i64, _i64, _vp, _vp, _vp, _i32, ctypes.c_double, _vp, _sz, _vp]),
     "tucker_reconstruct_workspace": (_sz, [_i32, _i64p, _i64p, _i32]),
     "tucker_reconstruct": (ctypes.c_int, [_i32, _i64p, _i64p, _i32, _i32, _vp, _vpp, _vp, _vp, _sz, _vp]),
     "tucker_error_workspace": (_sz, [_i32, _i64p, _i64p, _i32]),

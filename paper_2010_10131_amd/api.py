@@ -301,18 +301,18 @@ def ttm_mode_n_prepared(Y: torch.Tensor, Uprep: torch.Tensor, n: int, R: int, pr
     return Z
 
 
-def eig_leading(S: torch.Tensor, R: int, max_sweeps: int = 0):
-    """R leading eigenpairs of a symmetric FP64 matrix: (U n x R, lam R)."""
+def eig_leading(S: torch.Tensor, R: int, max_sweeps: int = 0, s_unit: float = 0.0):
+    """R leading eigenpairs of a symmetric FP64 matrix: (U n x R, lam R, ws).
+    s_unit: unit roundoff with which S was formed (eig_leading_ex)."""
     _need(S, "S")
     L = _lib.load()
     n = S.shape[0]
     U = fortran_empty((n, R), torch.float64, S.device)
     lam = torch.empty(R, dtype=torch.float64, device=S.device)
     ws = _ws(L.eig_leading_workspace(n), S.device)
-    ws.zero_()
-    check(L.eig_leading(n, R, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(U.data_ptr()),
-                        ctypes.c_void_p(lam.data_ptr()), max_sweeps, ctypes.c_void_p(ws.data_ptr()),
-                        ws.numel(), _stream()))
+    check(L.eig_leading_ex(n, R, ctypes.c_void_p(S.data_ptr()), ctypes.c_void_p(U.data_ptr()),
+                           ctypes.c_void_p(lam.data_ptr()), max_sweeps, ctypes.c_double(s_unit),
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
     return U, lam, ws
 
 

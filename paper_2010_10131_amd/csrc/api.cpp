@@ -401,7 +401,7 @@ extern "C" sth_status sthosvd_run(const sth_plan *p, const void *X, void *core, 
     char *w = (char *)ws;
     int64_t *flag = (int64_t *)(w + p->o_flag);
     char *bufA = w + p->o_bufA, *bufB = w + p->o_bufB;
-    HIPCHK(zero_words(flag, 2, s), "flag clear");
+    HIPCHK(zero_words(flag, 6, s), "flag clear");
 
     for (const Step &stp : p->steps) {
         const void *src = stp.src == 0 ? X : (stp.src == 1 ? (const void *)bufA : (const void *)bufB);
@@ -561,17 +561,30 @@ extern "C" sth_status ttm_mode_n_prepared(int32_t order, const int64_t *dims, in
 
 extern "C" size_t eig_leading_workspace(int64_t n) { return n >= 1 ? align_up(eig_ws_bytes(n)) : 0; }
 
-extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double *U, double *lam,
-                                  int32_t max_sweeps, void *ws, size_t ws_bytes, sth_stream_t stream) {
+static sth_status eig_leading_impl(int64_t n, int64_t R, const double *S, double *U, double *lam,
+                                   int32_t max_sweeps, double s_unit, void *ws, size_t ws_bytes,
+                                   sth_stream_t stream) {
     if (n < 1 || n > MAX_EIG_N) return fail(n < 1 ? STH_ERR_INVALID : STH_ERR_UNSUPPORTED, "n = %lld outside 1..%lld", (long long)n, (long long)MAX_EIG_N);
     if (R < 1 || R > n) return fail(STH_ERR_INVALID, "R = %lld outside 1..n", (long long)R);
+    if (!(s_unit >= 0.0 && s_unit < 1.0)) return fail(STH_ERR_INVALID, "s_unit outside [0, 1)");
     sth_status st;
     if ((st = check_ptr(S, "S")) || (st = check_ptr(U, "U")) || (st = check_ptr(lam, "lam", true)) || (st = check_ptr(ws, "ws"))) return st;
     if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
-    HIPCHK(zero_words(ws, 2, (hipStream_t)stream), "flag clear");
+    HIPCHK(zero_words(ws, 6, (hipStream_t)stream), "flag clear");
     HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (int64_t *)ws,
-                      (hipStream_t)stream, n, true, 0.0), "eig");
+                      (hipStream_t)stream, n, true, s_unit), "eig");
     return STH_OK;
+}
+
+extern "C" sth_status eig_leading(int64_t n, int64_t R, const double *S, double *U, double *lam,
+                                  int32_t max_sweeps, void *ws, size_t ws_bytes, sth_stream_t stream) {
+    return eig_leading_impl(n, R, S, U, lam, max_sweeps, 0.0, ws, ws_bytes, stream);
+}
+
+extern "C" sth_status eig_leading_ex(int64_t n, int64_t R, const double *S, double *U, double *lam,
+                                     int32_t max_sweeps, double s_unit, void *ws, size_t ws_bytes,
+                                     sth_stream_t stream) {
+    return eig_leading_impl(n, R, S, U, lam, max_sweeps, s_unit, ws, ws_bytes, stream);
 }
 
 // --------------------------------------------------------------- HOOI ----
@@ -664,7 +677,7 @@ extern "C" sth_status sth_hooi(int32_t order, const int64_t *dims, const int64_t
     char *w = (char *)ws;
     int64_t *flag = (int64_t *)(w + L.flag);
     void *uq = w + L.uq;
-    HIPCHK(zero_words(flag, 2, s), "flag clear");
+    HIPCHK(zero_words(flag, 6, s), "flag clear");
     // X x_m U_m^T for every m != skip, increasing m; the last product goes to
     // last_dst (or a buffer); returns the result and its dims in cur
     auto chain = [&](int skip, void *last_dst, std::vector<int64_t> &cur, const void *&res) -> sth_status {
@@ -860,7 +873,7 @@ extern "C" sth_status sthosvd_mode_step(int32_t order, const int64_t *dims, int3
     if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
-    HIPCHK(zero_words(w + pl->o_flag, 2, s), "flag clear");
+    HIPCHK(zero_words(w + pl->o_flag, 6, s), "flag clear");
     return exec_step(*pl, pl->steps[0], Y, Z, U, eigvals, als_init, seed, w, s);
 }
 
@@ -955,7 +968,7 @@ struct sth_batch_plan_s {
     int count = 0, N = 0, dtype = 0, gram_prec = 0, ttm_prec = 0, max_sweeps = 60;
     std::vector<BatchStepT> steps;
     std::vector<char> blob;                // every table, host copy
-    mutable void *pinned = nullptr;        // pinned copy, allocated by the first run
+    mutable void *pinned = nullptr;        // pinned copy, filled at plan time (first run without a device)
     mutable std::mutex mu;
     size_t table_bytes = 0, tables_off = 0, flag_off = 0, total = 0;
     ~sth_batch_plan_s() {
@@ -1046,6 +1059,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             maxUq = std::max(maxUq, ttm_prep_bytes(b.I, b.R, d0.ttm_prec));
             if (b.I > MAX_EIG_N)
                 return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: I_n = %lld exceeds the eigensolver limit %lld", t, s, (long long)b.I, (long long)MAX_EIG_N);
+            if (b.R > 64) return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n > 64 in the batched path", t, s);
             b.sib = 0;   // the direct solver for every order
             maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.R));
             b.nchunks = (int)((b.I + 31) / 32);
@@ -1133,6 +1147,19 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
     p->tables_off = a.take(p->table_bytes);
     p->total = a.off;
     p->blob = std::move(blob);
+    // the pinned copy the runs enqueue from: allocated here, so that a run
+    // (possibly under graph capture) allocates nothing.  Planning stays
+    // host-only work: without a usable device the copy is made by the first
+    // run instead.
+    {
+        void *h = nullptr;
+        if (hipHostMalloc(&h, p->table_bytes > 0 ? p->table_bytes : 16, hipHostMallocDefault) == hipSuccess) {
+            memcpy(h, p->blob.data(), p->table_bytes);
+            p->pinned = h;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
     *ws_out = p->total;
     *out = p.release();
     return STH_OK;
@@ -1157,13 +1184,13 @@ extern "C" sth_status sthosvd_run_batched(const sth_batch_plan *p, const void *c
         std::lock_guard<std::mutex> lk(p->mu);
         if (!p->pinned) {
             void *h = nullptr;
-            HIPCHK(hipHostMalloc(&h, p->table_bytes, hipHostMallocDefault), "pinned tables");
+            HIPCHK(hipHostMalloc(&h, p->table_bytes > 0 ? p->table_bytes : 16, hipHostMallocDefault), "pinned tables");
             memcpy(h, p->blob.data(), p->table_bytes);
             p->pinned = h;
         }
     }
     HIPCHK(hipMemcpyAsync(tab, p->pinned, p->table_bytes, hipMemcpyHostToDevice, s), "tables");
-    HIPCHK(zero_words(flag, 2, s), "flag clear");
+    HIPCHK(zero_words(flag, 6, s), "flag clear");
     auto res = [&](const BatchLaunchT &L) {
         BatchLaunch b;
         b.list = (const int32_t *)(tab + L.list_off);
@@ -1198,7 +1225,10 @@ extern "C" sth_status sthosvd_check_batched(const sth_batch_plan *p, void *ws, s
     int64_t *dflag = (int64_t *)((char *)ws + p->flag_off);
     HIPCHK(hipStreamSynchronize((hipStream_t)stream), "sync");
     HIPCHK(hipMemcpy(&flag, dflag, sizeof(flag), hipMemcpyDeviceToHost), "flag read");
-    if (flag == 1) return fail(STH_ERR_NUMERIC, "eigensolver hit its sweep cap");
+    const int64_t zero = 0;
+    HIPCHK(hipMemcpy(dflag, &zero, sizeof(zero), hipMemcpyHostToDevice), "flag clear");
+    if (flag == 2) return fail(STH_ERR_NUMERIC, "Cholesky met a non-positive pivot");
+    if (flag == 3) return fail(STH_ERR_NUMERIC, "NaN or Inf met");
     if (flag) return fail(STH_ERR_NUMERIC, "numeric flag %lld", (long long)flag);
     return STH_OK;
 }

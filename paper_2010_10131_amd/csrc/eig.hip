@@ -352,14 +352,18 @@ hipError_t eig_launch(int64_t n, int64_t R, const double *S, double *U, double *
     // start block: seeded Gaussian, used as it is (its span is all that
     // matters to the iteration, and an n x p Gaussian is well conditioned)
     if ((e = gaussian_f64(w.Q, n * p, 0x5EED5EEDull, (uint64_t)n * 1000 + p, s))) return e;
+    // a Cholesky breakdown inside the iteration (S of rank below p) is not an
+    // error of the result: it spoils the Ritz pairs, the residual test then
+    // sends the solve to the direct solver; it is recorded in flag[2] only
+    int64_t *si_flag = flag ? flag + 2 : nullptr;
     for (int it = 0; it < SI_ITERS; ++it) {
         if ((e = gemm_f64(0, 0, ni, pi, ni, 1.0, S, n, w.Q, n, 0.0, w.Z, n, w.gws, s))) return e;
-        if ((e = orth(w.Z, w.Q, ni, pi, it + 1 == SI_ITERS ? 3 : 2, w, flag, s))) return e;
+        if ((e = orth(w.Z, w.Q, ni, pi, it + 1 == SI_ITERS ? 3 : 2, w, si_flag, s))) return e;
     }
     // Rayleigh-Ritz: T = Q^T S Q, its R leading pairs (W, theta), U = Q W
     if ((e = gemm_f64(0, 0, ni, pi, ni, 1.0, S, n, w.Q, n, 0.0, w.Z, n, w.gws, s))) return e;
     if ((e = gemm_f64(1, 0, pi, pi, ni, 1.0, w.Q, n, w.Z, n, 0.0, w.T, p, w.gws, s))) return e;
-    if ((e = teig_launch(w.T, p, p, R, w.W, p, w.th, false, w.te, flag, nullptr, 0.0, s))) return e;
+    if ((e = teig_launch(w.T, p, p, R, w.W, p, w.th, false, w.te, si_flag, nullptr, 0.0, s))) return e;
     hipLaunchKernelGGL(rr_finish_kernel, dim3((unsigned)R), dim3(256), 0, s, w.Q, w.Z, ni, pi, w.W, w.th, (int)R, U,
                        lam, w.res);
     if ((e = hipGetLastError())) return e;

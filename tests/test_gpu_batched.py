@@ -9,16 +9,14 @@ import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-# mixed shapes: first-mode I % 4 != 0, n <= 128 (Jacobi) and n > 128 (subspace
-# iteration), small and large ranks, a mode of size < 32
+# mixed shapes: first-mode I % 4 != 0, orders <= 128 (matrix in LDS) and
+# > 128 (matrix in the workspace), small and large ranks, a mode of size < 32
 SHAPES = [((40, 36, 33), (4, 5, 6)), ((37, 60, 50), (6, 8, 5)), ((130, 40, 35), (16, 6, 5)),
           ((200, 150, 33), (30, 20, 5)), ((64, 256, 40), (10, 40, 8)), ((96, 96, 96), (12, 12, 12)),
           ((33, 20, 150), (5, 4, 18)), ((250, 60, 32), (60, 9, 5)),
           ((120, 50, 40), (12, 6, 5)), ((110, 4, 5), (25, 3, 4))]
-# ((120, 50, 40), ...): order 120 takes the subspace iteration; ((110, 4, 5), ...):
-# R_1 = 25 exceeds the rank bound 20 of the mode-1 Gram, which keeps the Jacobi
-# ((33, 20, 150), (5, 4, 18)): the mode-3 Gram has rank <= 5 * 4 = 20, below the
-# subspace block max(18 + 16, 27) -> 40, which the plan caps at 20
+# ((110, 4, 5), ...): R_1 = 25 exceeds the rank bound 20 of the mode-1 Gram;
+# ((33, 20, 150), (5, 4, 18)): the mode-3 Gram has rank <= 5 * 4 = 20 > 18
 
 
 @pytest.fixture(scope="module")
@@ -141,3 +139,52 @@ def test_autotuner_picks_a_valid_choice(api):
         Go, Uo, _ = oracle.sthosvd(xs[t], r)
         xn = np.linalg.norm(xs[t].astype(np.float64))
         assert np.linalg.norm(recon(api, G[t], U[t]) - oracle.reconstruct(Go, Uo)) / xn <= 1e-5
+
+
+def test_batched_gapless_and_rank_deficient_match_oracle(api):
+    """Gaussian tensors (no gap after R_n in any mode) and a mode whose Gram
+    has rank below R_n (mode 3 of (33, 20, 150) with R_3 = 24 > 15) in one
+    batch: every tensor against the oracle."""
+    import torch
+    shapes = [((200, 150, 40), (20, 15, 5)), ((129, 64, 33), (12, 8, 4)), ((64, 64, 64), (8, 8, 8)),
+              ((33, 20, 150), (5, 3, 24))]
+    rng = np.random.default_rng(41)
+    xs = [np.asfortranarray(rng.standard_normal(d).astype(np.float32)) for d, _ in shapes[:3]]
+    xs.append(wl.lowrank_plus_noise(*shapes[3], "none", 1e-4, 43, "float32"))
+    xd = [api.to_device(x) for x in xs]
+    xp = torch.tensor([x.data_ptr() for x in xd], dtype=torch.int64, device="cuda")
+    plan = api.BatchPlan(shapes, "fp64", "fp32")
+    G, U, cp, up = plan.outputs()
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.run(xp, cp, up, ws)
+    plan.check(ws)
+    for t, (d, r) in enumerate(shapes):
+        Go, Uo, _ = oracle.sthosvd(xs[t], r)
+        xn = np.linalg.norm(xs[t].astype(np.float64))
+        t2 = np.linalg.norm(recon(api, G[t], U[t]) - oracle.reconstruct(Go, Uo)) / xn
+        assert t2 <= 1e-6, (t, d, r, t2)
+        for n in range(3):
+            u = api.to_numpy(U[t][n])
+            np.testing.assert_allclose(u.T @ u, np.eye(r[n]), atol=1e-12)
+
+
+def test_batched_64_tensors_match_oracle(api):
+    """64 tensors of the batched workload's recipe (sides 32..128, ranks
+    10-25 %, low rank + 1e-4 noise) against the oracle, default recipe."""
+    import torch
+    shapes, xs = wl.batch_tensors(64, hi=128, workers=4)
+    xd = [api.to_device(x) for x in xs]
+    xp = torch.tensor([x.data_ptr() for x in xd], dtype=torch.int64, device="cuda")
+    plan = api.BatchPlan(shapes, "bf16x6", "bf16x3")
+    G, U, cp, up = plan.outputs()
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.run(xp, cp, up, ws)
+    plan.check(ws)
+    worst = 0.0
+    for t, (d, r) in enumerate(shapes):
+        Go, Uo, _ = oracle.sthosvd(xs[t], r)
+        xn = np.linalg.norm(xs[t].astype(np.float64))
+        t2 = np.linalg.norm(recon(api, G[t], U[t]) - oracle.reconstruct(Go, Uo)) / xn
+        worst = max(worst, t2)
+        assert t2 <= 1e-5, (t, d, r, t2)
+    print(f"64 tensors: worst T2 {worst:.2e}")
