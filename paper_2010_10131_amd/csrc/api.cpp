@@ -222,6 +222,10 @@ static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_ou
             delete p;
             return fail(STH_ERR_UNSUPPORTED, "ALS mode %d: R_n = %lld exceeds %lld", stp.n, (long long)stp.R, (long long)MAX_ALS_R);
         }
+        if (solver == STH_SOLVER_ALS && stp.R > stp.L * stp.M) {
+            delete p;
+            return fail(STH_ERR_UNSUPPORTED, "ALS mode %d: R_n = %lld exceeds the rank bound %lld of the unfolding (its normal equations are singular; use EIG)", stp.n, (long long)stp.R, (long long)(stp.L * stp.M));
+        }
         stp.solver = solver;
         p->solver_of_mode[stp.n] = solver;
         stp.src = (s == 0) ? 0 : ((s - 1) % 2 == 0 ? 1 : 2);

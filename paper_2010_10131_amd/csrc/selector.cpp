@@ -42,11 +42,14 @@ void selector_predict(const float *w, const float *x, float *y) {
     }
 }
 
-static int apply_limits(int choice, int64_t I, int64_t R) {
-    if (choice == STH_SOLVER_ALS && R > SEL_MAX_ALS_R) choice = STH_SOLVER_EIG;
-    if (choice == STH_SOLVER_EIG && I > SEL_EIG_DIRECT_MAX && R > SEL_EIG_SI_MAX_R && R <= SEL_MAX_ALS_R)
+int apply_limits(int choice, int64_t I, int64_t R, int64_t J) {
+    // ALS needs R_n <= J_n (R_k = Y^T L_k has rank <= J_n: above it the
+    // normal equations are singular) and the R_n x R_n Cholesky in LDS
+    const bool als_ok = R <= SEL_MAX_ALS_R && R <= J;
+    if (choice == STH_SOLVER_ALS && !als_ok) choice = STH_SOLVER_EIG;
+    if (choice == STH_SOLVER_EIG && I > SEL_EIG_DIRECT_MAX && R > SEL_EIG_SI_MAX_R && als_ok)
         choice = STH_SOLVER_ALS;
-    if (choice == STH_SOLVER_EIG && I > SEL_MAX_EIG_N) choice = STH_SOLVER_ALS;
+    if (choice == STH_SOLVER_EIG && I > SEL_MAX_EIG_N && als_ok) choice = STH_SOLVER_ALS;
     return choice;
 }
 
@@ -55,7 +58,7 @@ int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *wei
     float f[SEL_IN], y[SEL_OUT];
     selector_features(I, R, J, f);
     selector_predict(weights, f, y);
-    return apply_limits((y[1] < y[0]) ? STH_SOLVER_ALS : STH_SOLVER_EIG, I, R);
+    return apply_limits((y[1] < y[0]) ? STH_SOLVER_ALS : STH_SOLVER_EIG, I, R, J);
 }
 
 int selector_tree_choose(int64_t I, int64_t R, int64_t J) {
@@ -64,7 +67,7 @@ int selector_tree_choose(int64_t I, int64_t R, int64_t J) {
     int k = 0;
     for (int depth = 0; kTreeFeature[k] >= 0 && depth < kTreeNodes; ++depth)
         k = (f[kTreeFeature[k]] <= kTreeThreshold[k]) ? kTreeLeft[k] : kTreeRight[k];
-    return apply_limits(kTreeClass[k] ? STH_SOLVER_ALS : STH_SOLVER_EIG, I, R);
+    return apply_limits(kTreeClass[k] ? STH_SOLVER_ALS : STH_SOLVER_EIG, I, R, J);
 }
 
 }  // namespace sth

@@ -26,18 +26,24 @@ void selector_predict(const float *weights, const float *feat10, float *out2);
 constexpr int64_t SEL_MAX_EIG_N = 512;   // eigensolver: I_n x I_n Gram
 constexpr int64_t SEL_MAX_ALS_R = 128;   // ALS: R_n x R_n Cholesky in LDS
 // EIG above order 128 with R_n > 124 leaves no room for the subspace block's
-// guard vectors and runs cyclic Jacobi on the whole Gram, two orders of
-// magnitude slower than ALS there: ALS is taken whenever its limit allows.
+// guard vectors and runs the direct solver on the whole Gram from the
+// workspace, several times slower than ALS there: ALS is taken whenever its
+// limits allow.
 constexpr int64_t SEL_EIG_SI_MAX_R = 124;
 constexpr int64_t SEL_EIG_DIRECT_MAX = 128;
 
-// 0 = EIG, 1 = ALS: argmin of the predicted times (EIG on ties), then the
-// solver limits (EIG needs I_n <= SEL_MAX_EIG_N, ALS R_n <= SEL_MAX_ALS_R) and
-// the whole-Gram Jacobi rule above.
+// The solver limits applied to a choice (0 = EIG, 1 = ALS) for a mode with
+// (I_n, R_n, J_n): ALS needs R_n <= SEL_MAX_ALS_R and R_n <= J_n (the rank
+// bound of the unfolding), EIG needs I_n <= SEL_MAX_EIG_N; a mode that the
+// chosen solver cannot run goes to the other one when it can, and the
+// whole-Gram rule above.
+int apply_limits(int choice, int64_t I, int64_t R, int64_t J);
+
+// 0 = EIG, 1 = ALS: argmin of the predicted times (EIG on ties), then
+// apply_limits.
 int selector_choose(int64_t I, int64_t R, int64_t J, int order, const float *weights);
 
-// 0 = EIG, 1 = ALS: the compiled-in decision tree's class, then the same
-// solver limits and whole-Gram rule.
+// 0 = EIG, 1 = ALS: the compiled-in decision tree's class, then apply_limits.
 int selector_tree_choose(int64_t I, int64_t R, int64_t J);
 
 }  // namespace sth

@@ -101,17 +101,19 @@ def tree_predict(tree, X):
 
 
 # The library applies the solvers' limits after either model (selector.h):
-# ALS needs R_n <= 128; EIG needs I_n <= 512; above order 128 with R_n in
-# 125..128 the plan takes ALS (EIG would run Jacobi on the whole Gram).
+# ALS needs R_n <= 128 and R_n <= J_n (the rank bound of the unfolding); EIG
+# needs I_n <= 512; above order 128 with R_n in 125..128 the plan takes ALS
+# where it can (EIG would run the direct solver on the whole Gram).
 def apply_limits(choice, recs):
     out = np.array(choice, dtype=int)
     for i, r in enumerate(recs):
-        I, R = r["I"], r["R"]
-        if out[i] == 1 and R > 128:
+        I, R, J = r["I"], r["R"], r["J"]
+        als_ok = R <= 128 and R <= J
+        if out[i] == 1 and not als_ok:
             out[i] = 0
-        if out[i] == 0 and I > 128 and 124 < R <= 128:
+        if out[i] == 0 and I > 128 and 124 < R <= 128 and als_ok:
             out[i] = 1
-        if out[i] == 0 and I > 512:
+        if out[i] == 0 and I > 512 and als_ok:
             out[i] = 1
     return out
 

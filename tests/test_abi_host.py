@@ -72,6 +72,18 @@ def test_plan_validation_errors():
     assert _err(dims=(600, 300, 4), ranks=(8, 200, 2), per_mode=("als", "als", "eig")) == UNSUP
 
 
+def test_als_above_the_rank_bound_of_the_unfolding():
+    """Mode 1 of (64, 2, 2) with R_1 = 5 > J_1 = 4: ALS's normal equations
+    would be singular.  Either learned selector takes EIG there; an explicit
+    ALS request is refused before anything runs."""
+    from paper_2010_10131_amd import _lib
+    for solver in ("auto", "auto_tree"):
+        assert _plan(dims=(64, 2, 2), ranks=(5, 2, 2), solver=solver).solvers[0] == 0
+    assert _err(dims=(64, 2, 2), ranks=(5, 2, 2), per_mode=("als", "eig", "eig")) == _lib.STH_ERR_UNSUPPORTED
+    # R_1 = J_1 is allowed
+    assert _plan(dims=(64, 2, 2), ranks=(4, 2, 2), per_mode=("als", "eig", "eig")).solvers == [1, 0, 0]
+
+
 def test_plan_shapes_solvers_and_workspace():
     import torch
     p = _plan()

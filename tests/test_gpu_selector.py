@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
@@ -103,3 +104,15 @@ def test_host_inference_matches_device(api):
     Yd = api.mlp_forward(torch.from_numpy(p).cuda(), Xd).cpu().numpy()
     for k, s in enumerate(shapes):
         np.testing.assert_allclose(api.selector_predict(*s, weights=p), Yd[:, k], rtol=1e-5, atol=1e-5)
+
+
+def test_auto_takes_eig_above_the_rank_bound(api):
+    """(64, 2, 2) with ranks (5, 2, 2) under either selector: mode 1 runs EIG
+    (ALS would meet singular normal equations) and matches the oracle."""
+    import torch
+    X = wl.lowrank_plus_noise((64, 2, 2), (4, 2, 2), "none", 1e-3, 3, "float64")
+    for solver in ("auto", "auto_tree"):
+        G, U, _ = api.sthosvd(api.to_device(X), (5, 2, 2), "fp64", "fp64", solver=solver)
+        Go, Uo, _ = oracle.sthosvd(X, (5, 2, 2))
+        Xh = oracle.reconstruct(api.to_numpy(G), [api.to_numpy(u) for u in U])
+        assert np.linalg.norm(Xh - oracle.reconstruct(Go, Uo)) <= 1e-12 * np.linalg.norm(X)
