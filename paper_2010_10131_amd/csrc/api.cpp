@@ -311,19 +311,31 @@ AlsBufs als_bufs(double *base, int64_t I, int64_t R) {
     return b;
 }
 
-// Cholesky-QR twice of the I x R matrix A (well conditioned): Q = A R^{-1},
-// R = R2 R1 (upper, positive diagonal).  Q may alias nothing in A.
-hipError_t cholqr2(const double *A, int I, int R, double *Q, double *Rfac, AlsBufs &b, void *gws,
+// Shifted Cholesky-QR3 of the I x R matrix A: Q = A R^{-1} with R = R3 R2 R1
+// upper triangular with a positive diagonal.  The first pass factors
+// A^T A + s I (s = 11 (I R + R (R + 1)) u ||A||_F^2, u = 2^-53), which exists
+// for any condition number up to ~1/u and leaves A R1^{-1} well conditioned;
+// two plain passes then make the columns orthonormal to working accuracy.
+// The bases of the ALS sweeps need this: on steeply decaying spectra (the
+// 2^-k core of the 4-way workload) L_k has a condition number near 1e9,
+// beyond what plain Cholesky-QR twice tolerates.  Uses b.T1, b.P, b.G2 and
+// the R x R buffers; Q may alias nothing in A.
+hipError_t cholqr3(const double *A, int I, int R, double *Q, double *Rfac, AlsBufs &b, void *gws,
                    int64_t *flag, hipStream_t s) {
     hipError_t e;
+    const double shift = 11.0 * ((double)I * R + (double)R * (R + 1)) * 1.1102230246251565e-16 * R;
     if ((e = gemm_f64(1, 0, R, R, I, 1.0, A, I, A, I, 0.0, b.G2, R, gws, s))) return e;
-    if ((e = chol_launch(b.G2, R, R, 0.0, b.R1, b.R1inv, flag, s))) return e;
+    if ((e = chol_launch(b.G2, R, R, shift, b.R1, b.R1inv, flag, s))) return e;
     if ((e = gemm_f64(0, 0, I, R, R, 1.0, A, I, b.R1inv, R, 0.0, b.T1, I, gws, s))) return e;
     if ((e = gemm_f64(1, 0, R, R, I, 1.0, b.T1, I, b.T1, I, 0.0, b.G2, R, gws, s))) return e;
     if ((e = chol_launch(b.G2, R, R, 0.0, b.R2, b.R2inv, flag, s))) return e;
-    if ((e = gemm_f64(0, 0, I, R, R, 1.0, b.T1, I, b.R2inv, R, 0.0, Q, I, gws, s))) return e;
+    if ((e = gemm_f64(0, 0, I, R, R, 1.0, b.T1, I, b.R2inv, R, 0.0, b.P, I, gws, s))) return e;
+    if ((e = gemm_f64(1, 0, R, R, I, 1.0, b.P, I, b.P, I, 0.0, b.G2, R, gws, s))) return e;
+    if ((e = chol_launch(b.G2, R, R, 0.0, b.Rc, b.Rcinv, flag, s))) return e;
+    if ((e = gemm_f64(0, 0, I, R, R, 1.0, b.P, I, b.Rcinv, R, 0.0, Q, I, gws, s))) return e;
     if (Rfac) {
-        if ((e = gemm_f64(0, 0, R, R, R, 1.0, b.R2, R, b.R1, R, 0.0, Rfac, R, gws, s))) return e;
+        if ((e = gemm_f64(0, 0, R, R, R, 1.0, b.R2, R, b.R1, R, 0.0, b.C, R, gws, s))) return e;
+        if ((e = gemm_f64(0, 0, R, R, R, 1.0, b.Rc, R, b.C, R, 0.0, Rfac, R, gws, s))) return e;
     }
     return hipSuccess;
 }
@@ -362,7 +374,7 @@ static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *s
         HIPCHK(gaussian_f64(b.L0, (int64_t)I * R, seed, (uint64_t)n, s), "als init");
         L0 = b.L0;
     }
-    HIPCHK(cholqr2(L0, I, R, b.Q, nullptr, b, gws, flag, s), "als qr0");
+    HIPCHK(cholqr3(L0, I, R, b.Q, nullptr, b, gws, flag, s), "als qr0");
     for (int k = 0; k < p->als_iters; ++k) {
         // Z = Y x_n Q^T  (R_k as a tensor)
         HIPCHK(ttm_prep_u(b.Q, I, R, 0, tp, uq, s), "als prep");
@@ -376,7 +388,7 @@ static sth_status exec_step(const sth_plan_s &pl, const Step &stp, const void *s
         HIPCHK(gemm_f64(0, 1, I, R, R, 1.0, b.T1, I, b.Rcinv, R, 0.0, b.Lk, I, gws, s), "als L2");
         const bool last = (k + 1 == p->als_iters);
         // next basis, or the final Q^ R^ = L
-        HIPCHK(cholqr2(b.Lk, I, R, last ? Un : b.Q, last ? b.Rhat : nullptr, b, gws, flag, s), "als qr");
+        HIPCHK(cholqr3(b.Lk, I, R, last ? Un : b.Q, last ? b.Rhat : nullptr, b, gws, flag, s), "als qr");
     }
     // core update: Y' = R x_n R^  (Z'(a, r, b) = sum_s R^(r, s) Z(a, s, b))
     HIPCHK(ttm_prep_u(b.Rhat, R, R, 1, tp, uq, s), "als core prep");
