@@ -417,7 +417,7 @@ extern "C" sth_status sthosvd_run(const sth_plan *p, const void *X, void *core, 
     char *w = (char *)ws;
     int64_t *flag = (int64_t *)(w + p->o_flag);
     char *bufA = w + p->o_bufA, *bufB = w + p->o_bufB;
-    HIPCHK(zero_words(flag, 6, s), "flag clear");
+    HIPCHK(zero_words(flag, 8, s), "flag clear");
 
     for (const Step &stp : p->steps) {
         const void *src = stp.src == 0 ? X : (stp.src == 1 ? (const void *)bufA : (const void *)bufB);
@@ -586,7 +586,7 @@ static sth_status eig_leading_impl(int64_t n, int64_t R, const double *S, double
     sth_status st;
     if ((st = check_ptr(S, "S")) || (st = check_ptr(U, "U")) || (st = check_ptr(lam, "lam", true)) || (st = check_ptr(ws, "ws"))) return st;
     if (ws_bytes < eig_ws_bytes(n)) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, eig_ws_bytes(n));
-    HIPCHK(zero_words(ws, 6, (hipStream_t)stream), "flag clear");
+    HIPCHK(zero_words(ws, 8, (hipStream_t)stream), "flag clear");
     HIPCHK(eig_launch(n, R, S, U, lam, 1e-15, max_sweeps > 0 ? max_sweeps : 60, ws, (int64_t *)ws,
                       (hipStream_t)stream, n, true, s_unit), "eig");
     return STH_OK;
@@ -693,7 +693,7 @@ extern "C" sth_status sth_hooi(int32_t order, const int64_t *dims, const int64_t
     char *w = (char *)ws;
     int64_t *flag = (int64_t *)(w + L.flag);
     void *uq = w + L.uq;
-    HIPCHK(zero_words(flag, 6, s), "flag clear");
+    HIPCHK(zero_words(flag, 8, s), "flag clear");
     // X x_m U_m^T for every m != skip, increasing m; the last product goes to
     // last_dst (or a buffer); returns the result and its dims in cur
     auto chain = [&](int skip, void *last_dst, std::vector<int64_t> &cur, const void *&res) -> sth_status {
@@ -889,7 +889,7 @@ extern "C" sth_status sthosvd_mode_step(int32_t order, const int64_t *dims, int3
     if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
-    HIPCHK(zero_words(w + pl->o_flag, 6, s), "flag clear");
+    HIPCHK(zero_words(w + pl->o_flag, 8, s), "flag clear");
     return exec_step(*pl, pl->steps[0], Y, Z, U, eigvals, als_init, seed, w, s);
 }
 
@@ -1206,7 +1206,7 @@ extern "C" sth_status sthosvd_run_batched(const sth_batch_plan *p, const void *c
         }
     }
     HIPCHK(hipMemcpyAsync(tab, p->pinned, p->table_bytes, hipMemcpyHostToDevice, s), "tables");
-    HIPCHK(zero_words(flag, 6, s), "flag clear");
+    HIPCHK(zero_words(flag, 8, s), "flag clear");
     auto res = [&](const BatchLaunchT &L) {
         BatchLaunch b;
         b.list = (const int32_t *)(tab + L.list_off);

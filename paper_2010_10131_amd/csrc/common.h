@@ -138,6 +138,19 @@ template <int PREC> union FragQ {
 
 // Counter-based standard normal sample: SplitMix64 (Steele, Lea & Flood,
 // OOPSLA 2014) on (seed, stream, element), two uniforms -> Box-Muller.
+// Gate of the launches that repeat a solve step only when a residual test
+// failed: true when res is null (ungated) or when some res[r], r < R, is
+// above tol * res[R] or not finite.  Every wave reads the same R + 1 values,
+// so the answer is uniform across the workgroup (no barrier needed).
+__device__ __forceinline__ bool gate_open(const double *res, int R, double tol) {
+    if (!res) return true;
+    const double thr = tol * res[R];
+    int bad = 0;
+    for (int r = (int)(threadIdx.x & 63); r < R; r += 64)
+        if (!(res[r] <= thr)) bad = 1;
+    return __ballot(bad) != 0;
+}
+
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
     z += 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;

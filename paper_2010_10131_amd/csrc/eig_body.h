@@ -15,7 +15,6 @@ constexpr int64_t EIG_LDS_DIRECT_MAX = 96;
 // on a gapped spectrum at a fraction of the full Jacobi's sweeps).
 constexpr int64_t EIG_SI_MIN = 48;
 constexpr int64_t SI_BLOCK_MAX = 128;    // Rayleigh-Ritz block (Cholesky-QR and small Jacobi reach 128)
-constexpr int SI_ITERS_DEV = 3;          // subspace iterations before Rayleigh-Ritz
 constexpr int EIG_LDS_AV = 150 * 1024;   // LDS bytes available for Jacobi's A and V
 
 // Block size of the subspace iteration: R + 16 guard vectors, rounded up to

@@ -46,9 +46,11 @@ inline double gram_unit(int prec) {
     return prec == 0 ? 1.1102230246251565e-16 : (prec == 2 ? 7.62939453125e-06 : 5.9604644775390625e-08);
 }
 // the direct solver alone (scratch: teig_scratch_doubles(n, R, n <= 128) doubles)
+// chk (may be null): run only when gate_open(chk, R, chk_tol); count (may be
+// null): incremented when it runs
 hipError_t teig_launch(const double *S, int64_t lds, int64_t n, int64_t R, double *U, int64_t ldu, double *lam,
                        bool sign_rule, void *scratch, int64_t *flag, const double *chk, double chk_tol,
-                       hipStream_t s);
+                       int64_t *count, hipStream_t s);
 
 // Small FP64 LA and reductions (la.hip)
 int gemm_splits(int m, int n, int k);
@@ -56,8 +58,10 @@ size_t gemm_ws_bytes(int m, int n, int k);
 hipError_t gemm_f64(int ta, int tb, int m, int n, int k, double alpha, const double *A,
                     int64_t lda, const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
                     void *ws, hipStream_t s);
+// gate (may be null): run only when gate_open(gate, gate_R, gate_tol)
 hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, double *R,
-                       double *Rinv, int64_t *flag, hipStream_t s);
+                       double *Rinv, int64_t *flag, hipStream_t s, const double *gate = nullptr,
+                       int gate_R = 0, double gate_tol = 0.0);
 hipError_t sumsq_launch(int dtype, const void *x, const void *y, int64_t count, double *out,
                         double *part, int64_t *flag, hipStream_t s);
 hipError_t fill_f64(double *p, int64_t n, double v, hipStream_t s);

@@ -149,16 +149,21 @@ __global__ __launch_bounds__(CHOL_THREADS) void chol_kernel(const double *__rest
                                                             int64_t ldg, double shift_rel,
                                                             double *__restrict__ Rout,
                                                             double *__restrict__ Rinv,
-                                                            int64_t *__restrict__ flag) {
+                                                            int64_t *__restrict__ flag,
+                                                            const double *__restrict__ gate, int gate_R,
+                                                            double gate_tol) {
+    if (!gate_open(gate, gate_R, gate_tol)) return;
     chol_body<CHOL_THREADS>(G, n, ldg, shift_rel, Rout, Rinv, flag);
 }
 
 hipError_t chol_launch(const double *G, int n, int64_t ldg, double shift_rel, double *R,
-                       double *Rinv, int64_t *flag, hipStream_t s) {
+                       double *Rinv, int64_t *flag, hipStream_t s, const double *gate, int gate_R,
+                       double gate_tol) {
     const size_t lds = chol_lds_bytes(n);
     if (lds > 64 * 1024)
         if (hipError_t ea = hipFuncSetAttribute((const void *)chol_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) return ea;
-    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(CHOL_THREADS), lds, s, G, n, ldg, shift_rel, R, Rinv, flag);
+    hipLaunchKernelGGL(chol_kernel, dim3(1), dim3(CHOL_THREADS), lds, s, G, n, ldg, shift_rel, R, Rinv, flag,
+                       gate, gate_R, gate_tol);
     return hipGetLastError();
 }
 

@@ -240,8 +240,8 @@ def test_eig_gapless_spectrum_is_exact(api):
     S = spd_with_spectrum(lam, 3)
     U, ev, ws = api.eig_leading(api.to_device(S), R)
     U = api.to_numpy(U)
-    flags = ws[:16].view(dtype=torch.int64).cpu().numpy()
-    assert flags[0] == 0 and flags[1] == 1, flags
+    flags = ws[:32].view(dtype=torch.int64).cpu().numpy()
+    assert flags[0] == 0 and flags[1] == 1 and flags[3] == 1, flags   # both rounds failed
     lo, Vo, _ = oracle.jacobi_eig(S)
     sin_theta = np.linalg.norm(U @ U.T - Vo[:, :R] @ Vo[:, :R].T, 2)
     assert sin_theta <= 1e-11, sin_theta
@@ -250,6 +250,28 @@ def test_eig_gapless_spectrum_is_exact(api):
     np.testing.assert_allclose(U.T @ U, np.eye(R), atol=1e-13)
     gaps = lo[:R] - lo[1:R + 1]
     assert np.all(np.abs(U - Vo[:, :R]) <= 1e-12 + 64 * n * 2.2e-16 * lo[0] / np.minimum(gaps, np.r_[np.inf, gaps[:-1]]))
+
+
+def test_eig_second_round_resolves_a_moderate_gap(api):
+    """lam_(p+1) / lam_R ~ 2e-4 (p = 40): three products leave Ritz residuals
+    near 1e-12 |theta_1|, above the FP64 test, so the gated second round runs
+    (two more products and Rayleigh-Ritz); five products pass it, and the
+    direct solver is not needed.  The result is the oracle's leading
+    subspace."""
+    import torch
+    n, R = 300, 20
+    lam = np.concatenate([1.0 - np.arange(20) / 40.0, 0.5 * 2.0 ** -np.arange(1.0, 21.0),
+                          1e-4 * 0.9 ** np.arange(n - 40)])
+    S = spd_with_spectrum(lam, 29)
+    U, ev, ws = api.eig_leading(api.to_device(S), R)
+    U, ev = api.to_numpy(U), ev.cpu().numpy()
+    flags = ws[:32].view(dtype=torch.int64).cpu().numpy()
+    assert flags[0] == 0 and flags[3] == 1 and flags[1] == 0, flags
+    lo, Vo, _ = oracle.jacobi_eig(S)
+    np.testing.assert_allclose(ev, lo[:R], rtol=0, atol=4 * n * 2.2e-16 * lo[0])
+    assert np.linalg.norm(U @ U.T - Vo[:, :R] @ Vo[:, :R].T, 2) <= 1e-12
+    assert np.linalg.norm(S @ U - U * ev, axis=0).max() <= 16 * np.sqrt(n) * 2.3e-16 * lo[0]
+    np.testing.assert_allclose(U.T @ U, np.eye(R), atol=1e-13)
 
 
 @pytest.mark.parametrize("n,R", [(129, 8), (300, 40), (512, 64)])
