@@ -333,28 +333,36 @@ def bench_batched(args, api, torch, dev, gp, tp):
 
 
 
-def bench_ablation(api, torch, Xd, ranks, reps=3):
-    """The comparison of Sec. V's Fig. 8 on this device: st-HOSVD with
-    explicit matricization (per mode the working tensor is permuted into a
-    contiguous I_n x J_n matrix -- mode 1 of a column-major tensor is one
-    already -- S = Y_(n) Y_(n)^T and Z = U^T Y_(n) by the vendor FP32 GEMM,
-    this library's eigensolver, Z folded back) against the matricization-free
-    path with FP32 products (recipe fp32).  Time per decomposition and the
-    peak device memory each needs beyond the input."""
+def explicit_sthosvd(api, torch, Xd, ranks):
+    """st-HOSVD with explicit matricization (the comparison of Sec. V's
+    Fig. 8): per mode the working tensor is permuted into a contiguous
+    I_n x J_n matrix (mode 1 of a column-major tensor is one already),
+    S = Y_(n) Y_(n)^T and Z = U^T Y_(n) by the vendor FP32 GEMM, this
+    library's eigensolver on S, and Z folded back.  Returns (G, U)."""
     N = Xd.dim()
+    Y = Xd
+    Us = []
+    for n in range(N):
+        I = Y.shape[n]
+        Yn = Y.movedim(n, 0).reshape(I, -1)          # copies unless it is a view already
+        S = torch.matmul(Yn, Yn.t()).double().t()      # symmetric: the column-major view
+        U, _, _ = api.eig_leading(S, ranks[n], s_unit=2.0 ** -24)   # S from FP32 products
+        Z = torch.matmul(U.t().float(), Yn)          # R x J_n
+        others = [Y.shape[m] for m in range(N) if m != n]
+        Y = Z.reshape(ranks[n], *others).movedim(0, n)
+        Us.append(U)
+    return Y, Us
+
+
+def bench_ablation(api, torch, Xd, ranks, reps=3):
+    """The comparison of Sec. V's Fig. 8 on this device: explicit_sthosvd
+    against the matricization-free path with FP32 products (recipe fp32).
+    Time per decomposition and the peak device memory each needs beyond the
+    input."""
     dev = Xd.device
 
     def explicit():
-        Y = Xd
-        for n in range(N):
-            I = Y.shape[n]
-            Yn = Y.movedim(n, 0).reshape(I, -1)          # copies unless it is a view already
-            S = torch.matmul(Yn, Yn.t()).double().t()      # symmetric: the column-major view
-            U, _, _ = api.eig_leading(S, ranks[n], s_unit=2.0 ** -24)   # S from FP32 products
-            Z = torch.matmul(U.t().float(), Yn)          # R x J_n
-            others = [Y.shape[m] for m in range(N) if m != n]
-            Y = Z.reshape(ranks[n], *others).movedim(0, n)
-        return Y
+        return explicit_sthosvd(api, torch, Xd, ranks)[0]
 
     def measure(fn):
         fn()

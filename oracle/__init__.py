@@ -222,6 +222,8 @@ def sthosvd(X, ranks, order=None, methods=None, L0=None, als_iters: int = 5,
     lp = (_dp * N)(*[_d(l) for l in lam])
     op = (ctypes.c_int * N)(*order) if order is not None else None
     mp = (ctypes.c_int * N)(*methods) if methods is not None else None
+    if methods is not None and any(m == 1 for m in methods) and L0 is None:
+        raise ValueError("ALS modes need their initial guesses L0 (Alg. 3 input)")
     if L0 is not None:
         L0 = [_f(l) if l is not None else np.zeros((dims[n], ranks[n]), order="F")
               for n, l in enumerate(L0)]

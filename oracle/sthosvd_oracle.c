@@ -514,6 +514,11 @@ int orc_sthosvd(int N, const i64 *dims, const i64 *ranks, const int *order,
             free(lv);
             free(V);
         } else {
+            /* ALS starts from the caller's initial guesses (Alg. 3 input) */
+            if (!L0 || !L0[n]) {
+                rc = -30;
+                break;
+            }
             int r = orc_als_mode(In, J, Rn, Yn, L0[n], als_iters, als_variant, U[n], On);
             if (r != 0) rc = -20 + r;
         }

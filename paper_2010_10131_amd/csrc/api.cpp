@@ -114,6 +114,7 @@ struct Step {
     int n;
     int64_t L, I, M, R;
     int solver;
+    bool chosen;   // solver picked by the selector (the memory model may move it to ALS)
     int src, dst;  // 0 = X, 1 = buffer A, 2 = buffer B, 3 = core
 };
 
@@ -146,6 +147,51 @@ static int gram_prec_of(const sth_plan_s &p) { return p.dtype == STH_F64 ? STH_P
 static size_t als_small_doubles(int64_t I, int64_t R) { return (size_t)(5 * I * R + 9 * R * R); }
 
 static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_out, size_t *ws_out);
+
+// Workspace bytes a step needs for the EIG branch beyond the ping-pong
+// buffers: the Gram partial sums, the I_n x I_n Gram and the eigensolver.
+static size_t eig_step_bytes(const sth_plan_s &p, const Step &st) {
+    (void)p;
+    return gram_ws_bytes(st.I, st.I, st.L * st.M, true) + (size_t)(st.I * st.I) * sizeof(double) + eig_ws_bytes(st.I);
+}
+
+// Workspace offsets of a plan from its steps and their solvers.
+static void plan_layout(sth_plan_s &pl) {
+    size_t maxA = 0, maxB = 0, maxZ = 0, maxPart = 0, maxS = 0, maxEig = 0, maxUq = 0, maxSmall = 0, maxGemm = 0;
+    const int tp = ttm_prec_of(pl);
+    for (const Step &stp : pl.steps) {
+        const size_t out_elems = (size_t)(stp.L * stp.R * stp.M);
+        if (stp.dst == 1) maxA = std::max(maxA, out_elems);
+        if (stp.dst == 2) maxB = std::max(maxB, out_elems);
+        const int64_t P = stp.L * stp.M;
+        if (stp.solver == STH_SOLVER_EIG) {
+            maxPart = std::max(maxPart, gram_ws_bytes(stp.I, stp.I, P, true));
+            maxS = std::max(maxS, (size_t)(stp.I * stp.I) * sizeof(double));
+            maxEig = std::max(maxEig, eig_ws_bytes(stp.I));
+            maxUq = std::max(maxUq, ttm_prep_bytes(stp.I, stp.R, tp));
+        } else {
+            maxZ = std::max(maxZ, out_elems);
+            maxPart = std::max(maxPart, gram_ws_bytes(stp.I, stp.R, P, false));
+            maxUq = std::max(maxUq, std::max(ttm_prep_bytes(stp.I, stp.R, tp), ttm_prep_bytes(stp.R, stp.R, tp)));
+            maxSmall = std::max(maxSmall, als_small_doubles(stp.I, stp.R) * sizeof(double));
+            const int I = (int)stp.I, R = (int)stp.R;
+            maxGemm = std::max({maxGemm, gemm_ws_bytes(R, R, I), gemm_ws_bytes(I, R, R), gemm_ws_bytes(R, R, R)});
+        }
+    }
+    Arena a;
+    pl.o_flag = a.take(256);
+    pl.o_bufA = a.take(maxA * esize(pl.dtype));
+    pl.o_bufB = a.take(maxB * esize(pl.dtype));
+    pl.o_bufZ = a.take(maxZ * esize(pl.dtype));
+    pl.o_part = a.take(maxPart);
+    pl.o_S = a.take(maxS);
+    pl.o_eig = a.take(maxEig);
+    pl.o_uq = a.take(maxUq);
+    pl.o_small = a.take(maxSmall);
+    pl.o_gemm = a.take(maxGemm);
+    pl.o_sum = a.take(SUMSQ_BLOCKS * sizeof(double));
+    pl.total = a.off;
+}
 
 extern "C" sth_status sthosvd_plan(const sth_desc *d, sth_plan **plan_out, size_t *ws_out) {
     return make_plan(d, MAX_ORDER, plan_out, ws_out);
@@ -193,7 +239,6 @@ static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_ou
 
     // shapes on the current working tensor, solver choice (Alg. 2 line 3)
     std::vector<int64_t> cur = p->dims;
-    size_t maxA = 0, maxB = 0, maxZ = 0, maxPart = 0, maxS = 0, maxEig = 0, maxUq = 0, maxSmall = 0, maxGemm = 0;
     const int nsteps = std::min(N, max_steps);
     for (int s = 0; s < nsteps; ++s) {
         Step stp;
@@ -209,6 +254,7 @@ static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_ou
                 return fail(STH_ERR_INVALID, "per_mode[%d] = %d", stp.n, solver);
             }
         }
+        const bool chosen = solver == STH_SOLVER_AUTO || solver == STH_SOLVER_AUTO_TREE;
         if (solver == STH_SOLVER_AUTO) {
             solver = selector_choose(stp.I, stp.R, stp.L * stp.M, N, d->mlp_weights);
         } else if (solver == STH_SOLVER_AUTO_TREE) {
@@ -227,43 +273,33 @@ static sth_status make_plan(const sth_desc *d, int max_steps, sth_plan **plan_ou
             return fail(STH_ERR_UNSUPPORTED, "ALS mode %d: R_n = %lld exceeds the rank bound %lld of the unfolding (its normal equations are singular; use EIG)", stp.n, (long long)stp.R, (long long)(stp.L * stp.M));
         }
         stp.solver = solver;
-        p->solver_of_mode[stp.n] = solver;
+        stp.chosen = chosen;
         stp.src = (s == 0) ? 0 : ((s - 1) % 2 == 0 ? 1 : 2);
         stp.dst = (s == nsteps - 1) ? 3 : (s % 2 == 0 ? 1 : 2);
-        const size_t out_elems = (size_t)(stp.L * stp.R * stp.M);
-        if (stp.dst == 1) maxA = std::max(maxA, out_elems);
-        if (stp.dst == 2) maxB = std::max(maxB, out_elems);
-        const int64_t P = stp.L * stp.M;
-        const int tp = ttm_prec_of(*p);
-        if (solver == STH_SOLVER_EIG) {
-            maxPart = std::max(maxPart, gram_ws_bytes(stp.I, stp.I, P, true));
-            maxS = std::max(maxS, (size_t)(stp.I * stp.I) * sizeof(double));
-            maxEig = std::max(maxEig, eig_ws_bytes(stp.I));
-            maxUq = std::max(maxUq, ttm_prep_bytes(stp.I, stp.R, tp));
-        } else {
-            maxZ = std::max(maxZ, out_elems);
-            maxPart = std::max(maxPart, gram_ws_bytes(stp.I, stp.R, P, false));
-            maxUq = std::max(maxUq, std::max(ttm_prep_bytes(stp.I, stp.R, tp), ttm_prep_bytes(stp.R, stp.R, tp)));
-            maxSmall = std::max(maxSmall, als_small_doubles(stp.I, stp.R) * sizeof(double));
-            const int I = (int)stp.I, R = (int)stp.R;
-            maxGemm = std::max({maxGemm, gemm_ws_bytes(R, R, I), gemm_ws_bytes(I, R, R), gemm_ws_bytes(R, R, R)});
-        }
         cur[stp.n] = stp.R;
         p->steps.push_back(stp);
     }
-    Arena a;
-    p->o_flag = a.take(256);
-    p->o_bufA = a.take(maxA * esize(p->dtype));
-    p->o_bufB = a.take(maxB * esize(p->dtype));
-    p->o_bufZ = a.take(maxZ * esize(p->dtype));
-    p->o_part = a.take(maxPart);
-    p->o_S = a.take(maxS);
-    p->o_eig = a.take(maxEig);
-    p->o_uq = a.take(maxUq);
-    p->o_small = a.take(maxSmall);
-    p->o_gemm = a.take(maxGemm);
-    p->o_sum = a.take(SUMSQ_BLOCKS * sizeof(double));
-    p->total = a.off;
+    plan_layout(*p);
+    // memory model: over the cap, the modes the selector sent to EIG move to
+    // ALS (where ALS applies), the one with the largest EIG footprint (the
+    // I_n^2 Gram, its partial sums and the eigensolver scratch) first
+    while (d->workspace_cap > 0 && p->total > (size_t)d->workspace_cap) {
+        Step *best = nullptr;
+        size_t best_bytes = 0;
+        for (Step &st : p->steps) {
+            if (!st.chosen || st.solver != STH_SOLVER_EIG) continue;
+            if (st.R > MAX_ALS_R || st.R > st.L * st.M) continue;
+            const size_t b = eig_step_bytes(*p, st);
+            if (!best || b > best_bytes) {
+                best = &st;
+                best_bytes = b;
+            }
+        }
+        if (!best) break;
+        best->solver = STH_SOLVER_ALS;
+        plan_layout(*p);
+    }
+    for (const Step &st : p->steps) p->solver_of_mode[st.n] = st.solver;
     if (d->workspace_cap > 0 && p->total > (size_t)d->workspace_cap) {
         size_t need = p->total;
         delete p;

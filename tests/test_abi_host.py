@@ -84,6 +84,27 @@ def test_als_above_the_rank_bound_of_the_unfolding():
     assert _plan(dims=(64, 2, 2), ranks=(4, 2, 2), per_mode=("als", "eig", "eig")).solvers == [1, 0, 0]
 
 
+def test_memory_model_moves_selected_eig_modes_to_als():
+    """Under a workspace cap the learned selectors' EIG modes move to ALS,
+    the largest EIG footprint (I_n^2 Gram, partial sums, eigensolver) first,
+    until the plan fits; an explicit EIG request over the cap is NOMEM."""
+    import torch
+    from paper_2010_10131_amd import _lib
+    dims, ranks = (512, 64, 64), (32, 8, 8)
+    for solver in ("auto", "auto_tree"):
+        free = _plan(dims=dims, ranks=ranks, solver=solver)
+        assert free.solvers == [0, 0, 0]
+        als1 = _plan(dims=dims, ranks=ranks, per_mode=("als", "eig", "eig"))
+        assert als1.workspace_bytes < free.workspace_bytes
+        capped = _plan(dims=dims, ranks=ranks, solver=solver, workspace_cap=als1.workspace_bytes)
+        assert capped.solvers == [1, 0, 0]
+        assert capped.workspace_bytes <= als1.workspace_bytes
+        # a cap nothing fits under stays NOMEM
+        assert _err(dims=dims, ranks=ranks, solver=solver, workspace_cap=1 << 20) == _lib.STH_ERR_NOMEM
+    assert _err(dims=dims, ranks=ranks, per_mode=("eig", "eig", "eig"),
+                workspace_cap=als1.workspace_bytes) == _lib.STH_ERR_NOMEM
+
+
 def test_plan_shapes_solvers_and_workspace():
     import torch
     p = _plan()
