@@ -64,6 +64,11 @@ def main():
                     help="skip the explicit-matricization comparison (512^3, FP32 products)")
     ap.add_argument("--no-hooi", action="store_true",
                     help="skip the HOOI refinement measurement (512^3, from the headline factors)")
+    ap.add_argument("--no-c3", action="store_true",
+                    help="skip the 4-way 160^4 workload (every recipe, EIG and ALS per mode)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run only the dominant kernels a few times (for rocprofv3 counter passes): "
+                         "512^3 mode-1 TTM and Gram, a 512 MiB copy, the skinny mode-1 Grams of 160^4 and 48^5")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -74,6 +79,9 @@ def main():
     from paper_2010_10131_amd import api
 
     dev = torch.device("cuda:0")
+    if args.kernels_only:
+        kernels_only(api, torch, dev)
+        return
     w = wl.C2
     t0 = time.time()
     X = wl.make(w)
@@ -215,6 +223,10 @@ def main():
     if not args.no_selector:
         selector = bench_selector(api, torch, dev, gp, tp)
 
+    c3 = None
+    if not args.no_c3:
+        c3 = bench_c3(api, torch, dev, with_oracle=not args.no_cpu_baseline)
+
     fp32_ms = results[fp32_name]["ms"]
     ttm_traffic = None
     if tp == TTM_PMC["ttm"]:
@@ -257,6 +269,7 @@ def main():
         "selector": selector,
         "hooi": hooi,
         "explicit_matricization": ablation,
+        "c3": c3,
     }
     print(json.dumps(out))
 
@@ -468,6 +481,11 @@ def bench_selector(api, torch, dev, gp, tp, reps=3):
         per_mode.append(row)
         Y = z_best
     exh_ms, _ = timed(per_mode=choice)
+    grams = {}
+    for prec in ("fp32", "bf16x3"):
+        us, gbs = skinny_gram(api, torch, X, prec)
+        grams[prec] = {"us": us, "x_read_gbps": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS}
+        log(f"[bench] c5 skinny gram mode-1 {prec}: {us:.1f} us, {gbs:.0f} GB/s")
     log(f"[bench] selector on {w.name}: auto {auto_choice} {auto_ms:.2f} ms, "
         f"auto_tree {tree_choice} {tree_ms:.2f} ms, exhaustive {choice} "
         f"{exh_ms:.2f} ms, always-eig {eig_ms:.2f} ms, always-als {als_ms:.2f} ms")
@@ -476,7 +494,132 @@ def bench_selector(api, torch, dev, gp, tp, reps=3):
             "always_als_ms": als_ms, "regret": auto_ms / exh_ms - 1.0,
             "auto_tree_ms": tree_ms, "auto_tree_choice": tree_choice,
             "auto_tree_regret": tree_ms / exh_ms - 1.0, "per_mode_steps": per_mode,
+            "skinny_gram_mode1": grams,
             "data": "device-drawn low-rank + 1e-4 noise (same recipe as the host generator)"}
+
+
+
+def skinny_gram(api, torch, X, prec, reps=10):
+    """Mode-1 Gram of a tensor whose first mode is short (I_1 << J_1): an HBM
+    stream of X.  Returns (us per launch, GB/s of X read)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        api.gram_mode_n(X, 0, prec)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        api.gram_mode_n(X, 0, prec)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    return us, X.numel() * X.element_size() / (us * 1e-6) / 1e9
+
+
+def bench_c3(api, torch, dev, with_oracle=True, reps=3):
+    """The 4-way 160^4 FP32 workload (ranks 16, core 2^-k per mode index,
+    1e-5 noise): every precision recipe with EIG on every mode, ALS on every
+    mode, and the learned choice; T2 = ||X^ - X^_oracle|| / ||X|| against
+    the FP64 oracle (EIG, explicit matricization, Jacobi); and the skinny
+    mode-1 Gram (160 x 4.1M, HBM-bound) in each product precision."""
+    w = wl.C3
+    t0 = time.time()
+    X = wl.make(w)
+    log(f"[bench] generated {w.name} in {time.time() - t0:.1f}s")
+    Xd = api.to_device(X, dev)
+    N = len(w.dims)
+    ref = xnorm = None
+    oracle_s = None
+    if with_oracle:
+        import oracle
+        oracle.build()
+        t = time.perf_counter()
+        Go, Uo, _ = oracle.sthosvd(X, w.ranks)
+        oracle_s = time.perf_counter() - t
+        ref = oracle.reconstruct(Go, Uo)
+        xnorm = float(np.linalg.norm(X.astype(np.float64)))
+        del Go, Uo
+        log(f"[bench] c3 oracle {oracle_s:.1f}s")
+    del X
+
+    def run(gp, tp, **kw):
+        plan = api.Plan(w.dims, w.ranks, torch.float32, gp, tp, **kw)
+        G = api.fortran_empty(w.ranks, torch.float32, dev)
+        U = [api.fortran_empty((w.dims[n], w.ranks[n]), torch.float64, dev) for n in range(N)]
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+        entry = {"gram": gp, "ttm": tp, "solvers": ["eig" if v == 0 else "als" for v in plan.solvers]}
+        try:
+            plan.run(Xd, G, U, ws)
+            plan.check(ws)
+        except Exception as e:   # a numerical failure of this recipe is a result, not an error
+            entry["failed"] = str(e)[:160]
+            return entry
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            plan.run(Xd, G, U, ws)
+        torch.cuda.synchronize()
+        entry["ms"] = (time.perf_counter() - t) * 1e3 / reps
+        if ref is not None:
+            import oracle
+            Xh = oracle.reconstruct(api.to_numpy(G), [api.to_numpy(u) for u in U])
+            entry["t2"] = float(np.linalg.norm(Xh - ref) / xnorm)
+        return entry
+
+    recipes = RECIPES + [("fp64gram_bf16x3", "fp64", "bf16x3", "mixed")]
+    eig = {}
+    for name, gp, tp, _ in recipes:
+        eig[name] = run(gp, tp, solver="eig")
+        log(f"[bench] c3 eig {name}: {eig[name]}")
+    als = {}
+    for name, gp, tp in (("fp32_gram64", "fp64", "fp32"), ("bf16x3", "bf16x3", "bf16x3")):
+        als[name] = run(gp, tp, solver="als")
+        log(f"[bench] c3 als {name}: {als[name]}")
+    ok = [(v["ms"], k) for k, v in eig.items() if "ms" in v and v.get("t2", 0.0) <= T2_BAR]
+    best = min(ok)[1] if ok else None
+    auto = None
+    if best:
+        auto = run(eig[best]["gram"], eig[best]["ttm"], solver="auto")
+        log(f"[bench] c3 auto ({best}): {auto}")
+    grams = {}
+    for prec in ("fp32", "bf16x3", "bf16x6", "fp64"):
+        us, gbs = skinny_gram(api, torch, Xd, prec)
+        grams[prec] = {"us": us, "x_read_gbps": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS}
+        log(f"[bench] c3 skinny gram mode-1 {prec}: {us:.1f} us, {gbs:.0f} GB/s")
+    return {"workload": w.name, "dims": list(w.dims), "ranks": list(w.ranks), "eig": eig, "als": als,
+            "auto": auto, "best_eig_recipe": best, "t2_bar": T2_BAR, "oracle_s": oracle_s,
+            "skinny_gram_mode1": grams,
+            "data": "synthetic low-rank (core 2^-(i+j+k+l)) + 1e-5 relative noise, seeded"}
+
+
+def kernels_only(api, torch, dev, reps=5):
+    """The dominant kernels alone, reps launches each, for rocprofv3 counter
+    passes: 512^3 mode-1 TTM (bf16x3, prepared factor) and Gram (bf16x3,
+    bf16x6), a 512 MiB device copy (calibration of the byte counters), and
+    the skinny mode-1 Grams of the 160^4 and 48^5 workloads."""
+    w = wl.C2
+    X = wl.lowrank_plus_noise_device(w.dims, w.ranks, w.decay, w.nu, w.seed, dev)
+    U0 = torch.linalg.qr(torch.randn(w.dims[0], w.ranks[0], dtype=torch.float64, device=dev))[0]
+    U0 = U0.t().contiguous().t()
+    U0p = api.ttm_factor_prepare(U0, "bf16x3")
+    Z = api.ttm_mode_n_prepared(X, U0p, 0, w.ranks[0], "bf16x3")
+    for _ in range(reps):
+        api.ttm_mode_n_prepared(X, U0p, 0, w.ranks[0], "bf16x3", out=Z)
+    Y = torch.empty_like(X)
+    for _ in range(reps):
+        Y.copy_(X)
+    del Y
+    for prec in ("bf16x3", "bf16x6"):
+        for _ in range(reps):
+            api.gram_mode_n(X, 0, prec)
+    del X, Z
+    for wk in (wl.C3, wl.C5):
+        Xs = wl.lowrank_plus_noise_device(wk.dims, wk.ranks, wk.decay, wk.nu, wk.seed, dev)
+        for prec in ("fp32", "bf16x3"):
+            for _ in range(reps):
+                api.gram_mode_n(Xs, 0, prec)
+        del Xs
+    torch.cuda.synchronize()
+    log("[bench] kernels-only pass done")
 
 
 if __name__ == "__main__":

@@ -308,6 +308,12 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
         }
         for (int i = tid; i < 2 * n; i += TE_T) s_v[i] = 0.0;
         for (int i = tid; i < n; i += TE_T) s_vw[i] = make_double2(0.0, 0.0);
+        // s_p (unused by this path) carries the next owner's column: column
+        // k + 1 as updated through step k - 1, staged by the wave holding it
+        if (wave == 0)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                if (lane + 64 * h < n) s_p[lane + 64 * h] = ar[h][0];
         __syncthreads();
         double Kprev = 0.0;
         for (int k = 0; k + 2 < n; ++k) {
@@ -345,11 +351,8 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
                 double col[2];
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
-                    double c = 0.0;
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        if (q == qk) c = ar[h][q];
-                    col[h] = c - (vpr[h] * wpk + wr[h] * vpk);
+                    const int i = lane + 64 * h;
+                    col[h] = (i < n ? s_p[i] : 0.0) - (vpr[h] * wpk + wr[h] * vpk);
                 }
                 double sig = 0.0;
 #pragma unroll
@@ -363,10 +366,12 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
                 const double x0 = te_lane(h1 ? col[1] : col[0], l1);
                 double beta = x0, tau = 0.0, scl = 0.0;
                 if (sig > 0.0) {
+                    // reciprocals refined by a Newton step in place of the
+                    // divisions (H stays orthogonal to working accuracy)
                     const double nrm = sqrt(x0 * x0 + sig);
                     beta = x0 >= 0.0 ? -nrm : nrm;
-                    tau = (beta - x0) / beta;
-                    scl = 1.0 / (x0 - beta);
+                    tau = (beta - x0) * te_rcp(beta);
+                    scl = te_rcp(x0 - beta);
                 }
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
@@ -422,6 +427,16 @@ __device__ void teig_body(const double *__restrict__ S, int64_t lds, int n, int 
             for (int h = 0; h < 2; ++h) {
                 const int i = lane + 64 * h;
                 if (i < n) part[wave * n + i] = acc[h];
+            }
+            if (wave == (k + 1) % TE_W && k + 1 < n) {
+                const int q1 = (k + 1) / TE_W;   // uniform: a branch chain, no lane selects
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (q == q1) {
+#pragma unroll
+                        for (int h = 0; h < 2; ++h)
+                            if (lane + 64 * h < n) s_p[lane + 64 * h] = ar[h][q];
+                    }
             }
             __syncthreads();
         }
