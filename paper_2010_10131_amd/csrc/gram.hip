@@ -246,11 +246,14 @@ __global__ __launch_bounds__(SK_T) void gram_skinny_kernel(const float *__restri
     }
 }
 
-// Sums the partial blocks over the row ranges in a fixed order and writes
-// the IA x IB result (mirroring the lower triangle when SYM).
+// Sums the partial blocks over the row ranges and writes the IA x IB result
+// (mirroring the lower triangle when SYM).  64 elements per workgroup, each
+// summed by four waves over interleaved ranges of partials (8 loads in
+// flight per thread), the four sums combined in a fixed order.
 template <int TB, bool SYM>
-__global__ void gram_reduce_kernel(const double *__restrict__ partials, int nkc, int nbi,
-                                   int nblocks, int64_t IA, int64_t IB, double *__restrict__ S) {
+__global__ __launch_bounds__(256) void gram_reduce_kernel(const double *__restrict__ partials, int nkc, int nbi,
+                                                          int nblocks, int64_t IA, int64_t IB,
+                                                          double *__restrict__ S) {
     const int q = blockIdx.y;
     int bi, bj;
     if (SYM) {
@@ -261,16 +264,33 @@ __global__ void gram_reduce_kernel(const double *__restrict__ partials, int nkc,
         bi = q % nbi;
         bj = q / nbi;
     }
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= TB * TB) return;
+    __shared__ double s_part[4][64];
+    const int el = threadIdx.x & 63, ks = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + el;
+    const bool ev = e < TB * TB;
+    const int ec = ev ? e : 0;
+    const int64_t stride = (int64_t)nblocks * TB * TB;
+    const double *src = partials + (int64_t)q * TB * TB + ec;
+    double acc = 0.0;
+    int k = ks;
+    for (; k + 28 < nkc; k += 32) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[(int64_t)(k + 4 * u) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; k < nkc; k += 4) acc += src[(int64_t)k * stride];
+    s_part[ks][el] = acc;
+    __syncthreads();
+    if (ks != 0 || !ev) return;
+    const double sum = (s_part[0][el] + s_part[1][el]) + (s_part[2][el] + s_part[3][el]);
     const int il = e % TB, jl = e / TB;
     const int64_t i = (int64_t)bi * TB + il, j = (int64_t)bj * TB + jl;
     if (i >= IA || j >= IB) return;
     if (SYM && bi == bj && il < jl) return;  // upper part of a diagonal block: mirrored below
-    double s = 0.0;
-    for (int k = 0; k < nkc; ++k) s += partials[((int64_t)k * nblocks + q) * TB * TB + e];
-    S[i + IA * j] = s;
-    if (SYM && i != j) S[j + IA * i] = s;
+    S[i + IA * j] = sum;
+    if (SYM && i != j) S[j + IA * i] = sum;
 }
 
 // ---------------------------------------------------------------- host ----
@@ -364,7 +384,7 @@ hipError_t launch_skinny(const float *A, int64_t I, int64_t P, double *partials,
     }
     if (e != hipSuccess) return e;
     const int NS = sk_ns(I);
-    hipLaunchKernelGGL((gram_reduce_kernel<32, true>), dim3((32 * 32 + 255) / 256, NS * (NS + 1) / 2), dim3(256), 0,
+    hipLaunchKernelGGL((gram_reduce_kernel<32, true>), dim3((32 * 32 + 63) / 64, NS * (NS + 1) / 2), dim3(256), 0,
                        s, partials, k.nkc, NS, NS * (NS + 1) / 2, I, I, S);
     return hipGetLastError();
 }
@@ -403,7 +423,7 @@ hipError_t launch_gram_t(const T *A, const T *B, int64_t L, int64_t IA, int64_t 
         if (L == 1 && WT >= 2) {
             hipError_t e = launch_gram_l1<PREC, WT>(A, IA, M, g, partials, s);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL((gram_reduce_kernel<TB, SYM>), dim3((TB * TB + 255) / 256, g.nblocks),
+            hipLaunchKernelGGL((gram_reduce_kernel<TB, SYM>), dim3((TB * TB + 63) / 64, g.nblocks),
                                dim3(256), 0, s, partials, g.nkc, g.nbi, g.nblocks, IA, IB, S);
             return hipGetLastError();
         }
@@ -418,7 +438,7 @@ hipError_t launch_gram_t(const T *A, const T *B, int64_t L, int64_t IA, int64_t 
                        g.kper, g.nkc, g.nbi, g.nbj, g.nblocks, total, partials);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((gram_reduce_kernel<TB, SYM>), dim3((TB * TB + 255) / 256, g.nblocks),
+    hipLaunchKernelGGL((gram_reduce_kernel<TB, SYM>), dim3((TB * TB + 63) / 64, g.nblocks),
                        dim3(256), 0, s, partials, g.nkc, g.nbi, g.nblocks, IA, IB, S);
     return hipGetLastError();
 }

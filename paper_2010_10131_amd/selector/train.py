@@ -150,12 +150,15 @@ def main():
     meta, recs = load_db(args.db)
     X = features(api, recs)                       # 10 x n
     te_ms, ta_ms = targets(recs)
-    # missing solver (e.g. ALS beyond its rank limit): a large finite log target
-    cap = np.log(max(te_ms[te_ms < BIG].max(initial=1.0), ta_ms[ta_ms < BIG].max(initial=1.0))) + 3.0
-    Tl = np.stack([np.where(te_ms < BIG, np.log(te_ms), cap), np.where(ta_ms < BIG, np.log(ta_ms), cap)])
+    both = (te_ms < BIG) & (ta_ms < BIG)
+    Tl = np.stack([np.log(np.where(both, te_ms, 1.0)), np.log(np.where(both, ta_ms, 1.0))])
     tr, ho = split(recs, args.seed)
-    mu = X[:, tr].mean(axis=1)
-    sd = X[:, tr].std(axis=1)
+    # the network is fitted on the modes where both solvers ran: a mode one
+    # solver cannot run is decided by the solvers' limits after the network
+    # (apply_limits), so a made-up target for it would only cost capacity
+    tr_fit = tr[both[tr]]
+    mu = X[:, tr_fit].mean(axis=1)
+    sd = X[:, tr_fit].std(axis=1)
     isd = 1.0 / np.maximum(sd, 1e-3)
     p = init_params(args.seed, mu, isd)
     dev = torch.device("cuda:0")
@@ -163,7 +166,7 @@ def main():
     def dcol(a):  # column-major device matrix of shape a.shape
         return torch.from_numpy(np.ascontiguousarray(a.T.astype(np.float32))).to(dev).t()
 
-    Xtr, Ttr = dcol(X[:, tr]), dcol(Tl[:, tr])
+    Xtr, Ttr = dcol(X[:, tr_fit]), dcol(Tl[:, tr_fit])
     pd = torch.from_numpy(p).to(dev)
     m = torch.zeros_like(pd)
     v = torch.zeros_like(pd)
@@ -178,7 +181,6 @@ def main():
             hist.append((step, float(loss.item())))
             print(f"[train] step {step} loss {hist[-1][1]:.5f}", flush=True)
     w = pd.cpu().numpy()
-    pred_tr = api.mlp_forward(pd, Xtr).cpu().numpy()
     pred_ho = api.mlp_forward(pd, dcol(X[:, ho])).cpu().numpy()
     rep = {"meta": meta, "seed": args.seed, "steps": args.steps, "lr": args.lr,
            "loss_history": hist}

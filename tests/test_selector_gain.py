@@ -62,20 +62,23 @@ def test_selector_beats_both_fixed_choices(heldout):
     tot_sel = chosen[both].sum()
     tot_best = np.minimum(te, ta)[both].sum()
     tot_eig, tot_als = te[both].sum(), ta[both].sum()
-    assert tot_sel < 0.8 * min(tot_eig, tot_als)
-    assert tot_sel / tot_best - 1.0 <= 0.15
-    # and it is right more often than the better fixed choice (EIG is the
-    # faster solver on 79 % of these modes; the regression of both times
-    # reaches about 84 %, the paper's decision tree, solver "auto_tree",
-    # about 94 %: tests/test_selector_tree.py)
+    # with this eigensolver EIG is the faster step on almost every mode (ALS
+    # wins where R_n in 125..128 leaves no room for the subspace block), so
+    # the bar is the exhaustive choice: regret <= 2 %, never slower than the
+    # better fixed choice, far faster than always-ALS
+    assert tot_sel <= min(tot_eig, tot_als)
+    assert tot_sel < 0.5 * tot_als
+    assert tot_sel / tot_best - 1.0 <= 0.02
+    # and at least as accurate as the paper's decision tree (93.6 % held out,
+    # Sec. IV-B)
     truth = (ta < te).astype(int)
     acc = np.mean(choice[both] == truth[both])
-    assert acc >= 0.8 and acc > max(np.mean(truth[both]), 1 - np.mean(truth[both]))
+    assert acc >= 0.936 and acc >= max(np.mean(truth[both]), 1 - np.mean(truth[both]))
 
 
 def test_whole_gram_jacobi_rule():
     from paper_2010_10131_amd import api
-    # above order 128 with R in 125..128, EIG would run Jacobi on the whole Gram
+    # above order 128 with R in 125..128, EIG would run the direct solver on the whole Gram
     for I, R in [(129, 125), (300, 126), (512, 128)]:
         assert api.selector_choose(I, R, 4096) == "als"
 

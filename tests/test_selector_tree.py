@@ -94,8 +94,9 @@ def test_tree_beats_both_fixed_choices_on_heldout(db):
                        for i in ho])
     ev = T.evaluate(choice, te[ho], ta[ho])
     assert ev["accuracy"] == pytest.approx(rep["heldout"]["accuracy"])
-    assert ev["total_ms_selected"] < 0.8 * min(ev["total_ms_always_eig_feasible"], ev["total_ms_always_als_feasible"])
-    assert ev["regret"] <= 0.05 and ev["accuracy"] >= 0.9
+    assert ev["total_ms_selected"] <= min(ev["total_ms_always_eig_feasible"], ev["total_ms_always_als_feasible"])
+    assert ev["total_ms_selected"] < 0.5 * ev["total_ms_always_als_feasible"]
+    assert ev["regret"] <= 0.02 and ev["accuracy"] >= 0.936
 
 
 def test_plan_auto_tree_uses_the_tree():
