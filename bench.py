@@ -40,8 +40,23 @@ T2_BAR = 1e-5
 # for a plain 512 MiB device copy of known size (fetch x 2.000, write x 1.000).
 # Source: profiles/ttm_mode1_512cubed_bf16x3_hbm_traffic.md.  Valid only for
 # that kernel as it is; None for any other TTM precision.
-TTM_PMC = {"ttm": "bf16x3", "fetch_kib": 262943.0, "fetch_scale": 2.000,
-           "write_kib": 66640.1, "write_scale": 1.000}
+TTM_PMC = {"ttm": "bf16x3", "fetch_kib": 262941.2, "fetch_scale": 2.000,
+           "write_kib": 66608.3, "write_scale": 1.000}
+# The same two passes over the skinny mode-1 Grams (bf16x3 products) of the
+# 160^4 and 48^5 workloads: KiB per dispatch, same scales.  Source:
+# profiles/gram_skinny_mode1_hbm_traffic.md.  Valid only for that kernel as it is.
+SKINNY_PMC = {"c3_160pow4_fp32": {"fetch_kib": 1280073.0, "write_kib": 30720.0},
+              "c5_48pow5_fp32": {"fetch_kib": 497765.0, "write_kib": 6144.0}}
+
+
+def skinny_traffic(workload, prec, us):
+    """HBM bytes of one skinny-Gram launch from the counters, and the rate
+    they give at the measured launch time (bf16x3 only)."""
+    c = SKINNY_PMC.get(workload)
+    if c is None or prec != "bf16x3":
+        return None
+    b = (c["fetch_kib"] * TTM_PMC["fetch_scale"] + c["write_kib"] * TTM_PMC["write_scale"]) * 1024
+    return {"hbm_bytes": b, "hbm_gbps": b / (us * 1e-6) / 1e9}
 
 
 def log(msg):
@@ -482,7 +497,8 @@ def bench_selector(api, torch, dev, gp, tp, reps=3):
     grams = {}
     for prec in ("fp32", "bf16x3"):
         us, gbs = skinny_gram(api, torch, X, prec)
-        grams[prec] = {"us": us, "x_read_gbps": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS}
+        grams[prec] = {"us": us, "x_read_gbps": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
+                       "counters": skinny_traffic(w.name, prec, us)}
         log(f"[bench] c5 skinny gram mode-1 {prec}: {us:.1f} us, {gbs:.0f} GB/s")
     log(f"[bench] selector on {w.name}: auto {auto_choice} {auto_ms:.2f} ms, "
         f"auto_tree {tree_choice} {tree_ms:.2f} ms, exhaustive {choice} "
@@ -624,7 +640,8 @@ def bench_c3(api, torch, dev, with_oracle=True, reps=3):
     grams = {}
     for prec in ("fp32", "bf16x3", "bf16x6", "fp64"):
         us, gbs = skinny_gram(api, torch, Xd, prec)
-        grams[prec] = {"us": us, "x_read_gbps": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS}
+        grams[prec] = {"us": us, "x_read_gbps": gbs, "frac_of_8tbs": gbs / HBM_PEAK_GBS,
+                       "counters": skinny_traffic(w.name, prec, us)}
         log(f"[bench] c3 skinny gram mode-1 {prec}: {us:.1f} us, {gbs:.0f} GB/s")
     return {"workload": w.name, "dims": list(w.dims), "ranks": list(w.ranks), "eig": eig, "als": als,
             "auto": auto, "best_eig_recipe": best, "t2_bar": T2_BAR, "oracle_s": oracle_s,

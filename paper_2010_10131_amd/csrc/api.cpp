@@ -1112,8 +1112,8 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             if (b.I > MAX_EIG_N)
                 return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: I_n = %lld exceeds the eigensolver limit %lld", t, s, (long long)b.I, (long long)MAX_EIG_N);
             if (b.R > 64) return fail(STH_ERR_UNSUPPORTED, "tensor %d mode %d: R_n > 64 in the batched path", t, s);
-            b.sib = 0;   // the direct solver for every order
-            maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.R));
+            b.sib = (int32_t)batch_si_block(b.I, b.R, b.L * b.M);
+            maxEig = std::max(maxEig, batch_eig_scratch(b.I, b.R, b.sib));
             b.nchunks = (int)((b.I + 31) / 32);
             b.ntiles = (int)((b.R + 15) / 16);
             b.rtb = b.ntiles <= 1 ? 1 : (b.ntiles <= 2 ? 2 : 4);
@@ -1146,7 +1146,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
         T.eig_lds = 0;
         T.max_nchunks = 0;
         for (int t = 0; t < count; ++t) {
-            T.eig_lds = std::max(T.eig_lds, batch_eig_lds(sd[s][t].I, sd[s][t].R));
+            T.eig_lds = std::max(T.eig_lds, batch_eig_lds(sd[s][t].I, sd[s][t].R, sd[s][t].sib));
             T.max_nchunks = std::max(T.max_nchunks, sd[s][t].nchunks);
         }
         auto make = [&](const std::vector<int32_t> &list, const std::vector<int64_t> &units, int cls) {

@@ -3,16 +3,22 @@
 //   grouped Gram      every (tensor, row range, output block) workgroup of
 //                     one tile class in one grid, XCD-aware ids;
 //   grouped reduce    the FP64 partial blocks of every tensor;
-//   batched eigen     one workgroup per tensor: the direct solver of
-//                     teig_body.h (tridiagonalization, bisection, inverse
-//                     iteration), the matrix in LDS up to order 128;
+//   batched eigen     one workgroup per tensor: up to order 128 the direct
+//                     solver of teig_body.h (tridiagonalization, bisection,
+//                     inverse iteration); above it a subspace iteration
+//                     inside the workgroup (FP64 matrix-core products,
+//                     shifted Cholesky-QR, Rayleigh-Ritz with the direct
+//                     solver on the p x p problem) accepted by the Ritz
+//                     residual test, the direct solver on S otherwise;
 //   grouped split     every factor into matrix-core quads;
 //   grouped TTM       workgroups assigned to tensors in proportion to rows.
 // Shapes, workspace offsets and launch prefix sums are fixed at plan time
 // and copied into the workspace at the start of a run; the caller's tensors
 // are reached through device arrays of pointers.  The run is enqueue-only
 // and graph-capturable.
+#include "chol_body.h"
 #include "common.h"
+#include "eig_body.h"
 #include "gram_body.h"
 #include "internal.h"
 #include "teig_body.h"
@@ -101,17 +107,238 @@ __global__ void batch_reduce_kernel(const BatchStep *__restrict__ descs,
 
 // C (m x n, ldc) = op(A) op(B) by one workgroup, 32 x 32 output tiles with
 // 32-deep LDS slabs (tile storage in the dynamic LDS).
+// ---- subspace iteration inside one workgroup (orders above 128) ----------
+// Scratch after the direct solver's (doubles): Q, Z, Z2 (n x p each), G, Rinv,
+// T, W (p x p each), th (p), res (R + 1), then the p x p direct solve's.
+__host__ __device__ inline size_t bsi_doubles(int64_t n, int64_t p, int64_t R) {
+    return (size_t)(3 * n * p + 4 * p * p + p + R + 1) + teig_scratch_doubles(p, R, true) + 64;
+}
+
+constexpr int BW = BE_THREADS / 64;   // waves
+
+// C (m x q) = A (m x k) B (k x q) on the FP64 matrix cores, 16 x 16 tiles dealt
+// to the waves, each tile's whole contraction in one wave (four steps' loads
+// issued together).  TRI_B: B upper triangular (k = q).  NS: C = 1.5 A - 0.5 A B.
+template <bool TRI_B, bool NS>
+__device__ void bsi_nn(int m, int q, int k, const double *__restrict__ A, int64_t lda,
+                       const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tr = lane & 15, tg = lane >> 4;
+    const int mt = (m + 15) >> 4, qt = (q + 15) >> 4;
+    for (int t = wave; t < mt * qt; t += BW) {
+        const int i0 = (t % mt) << 4, j0 = (t / mt) << 4;
+        const int kmax = TRI_B ? min(k, j0 + 16) : k;
+        const int ia = min(i0 + tr, m - 1), jb = min(j0 + tr, q - 1);
+        const bool rok = i0 + tr < m, cok = j0 + tr < q;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; 4 * s0 < kmax; s0 += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kk = 4 * (s0 + u) + tg;
+                const bool ok = kk < kmax;
+                const int kc = ok ? kk : 0;
+                a[u] = A[ia + lda * kc];
+                b[u] = B[kc + ldb * jb];
+                if (!(ok && rok)) a[u] = 0.0;
+                if (!(ok && cok)) b[u] = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+        }
+        const int col = j0 + tr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = i0 + tg + 4 * v;
+            if (row < m && col < q) C[row + ldc * col] = NS ? 1.5 * A[row + lda * col] - 0.5 * acc[v] : acc[v];
+        }
+    }
+}
+
+// C (p x q) = A^T B with A (k x p), B (k x q); SYM: B = A, tiles on and below
+// the diagonal, each written to both halves.
+template <bool SYM>
+__device__ void bsi_tn(int p, int q, int k, const double *__restrict__ A, int64_t lda,
+                       const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tr = lane & 15, tg = lane >> 4;
+    const int pt = (p + 15) >> 4, qt = (q + 15) >> 4;
+    const int ntile = SYM ? pt * (pt + 1) / 2 : pt * qt;
+    for (int t = wave; t < ntile; t += BW) {
+        int bi, bj;
+        if (SYM) {
+            bi = 0;
+            while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+            bj = t - bi * (bi + 1) / 2;
+        } else {
+            bi = t % pt;
+            bj = t / pt;
+        }
+        const int i0 = bi << 4, j0 = bj << 4;
+        const int ia = min(i0 + tr, p - 1), jb = min(j0 + tr, q - 1);
+        const bool rok = i0 + tr < p, cok = j0 + tr < q;
+        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int s0 = 0; 4 * s0 < k; s0 += 4) {
+            double a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int kk = 4 * (s0 + u) + tg;
+                const bool ok = kk < k;
+                const int kc = ok ? kk : 0;
+                a[u] = A[kc + lda * ia];
+                b[u] = B[kc + ldb * jb];
+                if (!(ok && rok)) a[u] = 0.0;
+                if (!(ok && cok)) b[u] = 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+        }
+        const int col = j0 + tr;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = i0 + tg + 4 * v;
+            if (row < p && col < q) {
+                C[row + ldc * col] = acc[v];
+                if (SYM && bi != bj) C[col + ldc * row] = acc[v];
+            }
+        }
+    }
+}
+
+struct BsiWs {
+    double *Q, *Z, *Z2, *G, *Rinv, *T, *W, *th, *res;
+    TeScratch te;
+};
+
+__device__ inline BsiWs bsi_layout(double *base, int n, int p, int R) {
+    BsiWs w;
+    double *d = (double *)(((uintptr_t)base + 255) & ~(uintptr_t)255);
+    w.Q = d; d += (int64_t)n * p;
+    w.Z = d; d += (int64_t)n * p;
+    w.Z2 = d; d += (int64_t)n * p;
+    w.G = d; d += p * p;
+    w.Rinv = d; d += p * p;
+    w.T = d; d += p * p;
+    w.W = d; d += p * p;
+    w.th = d; d += p;
+    w.res = d; d += R + 1;
+    w.te = teig_scratch_layout(d, p, R, true);
+    return w;
+}
+
+// One Cholesky-QR pass of the n x p matrix A into Q (shift_rel > 0: the
+// shifted pass of the shifted Cholesky-QR3 scheme).
+__device__ void bsi_cholqr(const double *A, double *Q, int n, int p, double shift_rel, BsiWs &w, int64_t *flag) {
+    bsi_tn<true>(p, p, n, A, n, A, n, w.G, p);
+    __syncthreads();
+    chol_body<BE_THREADS>(w.G, p, p, shift_rel, nullptr, w.Rinv, flag);
+    __syncthreads();
+    bsi_nn<true, false>(n, p, p, A, n, w.Rinv, p, Q, n);
+    __syncthreads();
+}
+
+// R leading eigenpairs of S (n > 128) into U by the subspace iteration of the
+// single-tensor path (2 products when S carries single-precision rounding,
+// 3 for FP64 data; intermediate bases: shifted + plain Cholesky-QR; the last:
+// + a Newton-Schulz step, or + a third plain pass for FP64 data) and
+// Rayleigh-Ritz with the direct solver on T = Q^T S Q.  Returns true when
+// every Ritz residual passes ||S u - theta u|| <= tol |theta_1|.
+__device__ bool bsi_solve(const double *S, int n, int R, int p, double s_unit, double *U, BsiWs &w,
+                          int64_t *flag, uint64_t stream) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const bool loose = s_unit >= 0x1p-24;
+    const int iters = loose ? 2 : 3;
+    for (int64_t e = tid; e < (int64_t)n * p; e += BE_THREADS) w.Q[e] = gaussian_value(0x5EED5EEDull, stream, (uint64_t)e);
+    __syncthreads();
+    const double shift = 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * p;
+    for (int it = 0; it < iters; ++it) {
+        bsi_nn<false, false>(n, p, n, S, n, w.Q, n, w.Z, n);
+        __syncthreads();
+        bsi_cholqr(w.Z, w.Z2, n, p, shift, w, flag);
+        if (it + 1 < iters) {
+            bsi_cholqr(w.Z2, w.Q, n, p, 0.0, w, flag);
+        } else if (loose) {
+            bsi_cholqr(w.Z2, w.Z, n, p, 0.0, w, flag);
+            bsi_tn<true>(p, p, n, w.Z, n, w.Z, n, w.G, p);
+            __syncthreads();
+            bsi_nn<false, true>(n, p, p, w.Z, n, w.G, p, w.Q, n);
+            __syncthreads();
+        } else {
+            bsi_cholqr(w.Z2, w.Z, n, p, 0.0, w, flag);
+            bsi_cholqr(w.Z, w.Q, n, p, 0.0, w, flag);
+        }
+    }
+    // Rayleigh-Ritz
+    bsi_nn<false, false>(n, p, n, S, n, w.Q, n, w.Z, n);
+    __syncthreads();
+    bsi_tn<false>(p, p, n, w.Q, n, w.Z, n, w.T, p);
+    __syncthreads();
+    if (teig_z_fits(p, R, true)) teig_body<true, true>(w.T, p, p, R, w.W, p, w.th, false, w.te, flag);
+    else teig_body<true, false>(w.T, p, p, R, w.W, p, w.th, false, w.te, flag);
+    __syncthreads();
+    // U = Q W with the sign rule, and the Ritz residuals (one wave per vector)
+    for (int r = wave; r < R; r += BW) {
+        const double t = w.th[r];
+        double ss = 0.0, best = -1.0, bval = 0.0;
+        int arg = 0;
+        for (int i = lane; i < n; i += 64) {
+            double u = 0.0, z = 0.0;
+            for (int k = 0; k < p; ++k) {
+                const double wk = w.W[k + (int64_t)p * r];
+                u += w.Q[i + (int64_t)n * k] * wk;
+                z += w.Z[i + (int64_t)n * k] * wk;
+            }
+            const double d = z - t * u;
+            ss += d * d;
+            U[i + (int64_t)n * r] = u;
+            if (fabs(u) > best) {
+                best = fabs(u);
+                arg = i;
+                bval = u;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            ss += __shfl_xor(ss, o);
+            const double b2 = __shfl_xor(best, o), v2 = __shfl_xor(bval, o);
+            const int a2 = __shfl_xor(arg, o);
+            if (b2 > best || (b2 == best && a2 < arg)) {
+                best = b2;
+                arg = a2;
+                bval = v2;
+            }
+        }
+        if (bval < 0.0)
+            for (int i = lane; i < n; i += 64) U[i + (int64_t)n * r] = -U[i + (int64_t)n * r];
+        if (lane == 0) w.res[r] = sqrt(ss);
+    }
+    __syncthreads();
+    const double tol = fmax(16.0 * sqrt((double)n) * 2.220446049250313e-16, s_unit) * fabs(w.th[0]);
+    int bad = 0;
+    for (int r = lane; r < R; r += 64)
+        if (!(w.res[r] <= tol)) bad = 1;
+    const bool ok = __ballot(bad) == 0;   // every wave reads the same values
+    __syncthreads();
+    return ok;
+}
+
 __global__ __launch_bounds__(BE_THREADS) void batch_eig_kernel(const BatchStep *__restrict__ descs,
                                                                char *__restrict__ ws,
                                                                double *const *__restrict__ Up,
-                                                               int order, int mode,
+                                                               int order, int mode, double s_unit,
                                                                int64_t *__restrict__ flag) {
     const BatchStep &d = descs[blockIdx.x];
     const int n = (int)d.I, R = (int)d.R;
     const double *S = (const double *)(ws + d.S_off);
     double *U = Up[(int64_t)d.tensor * order + mode];
     const bool alds = n <= TE_LDS_N, zlds = teig_z_fits(n, R, alds);
-    const TeScratch sc = teig_scratch_layout((double *)(ws + d.eig_off), n, R, alds);
+    double *const base = (double *)(ws + d.eig_off);
+    const TeScratch sc = teig_scratch_layout(base, n, R, alds);
+    if (d.sib > 0) {
+        // the subspace iteration; its scratch follows the direct solver's
+        BsiWs w = bsi_layout(base + teig_scratch_doubles(n, R, alds), n, d.sib, R);
+        if (bsi_solve(S, n, R, d.sib, s_unit, U, w, flag ? flag + 2 : nullptr,
+                      (uint64_t)n * 1000 + d.sib))
+            return;
+        if (threadIdx.x == 0 && flag) atomicAdd((unsigned long long *)(flag + 1), 1ull);   // direct solves taken
+    }
     if (alds) {
         if (zlds) teig_body<true, true>(S, n, n, R, U, n, nullptr, true, sc, flag);
         else teig_body<true, false>(S, n, n, R, U, n, nullptr, true, sc, flag);
@@ -184,12 +411,26 @@ size_t batch_gram_lds(int prec, int wt) {
     return std::max(l1, gen);
 }
 
-size_t batch_eig_lds(int64_t n, int64_t R) {
-    const bool alds = n <= TE_LDS_N;
-    return teig_lds_bytes(n, R, alds, teig_z_fits(n, R, alds), teig_v_keep(n, R, alds));
+int64_t batch_si_block(int64_t n, int64_t R, int64_t rank_bound) {
+    const int64_t p = si_block_host(n, R);
+    return (n > TE_LDS_N && p <= SI_BLOCK_MAX && p < n && R <= rank_bound) ? p : 0;
 }
 
-size_t batch_eig_scratch(int64_t n, int64_t R) { return teig_scratch_doubles(n, R, n <= TE_LDS_N) * 8; }
+size_t batch_eig_lds(int64_t n, int64_t R, int64_t p) {
+    const bool alds = n <= TE_LDS_N;
+    size_t b = teig_lds_bytes(n, R, alds, teig_z_fits(n, R, alds), teig_v_keep(n, R, alds));
+    if (p > 0) {
+        b = std::max(b, teig_lds_bytes(p, R, true, teig_z_fits(p, R, true), teig_v_keep(p, R, true)));
+        b = std::max(b, chol_lds_bytes(p));
+    }
+    return b;
+}
+
+size_t batch_eig_scratch(int64_t n, int64_t R, int64_t p) {
+    size_t d = teig_scratch_doubles(n, R, n <= TE_LDS_N);
+    if (p > 0) d += bsi_doubles(n, p, R);
+    return d * 8;
+}
 
 namespace {
 template <int PREC, int WT>
@@ -275,7 +516,7 @@ hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int 
             if (e != hipSuccess) return e;
         }
         hipLaunchKernelGGL(batch_eig_kernel, dim3((unsigned)sp.count), dim3(BE_THREADS), lds, s, t.descs, ws, Up,
-                           order, mode, flag);
+                           order, mode, gram_unit(gram_prec), flag);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     {

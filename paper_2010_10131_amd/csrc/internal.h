@@ -83,7 +83,7 @@ struct BatchStep {
     int64_t kper, gram_wg;
     int32_t nkc, nbi, nblocks, wt;
     int32_t nchunks, ntiles, rtb, contig;
-    int32_t tensor, sib;   // sib: unused (0)
+    int32_t tensor, sib;   // sib: subspace block of the eigensolve (0: the direct solver)
 };
 struct BatchLaunch {
     const int32_t *list;  // device: indices into the step's descriptors
@@ -103,8 +103,10 @@ struct BatchStepPlan {
     BatchLaunch prep;
 };
 size_t batch_gram_lds(int prec, int wt);
-size_t batch_eig_lds(int64_t n, int64_t R);      // dynamic LDS of the batched eigen workgroup
-size_t batch_eig_scratch(int64_t n, int64_t R);  // its global scratch (bytes)
+// subspace block of a batched eigensolve (0: the direct solver)
+int64_t batch_si_block(int64_t n, int64_t R, int64_t rank_bound);
+size_t batch_eig_lds(int64_t n, int64_t R, int64_t p);      // dynamic LDS of the batched eigen workgroup
+size_t batch_eig_scratch(int64_t n, int64_t R, int64_t p);  // its global scratch (bytes)
 hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int gram_prec,
                              int ttm_prec, int order, int mode, char *ws, const void *const *Xp,
                              void *const *Cp, double *const *Up, int64_t *flag, int max_sweeps,
