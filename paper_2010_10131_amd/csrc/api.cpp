@@ -1008,6 +1008,7 @@ struct BatchLaunchT {
     int len;
     int64_t total;
     int cls;
+    int l1 = 0;   // every tensor of the list has L = 1
 };
 struct BatchStepT {
     size_t descs_off;
@@ -1170,7 +1171,10 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
                     gb.push_back(sd[s][t].nblocks);
                 }
             if (!gl.empty()) {
-                T.gram.push_back(make(gl, gw, cls));
+                BatchLaunchT G = make(gl, gw, cls);
+                G.l1 = 1;
+                for (int32_t t : gl) G.l1 &= sd[s][t].L == 1 ? 1 : 0;
+                T.gram.push_back(G);
                 T.reduce.push_back(make(gl, gb, cls));
             }
             std::vector<int32_t> tl;
@@ -1250,6 +1254,7 @@ extern "C" sth_status sthosvd_run_batched(const sth_batch_plan *p, const void *c
         b.len = L.len;
         b.total = L.total;
         b.cls = L.cls;
+        b.l1 = L.l1;
         return b;
     };
     for (int s2 = 0; s2 < p->N; ++s2) {

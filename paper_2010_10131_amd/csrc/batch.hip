@@ -67,7 +67,14 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const BatchStep *__rest
     const int64_t local = lid - pref[k];
     const int64_t P = d.L * d.M;
     if (d.L == 1 && WT >= 2) {
-        if ((d.I & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0))
+        const bool v4 = (d.I & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
+        if constexpr (WT == 2) {
+            if (v4) {
+                gram_l1_body<PREC, 2, 2, 2, 2, true, false, true>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
+                return;
+            }
+        }
+        if (v4)
             gram_l1_body<PREC, WT, WT, 2, 2, true>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
         else
             gram_l1_body<PREC, WT, WT, 2, 2, false>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
@@ -75,6 +82,30 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const BatchStep *__rest
         gram_body<float, PREC, WT, true>(Y, Y, d.L, d.I, d.I, P, d.kper, d.nkc, d.nbi, d.nbi,
                                         d.nblocks, d.gram_wg, local, part);
     }
+}
+
+// The 128-wide class of a launch whose tensors all have L = 1 (the first mode
+// step): eight waves of 64 x 32 tiles, as the single-tensor mode-1 Gram, with
+// the 16-byte loads when I % 4 == 0.
+template <int PREC>
+__global__ __launch_bounds__(512) void batch_gram_l1w_kernel(const BatchStep *__restrict__ descs,
+                                                            const int32_t *__restrict__ list,
+                                                            const int64_t *__restrict__ pref, int len,
+                                                            int64_t total, char *__restrict__ ws,
+                                                            const void *const *__restrict__ Xp) {
+    const int64_t per_xcd = (total + 7) / 8;
+    const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (lid >= total) return;
+    const int k = find_segment(pref, len, lid);
+    const BatchStep &d = descs[list[k]];
+    const float *Y = bsrc(d, ws, Xp);
+    double *part = (double *)(ws + d.part_off);
+    const int64_t local = lid - pref[k];
+    const int64_t P = d.L * d.M;
+    if ((d.I & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0))
+        gram_l1_body<PREC, 4, 2, 2, 4, true, false, true>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
+    else
+        gram_l1_body<PREC, 4, 2, 2, 4, false>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
 }
 
 template <int TB>
@@ -451,6 +482,17 @@ template <int PREC>
 hipError_t launch_bgram_p(int wt, const BatchLaunch &bl, const BatchTables &t, char *ws,
                           const void *const *Xp, hipStream_t s) {
     const size_t lds = batch_gram_lds(PREC, wt);
+    if (wt == 4 && bl.l1) {
+        auto kern = batch_gram_l1w_kernel<PREC>;
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        const int64_t per_xcd = (bl.total + 7) / 8;
+        hipLaunchKernelGGL(kern, dim3((unsigned)(per_xcd * 8)), dim3(512), lds, s, t.descs, bl.list, bl.pref,
+                           bl.len, bl.total, ws, Xp);
+        return hipGetLastError();
+    }
     switch (wt) {
         case 1: return launch_bgram<PREC, 1>(bl, t, ws, Xp, lds, s);
         case 2: return launch_bgram<PREC, 2>(bl, t, ws, Xp, lds, s);

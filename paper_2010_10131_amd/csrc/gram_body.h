@@ -268,7 +268,16 @@ __device__ __forceinline__ void l1_store(uint8_t *slab, int TB, int g, int row, 
 // a diagonal block loads its one operand twice, from cache).  Branch-free
 // loads let the compiler wait for exactly the chunk being stored instead of
 // draining every load in flight before the next ones are issued.
-template <int PREC, int WTI, int WTJ, int WI, int WJ, bool VEC4, bool FULLI = false>
+// V4LD (batched mode-1 launches; I % 4 == 0 with aligned rows, any I): thread
+// (parity, operand, row quad iq, group g) owns rows 4 iq .. 4 iq + 3 of one
+// operand and the 8 columns g of every chunk of its parity (threads [0, 2 TB)
+// the even chunks, the rest the odd ones): eight 16-byte loads per chunk give
+// four rows' fragments (quads past I zeroed, their address clamped); the same
+// 32 values per thread as two chunks of two operands in flight.  Its LDS
+// stores are 64 bytes apart across lanes; where the matrix cores bound the
+// Gram (bf16x6 at I = 512) the FULLI loads are faster, so the single-tensor
+// path keeps those.
+template <int PREC, int WTI, int WTJ, int WI, int WJ, bool VEC4, bool FULLI = false, bool V4LD = false>
 __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_t I, int64_t P,
                                              int64_t kper, int nkc, int nblocks, int64_t total_wg,
                                              int64_t lid, double *__restrict__ partials) {
@@ -420,6 +429,57 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
         }
     };
 
+    if constexpr (V4LD) {
+        static_assert(NTH == 4 * TB, "one task per thread");
+        constexpr int TQ4 = TB / 4;
+        const int par4 = tid / (2 * TB), op4 = (tid / TB) & 1, iq4 = (tid % TB) % TQ4, g4 = (tid % TB) / TQ4;
+        // I % 4 == 0: a row quad is wholly inside or wholly past the last row
+        const bool rok4 = (op4 ? j0 : i0) + 4 * iq4 < I;
+        const float *src4 = Y + (rok4 ? (op4 ? j0 : i0) + 4 * iq4 : 0);
+        float rv[4][8];
+        auto load4 = [&](int cn) {
+            const int64_t pc = pbeg + (int64_t)(cn < nch ? cn : nch - 1) * KC;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int64_t pp = pc + 8 * g4 + j;
+                const int64_t pcl = pp < pend ? pp : pend - 1;
+                const float4 v = *reinterpret_cast<const float4 *>(src4 + I * pcl);
+                const bool in = rok4 && pp < pend;
+                rv[0][j] = in ? v.x : 0.f;
+                rv[1][j] = in ? v.y : 0.f;
+                rv[2][j] = in ? v.z : 0.f;
+                rv[3][j] = in ? v.w : 0.f;
+            }
+        };
+        auto store4 = [&](int buf) {
+            uint4 *sq = reinterpret_cast<uint4 *>(lds + (size_t)(buf * 2 + op4) * SLAB);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                FragQ<PREC> t;
+                make_frag(rv[rr], t.f);
+#pragma unroll
+                for (int qq = 0; qq < NQ; ++qq) sq[(qq * 4 + g4) * TB + 4 * iq4 + rr] = t.q[qq];
+            }
+        };
+        if (nch > 0) {
+            load4(par4);
+            if (par4 == 0) store4(0);
+        }
+        __syncthreads();
+        // chunk c in buffer 0 and chunk c + 1 in flight on the odd threads;
+        // every load and LDS store is issued unconditionally (clamped chunks
+        // past the end are stored and never multiplied)
+        for (int c = 0; c < nch; c += 2) {
+            if (par4 == 0) load4(c + 2);
+            compute(0, c);
+            if (par4 == 1) store4(1);
+            __syncthreads();
+            if (par4 == 1) load4(c + 3);
+            if (c + 1 < nch) compute(1, c + 1);
+            if (par4 == 0) store4(0);
+            __syncthreads();
+        }
+    } else {
     float4 ra0[LPT], rb0[LPT], ra1[LPT], rb1[LPT];
     auto prefetch = [&](int cn, float4 (&ra)[LPT], float4 (&rb)[LPT]) {
         if (FULLI) {
@@ -482,6 +542,7 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
             if (!diag) store(0, 1, rb0);
         }
         __syncthreads();
+    }
     }
     if (!active) return;
     double *dst = partials + ((int64_t)kc * nblocks + q) * (int64_t)TB * TB;

@@ -91,6 +91,7 @@ struct BatchLaunch {
     int len;
     int64_t total;
     int cls;  // tile class (Gram: WT; TTM: r-tiles per workgroup)
+    int l1;   // Gram: every tensor of the list has L = 1
 };
 struct BatchTables {
     const BatchStep *descs;  // device
