@@ -146,89 +146,188 @@ __host__ __device__ inline size_t bsi_doubles(int64_t n, int64_t p, int64_t R) {
 }
 
 constexpr int BW = BE_THREADS / 64;   // waves
+// Products of the iteration (operands contiguous column-major) stage their
+// shared operand through the dynamic LDS in slabs of BK contraction rows
+// (column stride BLD doubles: the 16 columns x 4 rows of a matrix-core
+// fragment then hit every bank twice, the minimum for 64 lanes of 8 bytes);
+// the next slab is prefetched into registers while the current one is
+// used.  Operands are read through buffer resources whose range check
+// returns zero past the matrix, so ragged edges need no selects.
+constexpr int BK = 32;
+constexpr int BLD = BK + 4;
+constexpr int BK_COLS = BE_THREADS / BK;        // slab columns per pass of the workgroup
+constexpr int BSI_PF = 128 / BK_COLS;           // passes for 128 columns
+static_assert(BK_COLS == 16, "a pass covers one 16-column tile");
+constexpr int BSI_OOB = 0x7FFFFFF0;             // byte offset past every operand
 
-// C (m x q) = A (m x k) B (k x q) on the FP64 matrix cores, 16 x 16 tiles dealt
-// to the waves, each tile's whole contraction in one wave (four steps' loads
-// issued together).  TRI_B: B upper triangular (k = q).  NS: C = 1.5 A - 0.5 A B.
+// LDS of the staged products for blocks of width p (two operand slabs)
+__host__ __device__ inline size_t bsi_stage_bytes(int64_t p) {
+    return (size_t)2 * 16 * ((p + 15) / 16) * BLD * sizeof(double);
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bsi_rsrc(const double *p, int64_t count) {
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, (int)(count * (int64_t)sizeof(double)), 0x00020000);
+}
+__device__ __forceinline__ double bsi_ld(__amdgpu_buffer_rsrc_t r, int byte_off) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, byte_off, 0, 0));
+}
+
+// rows k0 .. k0 + BK - 1 of the k x q matrix behind rb into registers (zero
+// outside it): the r-th value of a thread is column r * BK_COLS + tid / BK
+__device__ __forceinline__ void bsi_slab_load(double (&pf)[BSI_PF], __amdgpu_buffer_rsrc_t rb, int k, int q, int k0) {
+    const int kk = k0 + threadIdx.x % BK, c0 = threadIdx.x / BK;
+    const bool kok = kk < k;
+#pragma unroll
+    for (int r = 0; r < BSI_PF; ++r)
+        if (BK_COLS * r < q) pf[r] = bsi_ld(rb, kok ? 8 * (kk + k * (c0 + BK_COLS * r)) : BSI_OOB);
+}
+// columns below 16 * ceil(q / 16) into the slab (uniform in r)
+__device__ __forceinline__ void bsi_slab_store(const double (&pf)[BSI_PF], double *s, int q) {
+    const int kk = threadIdx.x % BK, c0 = threadIdx.x / BK;
+#pragma unroll
+    for (int r = 0; r < BSI_PF; ++r)
+        if (BK_COLS * r < q) s[kk + BLD * (c0 + BK_COLS * r)] = pf[r];
+}
+
+// C (m x q) = A (m x k) B (k x q), q <= 128, on the FP64 matrix cores: each
+// wave owns a 16-row strip and every column tile of it (up to 8
+// accumulators), its A fragments read from memory (16 consecutive rows per
+// column: coalesced), B staged slab by slab in the LDS for all waves.
+// TRI_B: B upper triangular (k = q; slabs below a tile's rows skipped).
+// NS: C = 1.5 A - 0.5 A B.
 template <bool TRI_B, bool NS>
-__device__ void bsi_nn(int m, int q, int k, const double *__restrict__ A, int64_t lda,
-                       const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc) {
+__device__ void bsi_nn(int m, int q, int k, const double *__restrict__ A, const double *__restrict__ B,
+                       double *__restrict__ C) {
+    extern __shared__ __align__(16) double s_st[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tr = lane & 15, tg = lane >> 4;
-    const int mt = (m + 15) >> 4, qt = (q + 15) >> 4;
-    for (int t = wave; t < mt * qt; t += BW) {
-        const int i0 = (t % mt) << 4, j0 = (t / mt) << 4;
-        const int kmax = TRI_B ? min(k, j0 + 16) : k;
-        const int ia = min(i0 + tr, m - 1), jb = min(j0 + tr, q - 1);
-        const bool rok = i0 + tr < m, cok = j0 + tr < q;
-        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int s0 = 0; 4 * s0 < kmax; s0 += 4) {
-            double a[4], b[4];
+    const int mt = (m + 15) >> 4, qt = (q + 15) >> 4, nsl = (k + BK - 1) / BK;
+    const __amdgpu_buffer_rsrc_t ra = bsi_rsrc(A, (int64_t)m * k), rb = bsi_rsrc(B, (int64_t)k * q);
+    for (int rd = 0; rd * BW < mt; ++rd) {
+        const int i0 = (rd * BW + wave) << 4;
+        const bool act = i0 < m;
+        // byte offset of this lane's row at contraction index 0 (past A when
+        // the row is out of range); the range check zeroes k >= k
+        const int abase = i0 + tr < m ? 8 * (i0 + tr) + 8 * m * tg : BSI_OOB;
+        const int astep = 8 * m * 4;
+        f64x4 acc[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int kk = 4 * (s0 + u) + tg;
-                const bool ok = kk < kmax;
-                const int kc = ok ? kk : 0;
-                a[u] = A[ia + lda * kc];
-                b[u] = B[kc + ldb * jb];
-                if (!(ok && rok)) a[u] = 0.0;
-                if (!(ok && cok)) b[u] = 0.0;
+        for (int j = 0; j < 8; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+        double pf[BSI_PF], a[BK / 4], an[BK / 4];
+        bsi_slab_load(pf, rb, k, q, 0);
+#pragma unroll
+        for (int u = 0; u < BK / 4; ++u) an[u] = bsi_ld(ra, abase == BSI_OOB ? BSI_OOB : abase + astep * u);
+        for (int sl = 0; sl < nsl; ++sl) {
+            const int k0 = sl * BK;
+            __syncthreads();   // every wave is done with the previous slab
+            bsi_slab_store(pf, s_st, q);
+#pragma unroll
+            for (int u = 0; u < BK / 4; ++u) a[u] = an[u];
+            __syncthreads();
+            if (sl + 1 < nsl) {
+                bsi_slab_load(pf, rb, k, q, k0 + BK);
+#pragma unroll
+                for (int u = 0; u < BK / 4; ++u)
+                    an[u] = bsi_ld(ra, abase == BSI_OOB ? BSI_OOB : abase + astep * ((k0 + BK) / 4 + u));
             }
+            if (act) {
+                // one uniform branch per tile and slab; TRI_B skips the
+                // slabs below the tile's last row of B
 #pragma unroll
-            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+                for (int j = 0; j < 8; ++j) {
+                    if (j < qt && (!TRI_B || k0 < 16 * j + 16)) {
+#pragma unroll
+                        for (int u = 0; u < BK / 4; ++u) {
+                            const double b = s_st[4 * u + tg + BLD * (16 * j + tr)];
+                            acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b, acc[j], 0, 0, 0);
+                        }
+                    }
+                }
+            }
         }
-        const int col = j0 + tr;
+        if (act) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = i0 + tg + 4 * v;
-            if (row < m && col < q) C[row + ldc * col] = NS ? 1.5 * A[row + lda * col] - 0.5 * acc[v] : acc[v];
+            for (int j = 0; j < 8; ++j) {
+                const int col = 16 * j + tr;
+                if (j < qt && col < q) {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = i0 + tg + 4 * v;
+                        if (row < m) C[row + (int64_t)m * col] = NS ? 1.5 * A[row + (int64_t)m * col] - 0.5 * acc[j][v] : acc[j][v];
+                    }
+                }
+            }
         }
     }
 }
 
-// C (p x q) = A^T B with A (k x p), B (k x q); SYM: B = A, tiles on and below
-// the diagonal, each written to both halves.
+// C (p x q) = A^T B with A (k x p), B (k x q), p, q <= 128: both operands
+// staged slab by slab in the LDS, the output tiles dealt to the waves (up to
+// 8 each).  SYM: B = A, tiles on and below the diagonal, each written to
+// both halves.
 template <bool SYM>
-__device__ void bsi_tn(int p, int q, int k, const double *__restrict__ A, int64_t lda,
-                       const double *__restrict__ B, int64_t ldb, double *__restrict__ C, int64_t ldc) {
+__device__ void bsi_tn(int p, int q, int k, const double *__restrict__ A, const double *__restrict__ B,
+                       double *__restrict__ C) {
+    extern __shared__ __align__(16) double s_st[];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, tr = lane & 15, tg = lane >> 4;
-    const int pt = (p + 15) >> 4, qt = (q + 15) >> 4;
+    const int pt = (p + 15) >> 4, qt = (q + 15) >> 4, nsl = (k + BK - 1) / BK;
     const int ntile = SYM ? pt * (pt + 1) / 2 : pt * qt;
-    for (int t = wave; t < ntile; t += BW) {
-        int bi, bj;
-        if (SYM) {
-            bi = 0;
-            while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-            bj = t - bi * (bi + 1) / 2;
-        } else {
-            bi = t % pt;
-            bj = t / pt;
-        }
-        const int i0 = bi << 4, j0 = bj << 4;
-        const int ia = min(i0 + tr, p - 1), jb = min(j0 + tr, q - 1);
-        const bool rok = i0 + tr < p, cok = j0 + tr < q;
-        f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-        for (int s0 = 0; 4 * s0 < k; s0 += 4) {
-            double a[4], b[4];
+    const __amdgpu_buffer_rsrc_t ra = bsi_rsrc(A, (int64_t)k * p), rb = bsi_rsrc(B, (int64_t)k * q);
+    double *s_a = s_st, *s_b = SYM ? s_st : s_st + BLD * 16 * pt;
+    int ti[8], tj[8];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int kk = 4 * (s0 + u) + tg;
-                const bool ok = kk < k;
-                const int kc = ok ? kk : 0;
-                a[u] = A[kc + lda * ia];
-                b[u] = B[kc + ldb * jb];
-                if (!(ok && rok)) a[u] = 0.0;
-                if (!(ok && cok)) b[u] = 0.0;
+    for (int j = 0; j < 8; ++j) {
+        const int t = wave + BW * j;
+        int bi = 0, bj = 0;
+        if (t < ntile) {
+            if (SYM) {
+                while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+                bj = t - bi * (bi + 1) / 2;
+            } else {
+                bi = t % pt;
+                bj = t / pt;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
         }
-        const int col = j0 + tr;
+        ti[j] = bi << 4;
+        tj[j] = bj << 4;
+    }
+    f64x4 acc[8];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = i0 + tg + 4 * v;
-            if (row < p && col < q) {
-                C[row + ldc * col] = acc[v];
-                if (SYM && bi != bj) C[col + ldc * row] = acc[v];
+    for (int j = 0; j < 8; ++j) acc[j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    double pa[BSI_PF], pb[BSI_PF];
+    bsi_slab_load(pa, ra, k, p, 0);
+    if (!SYM) bsi_slab_load(pb, rb, k, q, 0);
+    for (int sl = 0; sl < nsl; ++sl) {
+        __syncthreads();
+        bsi_slab_store(pa, s_a, p);
+        if (!SYM) bsi_slab_store(pb, s_b, q);
+        __syncthreads();
+        if (sl + 1 < nsl) {
+            bsi_slab_load(pa, ra, k, p, (sl + 1) * BK);
+            if (!SYM) bsi_slab_load(pb, rb, k, q, (sl + 1) * BK);
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (wave + BW * j < ntile) {
+#pragma unroll
+                for (int u = 0; u < BK / 4; ++u) {
+                    const double a = s_a[4 * u + tg + BLD * (ti[j] + tr)];
+                    const double b = s_b[4 * u + tg + BLD * (tj[j] + tr)];
+                    acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[j], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int col = tj[j] + tr;
+        if (wave + BW * j < ntile && col < q) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = ti[j] + tg + 4 * v;
+                if (row < p) {
+                    C[row + p * col] = acc[j][v];
+                    if (SYM && ti[j] != tj[j]) C[col + p * row] = acc[j][v];
+                }
             }
         }
     }
@@ -258,11 +357,11 @@ __device__ inline BsiWs bsi_layout(double *base, int n, int p, int R) {
 // One Cholesky-QR pass of the n x p matrix A into Q (shift_rel > 0: the
 // shifted pass of the shifted Cholesky-QR3 scheme).
 __device__ void bsi_cholqr(const double *A, double *Q, int n, int p, double shift_rel, BsiWs &w, int64_t *flag) {
-    bsi_tn<true>(p, p, n, A, n, A, n, w.G, p);
+    bsi_tn<true>(p, p, n, A, A, w.G);
     __syncthreads();
     chol_body<BE_THREADS>(w.G, p, p, shift_rel, nullptr, w.Rinv, flag);
     __syncthreads();
-    bsi_nn<true, false>(n, p, p, A, n, w.Rinv, p, Q, n);
+    bsi_nn<true, false>(n, p, p, A, w.Rinv, Q);
     __syncthreads();
 }
 
@@ -277,20 +376,24 @@ __device__ bool bsi_solve(const double *S, int n, int R, int p, double s_unit, d
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const bool loose = s_unit >= 0x1p-24;
     const int iters = loose ? 2 : 3;
-    for (int64_t e = tid; e < (int64_t)n * p; e += BE_THREADS) w.Q[e] = gaussian_value(0x5EED5EEDull, stream, (uint64_t)e);
+    // start block: independent uniform values in [-1, 1) (any block with a
+    // component along every wanted eigenvector converges)
+    const uint64_t key = splitmix64(0x5EED5EEDull ^ (stream << 20));
+    for (int64_t e = tid; e < (int64_t)n * p; e += BE_THREADS)
+        w.Q[e] = (double)(int64_t)splitmix64(key + (uint64_t)e) * 0x1p-63;
     __syncthreads();
     const double shift = 11.0 * ((double)n * p + (double)p * (p + 1)) * 1.1102230246251565e-16 * p;
     for (int it = 0; it < iters; ++it) {
-        bsi_nn<false, false>(n, p, n, S, n, w.Q, n, w.Z, n);
+        bsi_nn<false, false>(n, p, n, S, w.Q, w.Z);
         __syncthreads();
         bsi_cholqr(w.Z, w.Z2, n, p, shift, w, flag);
         if (it + 1 < iters) {
             bsi_cholqr(w.Z2, w.Q, n, p, 0.0, w, flag);
         } else if (loose) {
             bsi_cholqr(w.Z2, w.Z, n, p, 0.0, w, flag);
-            bsi_tn<true>(p, p, n, w.Z, n, w.Z, n, w.G, p);
+            bsi_tn<true>(p, p, n, w.Z, w.Z, w.G);
             __syncthreads();
-            bsi_nn<false, true>(n, p, p, w.Z, n, w.G, p, w.Q, n);
+            bsi_nn<false, true>(n, p, p, w.Z, w.G, w.Q);
             __syncthreads();
         } else {
             bsi_cholqr(w.Z2, w.Z, n, p, 0.0, w, flag);
@@ -298,28 +401,27 @@ __device__ bool bsi_solve(const double *S, int n, int R, int p, double s_unit, d
         }
     }
     // Rayleigh-Ritz
-    bsi_nn<false, false>(n, p, n, S, n, w.Q, n, w.Z, n);
+    bsi_nn<false, false>(n, p, n, S, w.Q, w.Z);
     __syncthreads();
-    bsi_tn<false>(p, p, n, w.Q, n, w.Z, n, w.T, p);
+    bsi_tn<false>(p, p, n, w.Q, w.Z, w.T);
     __syncthreads();
     if (teig_z_fits(p, R, true)) teig_body<true, true>(w.T, p, p, R, w.W, p, w.th, false, w.te, flag);
     else teig_body<true, false>(w.T, p, p, R, w.W, p, w.th, false, w.te, flag);
     __syncthreads();
-    // U = Q W with the sign rule, and the Ritz residuals (one wave per vector)
+    // U = Q W and V = Z W on the matrix cores (V in Z2), then per vector
+    // (one wave each) the Ritz residual ||V(:, r) - theta_r U(:, r)|| and the
+    // sign rule
+    bsi_nn<false, false>(n, R, p, w.Q, w.W, U);
+    bsi_nn<false, false>(n, R, p, w.Z, w.W, w.Z2);
+    __syncthreads();
     for (int r = wave; r < R; r += BW) {
         const double t = w.th[r];
         double ss = 0.0, best = -1.0, bval = 0.0;
         int arg = 0;
         for (int i = lane; i < n; i += 64) {
-            double u = 0.0, z = 0.0;
-            for (int k = 0; k < p; ++k) {
-                const double wk = w.W[k + (int64_t)p * r];
-                u += w.Q[i + (int64_t)n * k] * wk;
-                z += w.Z[i + (int64_t)n * k] * wk;
-            }
-            const double d = z - t * u;
+            const double u = U[i + (int64_t)n * r];
+            const double d = w.Z2[i + (int64_t)n * r] - t * u;
             ss += d * d;
-            U[i + (int64_t)n * r] = u;
             if (fabs(u) > best) {
                 best = fabs(u);
                 arg = i;
@@ -453,6 +555,7 @@ size_t batch_eig_lds(int64_t n, int64_t R, int64_t p) {
     if (p > 0) {
         b = std::max(b, teig_lds_bytes(p, R, true, teig_z_fits(p, R, true), teig_v_keep(p, R, true)));
         b = std::max(b, chol_lds_bytes(p));
+        b = std::max(b, bsi_stage_bytes(p));
     }
     return b;
 }
