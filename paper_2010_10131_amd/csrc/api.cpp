@@ -1118,7 +1118,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             b.nchunks = (int)((b.I + 31) / 32);
             b.ntiles = (int)((b.R + 15) / 16);
             b.rtb = b.ntiles <= 1 ? 1 : (b.ntiles <= 2 ? 2 : 4);
-            b.contig = (b.L == 1 && b.I % 4 == 0) ? 1 : 0;
+            b.contig = (b.L == 1) ? 1 : 0;
             cur[s] = b.R;
         }
         const size_t oA = a.take(maxA * 4), oB = a.take(maxB * 4), oPart = a.take(maxPart), oS = a.take(maxS),

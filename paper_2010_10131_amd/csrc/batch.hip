@@ -69,7 +69,8 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const BatchStep *__rest
     if (d.L == 1 && WT >= 2) {
         const bool v4 = (d.I & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0);
         if constexpr (WT == 2) {
-            if (v4) {
+            // the 16-byte loader needs only 4-byte aligned rows
+            if (d.I >= 4) {
                 gram_l1_body<PREC, 2, 2, 2, 2, true, false, true>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
                 return;
             }
@@ -86,7 +87,7 @@ __global__ __launch_bounds__(256) void batch_gram_kernel(const BatchStep *__rest
 
 // The 128-wide class of a launch whose tensors all have L = 1 (the first mode
 // step): eight waves of 64 x 32 tiles, as the single-tensor mode-1 Gram, with
-// the 16-byte loads when I % 4 == 0.
+// the 16-byte loads (any I >= 4).
 template <int PREC>
 __global__ __launch_bounds__(512) void batch_gram_l1w_kernel(const BatchStep *__restrict__ descs,
                                                             const int32_t *__restrict__ list,
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(512) void batch_gram_l1w_kernel(const BatchStep *__
     double *part = (double *)(ws + d.part_off);
     const int64_t local = lid - pref[k];
     const int64_t P = d.L * d.M;
-    if ((d.I & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) & 15) == 0))
+    if (d.I >= 4)
         gram_l1_body<PREC, 4, 2, 2, 4, true, false, true>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
     else
         gram_l1_body<PREC, 4, 2, 2, 4, false>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);

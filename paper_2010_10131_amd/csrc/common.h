@@ -22,6 +22,8 @@
 namespace sth {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+// four floats at a 4-byte aligned address (one 16-byte load on this target)
+typedef float f32x4u __attribute__((ext_vector_type(4), aligned(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 

@@ -268,11 +268,12 @@ __device__ __forceinline__ void l1_store(uint8_t *slab, int TB, int g, int row, 
 // a diagonal block loads its one operand twice, from cache).  Branch-free
 // loads let the compiler wait for exactly the chunk being stored instead of
 // draining every load in flight before the next ones are issued.
-// V4LD (batched mode-1 launches; I % 4 == 0 with aligned rows, any I): thread
+// V4LD (batched mode-1 launches, any I >= 4, rows 4-byte aligned): thread
 // (parity, operand, row quad iq, group g) owns rows 4 iq .. 4 iq + 3 of one
 // operand and the 8 columns g of every chunk of its parity (threads [0, 2 TB)
 // the even chunks, the rest the odd ones): eight 16-byte loads per chunk give
-// four rows' fragments (quads past I zeroed, their address clamped); the same
+// four rows' fragments (quads past I zeroed, a quad across row I read value
+// by value); the same
 // 32 values per thread as two chunks of two operands in flight.  Its LDS
 // stores are 64 bytes apart across lanes; where the matrix cores bound the
 // Gram (bf16x6 at I = 512) the FULLI loads are faster, so the single-tensor
@@ -433,22 +434,39 @@ __device__ __forceinline__ void gram_l1_body(const float *__restrict__ Y, int64_
         static_assert(NTH == 4 * TB, "one task per thread");
         constexpr int TQ4 = TB / 4;
         const int par4 = tid / (2 * TB), op4 = (tid / TB) & 1, iq4 = (tid % TB) % TQ4, g4 = (tid % TB) / TQ4;
-        // I % 4 == 0: a row quad is wholly inside or wholly past the last row
-        const bool rok4 = (op4 ? j0 : i0) + 4 * iq4 < I;
-        const float *src4 = Y + (rok4 ? (op4 ? j0 : i0) + 4 * iq4 : 0);
+        // a quad wholly inside the column is one 16-byte load (4-byte
+        // aligned when I % 4 != 0); the quad that runs past row I - 1 reads
+        // its rows below I one value at a time, so no load leaves the column
+        const int64_t rq = (op4 ? j0 : i0) + 4 * iq4;
+        const bool rok4 = rq < I, full4 = rq + 4 <= I;
+        const float *src4 = Y + (rok4 ? rq : 0);
         float rv[4][8];
         auto load4 = [&](int cn) {
             const int64_t pc = pbeg + (int64_t)(cn < nch ? cn : nch - 1) * KC;
+            if (full4) {
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t pp = pc + 8 * g4 + j;
-                const int64_t pcl = pp < pend ? pp : pend - 1;
-                const float4 v = *reinterpret_cast<const float4 *>(src4 + I * pcl);
-                const bool in = rok4 && pp < pend;
-                rv[0][j] = in ? v.x : 0.f;
-                rv[1][j] = in ? v.y : 0.f;
-                rv[2][j] = in ? v.z : 0.f;
-                rv[3][j] = in ? v.w : 0.f;
+                for (int j = 0; j < 8; ++j) {
+                    const int64_t pp = pc + 8 * g4 + j;
+                    const int64_t pcl = pp < pend ? pp : pend - 1;
+                    const f32x4u v = *reinterpret_cast<const f32x4u *>(src4 + I * pcl);
+                    const bool in = pp < pend;
+                    rv[0][j] = in ? v.x : 0.f;
+                    rv[1][j] = in ? v.y : 0.f;
+                    rv[2][j] = in ? v.z : 0.f;
+                    rv[3][j] = in ? v.w : 0.f;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int64_t pp = pc + 8 * g4 + j;
+                    const int64_t pcl = pp < pend ? pp : pend - 1;
+                    const bool in = rok4 && pp < pend;
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr) {
+                        const bool ok = in && rq + rr < I;
+                        rv[rr][j] = ok ? src4[I * pcl + (ok ? rr : 0)] : 0.f;
+                    }
+                }
             }
         };
         auto store4 = [&](int buf) {

@@ -12,8 +12,9 @@ __device__ __forceinline__ void ttm_load_chunk(const T *__restrict__ Y, int64_t 
     if (CONTIG && kb + 8 <= K) {
         const T *src = Y + base + kb;
         if constexpr (sizeof(T) == 4) {
-            float4 u = *reinterpret_cast<const float4 *>(src);
-            float4 w = *reinterpret_cast<const float4 *>(src + 4);
+            // 4-byte alignment suffices (rows of any length K)
+            const f32x4u u = *reinterpret_cast<const f32x4u *>(src);
+            const f32x4u w = *reinterpret_cast<const f32x4u *>(src + 4);
             x[0] = u.x; x[1] = u.y; x[2] = u.z; x[3] = u.w;
             x[4] = w.x; x[5] = w.y; x[6] = w.z; x[7] = w.w;
         } else {
