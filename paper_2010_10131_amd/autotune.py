@@ -16,7 +16,7 @@ import torch
 from .api import BatchPlan
 
 DEFAULT = (4, 4, 4)
-GRAM_WG_PER_CU = (2, 4, 8, 16)
+GRAM_WG_PER_CU = (2, 4, 8, 16, 32, 64)
 GRAM_WT_MAX = (1, 2, 4)
 TTM_ROWS_PER_WAVE = (1, 2, 4, 8)
 

@@ -1092,22 +1092,42 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
         for (int s = 0; s < N; ++s) {
             BatchStep &b = sd[s][t];
             memset(&b, 0, sizeof(b));
-            lim(N, cur.data(), s, b.L, b.I, b.M);
+            // rotated layout: every intermediate is stored with the mode it
+            // feeds first (the TTM writes its output transposed), so each step
+            // is the L = 1 view: I = I_s, M = the product of the other modes;
+            // after the last step the rotation has come full circle and the
+            // core is in natural order
+            b.L = 1;
+            b.I = cur[s];
+            b.M = 1;
+            for (int k = 0; k < N; ++k)
+                if (k != s) b.M *= cur[k];
             b.R = d.ranks[s];
             b.tensor = t;
             const int64_t P = b.L * b.M;
             const size_t out = (size_t)(b.L * b.R * b.M);
             if (s < N - 1) (s % 2 == 0 ? maxA : maxB) = std::max(s % 2 == 0 ? maxA : maxB, out);
-            int wt, nbi, nbj, nblocks, nkc;
+            int wt, nbi, nbj, nblocks, nkc, ns;
             int64_t kper;
-            gram_geometry(b.I, b.I, P, true, target, tile.gram_wt_max, &wt, &nbi, &nbj, &nblocks, &nkc, &kper);
-            b.wt = wt;
-            b.nbi = nbi;
-            b.nblocks = nblocks;
-            b.nkc = nkc;
-            b.kper = kper;
-            b.gram_wg = (int64_t)nkc * nblocks;
-            maxPart = std::max(maxPart, (size_t)nkc * nblocks * (32 * wt) * (32 * wt) * 8);
+            if (batch_gram_skinny(b.L, b.I, P, target, &ns, &nkc)) {
+                // whole lower triangles in 32 x 32 super tiles, one workgroup each
+                b.wt = BATCH_SKINNY;
+                b.nbi = ns;
+                b.nblocks = ns * (ns + 1) / 2;
+                b.nkc = nkc;
+                b.kper = 0;
+                b.gram_wg = nkc;
+                maxPart = std::max(maxPart, (size_t)nkc * b.nblocks * 32 * 32 * 8);
+            } else {
+                gram_geometry(b.I, b.I, P, true, target, tile.gram_wt_max, &wt, &nbi, &nbj, &nblocks, &nkc, &kper);
+                b.wt = wt;
+                b.nbi = nbi;
+                b.nblocks = nblocks;
+                b.nkc = nkc;
+                b.kper = kper;
+                b.gram_wg = (int64_t)nkc * nblocks;
+                maxPart = std::max(maxPart, (size_t)nkc * nblocks * (32 * wt) * (32 * wt) * 8);
+            }
             maxS = std::max(maxS, (size_t)(b.I * b.I) * 8);
             maxUq = std::max(maxUq, ttm_prep_bytes(b.I, b.R, d0.ttm_prec));
             if (b.I > MAX_EIG_N)
@@ -1118,7 +1138,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             b.nchunks = (int)((b.I + 31) / 32);
             b.ntiles = (int)((b.R + 15) / 16);
             b.rtb = b.ntiles <= 1 ? 1 : (b.ntiles <= 2 ? 2 : 4);
-            b.contig = (b.L == 1) ? 1 : 0;
+            b.contig = 1;
             cur[s] = b.R;
         }
         const size_t oA = a.take(maxA * 4), oB = a.take(maxB * 4), oPart = a.take(maxPart), oS = a.take(maxS),
@@ -1161,7 +1181,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             L.cls = cls;
             return L;
         };
-        for (int cls : {1, 2, 4}) {
+        for (int cls : {BATCH_SKINNY, 1, 2, 4}) {
             std::vector<int32_t> gl;
             std::vector<int64_t> gw, gb;
             for (int t = 0; t < count; ++t)

@@ -109,6 +109,26 @@ __global__ __launch_bounds__(512) void batch_gram_l1w_kernel(const BatchStep *__
         gram_l1_body<PREC, 4, 2, 2, 4, false>(Y, d.I, P, d.kper, d.nkc, d.nblocks, d.gram_wg, local, part);
 }
 
+// The skinny class (first mode step, I <= SK_MAXI): each workgroup of a
+// tensor takes the whole lower triangle of its Gram in 32 x 32 super tiles
+// over round-robin column blocks (the single-tensor skinny body), so no
+// output tile is padded beyond 32 rows and the tensor is read once.
+constexpr int BSK_CH = 2;   // 32-column chunks per stage: 2 TBp loader tasks, one per thread
+template <int PREC>
+__global__ __launch_bounds__(SK_T) void batch_gram_skinny_kernel(const BatchStep *__restrict__ descs,
+                                                                const int32_t *__restrict__ list,
+                                                                const int64_t *__restrict__ pref, int len,
+                                                                int64_t total, char *__restrict__ ws,
+                                                                const void *const *__restrict__ Xp) {
+    const int64_t per_xcd = (total + 7) / 8;
+    const int64_t lid = (int64_t)(blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (lid >= total) return;
+    const int k = find_segment(pref, len, lid);
+    const BatchStep &d = descs[list[k]];
+    gram_skinny_body<PREC, BSK_CH, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
+                                         (double *)(ws + d.part_off));
+}
+
 template <int TB>
 __global__ void batch_reduce_kernel(const BatchStep *__restrict__ descs,
                                     const int32_t *__restrict__ list,
@@ -528,17 +548,25 @@ __global__ __launch_bounds__(64 * BT_WAVES) void batch_ttm_kernel(
     const int64_t wg = blockIdx.x - pref[k], nwg = pref[k + 1] - pref[k];
     const int64_t P = d.L * d.M;
     const int64_t nrb = (P + 16 * NT - 1) / (16 * NT);
-    if (d.contig)
-        ttm_body<float, PREC, NT, RTB, true, true, BT_WAVES>(Y, uq, Z, d.L, d.I, d.R, P, d.nchunks,
-                                                             d.ntiles, nrb, wg, nwg, 0);
-    else
-        ttm_body<float, PREC, NT, RTB, false, true, BT_WAVES>(Y, uq, Z, d.L, d.I, d.R, P, d.nchunks,
-                                                              d.ntiles, nrb, wg, nwg, 0);
+    // every step is the L = 1 view of the rotated layout; the output goes out
+    // transposed, which makes the next mode the first
+    ttm_body<float, PREC, NT, RTB, true, true, BT_WAVES, 1, true>(Y, uq, Z, 1, d.I, d.R, P, d.nchunks,
+                                                                 d.ntiles, nrb, wg, nwg, 0);
 }
 
 // ---------------------------------------------------------------- host
 
+bool batch_gram_skinny(int64_t L, int64_t I, int64_t P, int64_t target, int *ns, int *nkc) {
+    if (L != 1 || I > SK_MAXI) return false;
+    *ns = sk_ns(I);
+    const int64_t nblk = (P + 32 * BSK_CH - 1) / (32 * BSK_CH);
+    // about `target` workgroups, each at least four stages
+    *nkc = (int)std::max<int64_t>(1, std::min<int64_t>(target, nblk / 4));
+    return true;
+}
+
 size_t batch_gram_lds(int prec, int wt) {
+    if (wt == BATCH_SKINNY) return (size_t)2 * BSK_CH * prec_nq(prec) * 4 * 32 * sk_ns(SK_MAXI) * 16;
     const int tb = 32 * wt, nq = prec_nq(prec);
     const size_t l1 = (size_t)2 * 2 * nq * 4 * tb * 16;
     const size_t gen = (size_t)2 * nq * tb * 4 * 16;
@@ -586,6 +614,17 @@ template <int PREC>
 hipError_t launch_bgram_p(int wt, const BatchLaunch &bl, const BatchTables &t, char *ws,
                           const void *const *Xp, hipStream_t s) {
     const size_t lds = batch_gram_lds(PREC, wt);
+    if (wt == BATCH_SKINNY) {
+        auto kern = batch_gram_skinny_kernel<PREC>;
+        if (lds > 64 * 1024) {
+            hipError_t e = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+            if (e != hipSuccess) return e;
+        }
+        const int64_t per_xcd = (bl.total + 7) / 8;
+        hipLaunchKernelGGL(kern, dim3((unsigned)(per_xcd * 8)), dim3(SK_T), lds, s, t.descs, bl.list, bl.pref,
+                           bl.len, bl.total, ws, Xp);
+        return hipGetLastError();
+    }
     if (wt == 4 && bl.l1) {
         auto kern = batch_gram_l1w_kernel<PREC>;
         if (lds > 64 * 1024) {
@@ -645,10 +684,10 @@ hipError_t batch_step_launch(const BatchTables &t, const BatchStepPlan &sp, int 
     }
     for (const BatchLaunch &bl : sp.reduce) {
         if (bl.len == 0) continue;
-        const int tb = 32 * bl.cls;
+        const int tb = bl.cls == BATCH_SKINNY ? 32 : 32 * bl.cls;   // skinny partials: 32 x 32 super tiles
         dim3 grid((unsigned)((tb * tb + 255) / 256), (unsigned)bl.total);
-        if (bl.cls == 1) hipLaunchKernelGGL(batch_reduce_kernel<32>, grid, dim3(256), 0, s, t.descs, bl.list, bl.pref, bl.len, ws);
-        else if (bl.cls == 2) hipLaunchKernelGGL(batch_reduce_kernel<64>, grid, dim3(256), 0, s, t.descs, bl.list, bl.pref, bl.len, ws);
+        if (tb == 32) hipLaunchKernelGGL(batch_reduce_kernel<32>, grid, dim3(256), 0, s, t.descs, bl.list, bl.pref, bl.len, ws);
+        else if (tb == 64) hipLaunchKernelGGL(batch_reduce_kernel<64>, grid, dim3(256), 0, s, t.descs, bl.list, bl.pref, bl.len, ws);
         else hipLaunchKernelGGL(batch_reduce_kernel<128>, grid, dim3(256), 0, s, t.descs, bl.list, bl.pref, bl.len, ws);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }

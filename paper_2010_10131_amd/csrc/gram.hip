@@ -61,189 +61,10 @@ __global__ __launch_bounds__((gram_l1_eight_waves<PREC, WT>() ? 512 : 256)) void
                                                       xcd_logical_id(total_wg), partials);
 }
 
-// ---- skinny Gram: L = 1 and I <= 160 (a short first mode, J_1 = M huge) --
-// Y (I x P, column-major) is read once, in blocks of 32 CH columns (each one
-// contiguous run of 128 I CH bytes) dealt round-robin to the workgroups:
-// workgroup k takes blocks k, k + nkc, ..., so that at any moment the chip
-// streams one contiguous region (independent far-apart streams per
-// workgroup camp on a few HBM channels).
-// The whole lower triangle of its partial Gram is held in registers as 32 x 32
-// super tiles (2 x 2 tiles of 16 x 16), at most SK_MS per wave.  Per stage CH
-// chunks of 32 columns go through LDS as matrix-core fragments: thread task
-// (row i, group g, chunk c) loads the 8 values Y(i, p0 + 32 c + 8 g + j),
-// consecutive lanes on consecutive rows (256-byte loads), splits them into
-// the precision's fragment and stores it; the next stage's loads are in flight
-// while the current one is multiplied.  FP32 accumulators are flushed into
-// FP64 every GRAM_FLUSH chunks; partial super tiles go to the workspace and
-// gram_reduce_kernel<32, true> sums them in a fixed order.
-constexpr int SK_MAXI = 160;
-constexpr int SK_W = 8, SK_T = 64 * SK_W;
-constexpr int SK_MS = 2;      // super tiles per wave: 15 lower 32 x 32 tiles at I = 160
-constexpr int SK_TASKS = 4;   // loader tasks per thread and stage
-
-__host__ __device__ inline int sk_ns(int64_t I) { return (int)(((I + 15) / 16 + 1) / 2); }
-
 template <int PREC, int CH, bool V4>
 __global__ __launch_bounds__(SK_T) void gram_skinny_kernel(const float *__restrict__ Y, int I, int64_t P,
                                                           int nkc, double *__restrict__ partials) {
-    constexpr int NQ = Frag<PREC>::NQ;
-    typedef typename Acc<PREC>::type AccT;
-    constexpr bool F64ACC = (PREC == P_FP64);
-    extern __shared__ uint4 s_sk[];
-    const int kc = blockIdx.x;
-    const int NS = sk_ns(I), NSS = NS * (NS + 1) / 2, TBp = 32 * NS;
-    const int64_t nblk = (P + 32 * CH - 1) / (32 * CH);
-    const int nst = kc < nblk ? (int)((nblk - 1 - kc) / nkc + 1) : 0;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
-    const int stage_q = CH * NQ * 4 * TBp;   // uint4 per stage buffer
-
-    int sbi[SK_MS], sbj[SK_MS];
-#pragma unroll
-    for (int m = 0; m < SK_MS; ++m) {
-        const int q = wave + SK_W * m;
-        int bi = -1, bj = 0;
-        if (q < NSS) {
-            bi = 0;
-            while ((bi + 1) * (bi + 2) / 2 <= q) ++bi;
-            bj = q - bi * (bi + 1) / 2;
-        }
-        sbi[m] = bi;
-        sbj[m] = bj;
-    }
-    AccT acc[SK_MS][2][2];
-    f64x4 acc64[SK_MS][2][2];
-#pragma unroll
-    for (int m = 0; m < SK_MS; ++m)
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                acc[m][x][y] = AccT{0, 0, 0, 0};
-                acc64[m][x][y] = f64x4{0, 0, 0, 0};
-            }
-
-    // V4 (I % 4 == 0, 16-byte aligned Y): task (row quad iq, group g, chunk c)
-    // loads the 4 x 8 block Y(4 iq .. 4 iq + 3, p0 + 32 c + 8 g + j) with eight
-    // 16-byte loads (consecutive lanes on consecutive row quads) and builds
-    // the four rows' fragments.  Otherwise task (row i, group g, chunk c)
-    // loads the 8 values of one row with 4-byte loads.
-    constexpr int RPT = V4 ? 4 : 1;                 // rows per task
-    constexpr int NTK = V4 ? 1 : SK_TASKS;          // tasks per thread
-    const int TQ = TBp / RPT;                       // row groups
-    const int ntask = TQ * 4 * CH;
-    float raw[NTK][RPT][8];
-    auto load = [&](int st) {
-        const int64_t p0 = ((int64_t)st * nkc + kc) * 32 * CH;
-#pragma unroll
-        for (int u = 0; u < NTK; ++u) {
-            const int t = tid + SK_T * u;
-            const int iq = t % TQ, rest = t / TQ, gg = rest & 3, c = rest >> 2;
-            const bool ok = t < ntask && RPT * iq < I;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int64_t pp = p0 + 32 * c + 8 * gg + j;
-                const bool in = ok && pp < P;
-                const int64_t pc = in ? pp : p0;
-                const int64_t a = (int64_t)(ok ? RPT * iq : 0) + (int64_t)I * pc;
-                if constexpr (V4) {
-                    const float4 v = *reinterpret_cast<const float4 *>(Y + a);
-                    raw[u][0][j] = in ? v.x : 0.f;
-                    raw[u][1][j] = in ? v.y : 0.f;
-                    raw[u][2][j] = in ? v.z : 0.f;
-                    raw[u][3][j] = in ? v.w : 0.f;
-                } else {
-                    const float v = Y[a];
-                    raw[u][0][j] = in ? v : 0.f;
-                }
-            }
-        }
-    };
-    auto store = [&](int buf) {
-        uint4 *sb = s_sk + (size_t)buf * stage_q;
-#pragma unroll
-        for (int u = 0; u < NTK; ++u) {
-            const int t = tid + SK_T * u;
-            if (t < ntask) {
-                const int iq = t % TQ, rest = t / TQ, gg = rest & 3, c = rest >> 2;
-#pragma unroll
-                for (int rr = 0; rr < RPT; ++rr) {
-                    FragQ<PREC> f;
-                    make_frag(raw[u][rr], f.f);
-#pragma unroll
-                    for (int qq = 0; qq < NQ; ++qq) sb[((c * NQ + qq) * 4 + gg) * TBp + RPT * iq + rr] = f.q[qq];
-                }
-            }
-        }
-    };
-    auto frag = [&](const uint4 *sb, int c, int row, Frag<PREC> &f) {
-        FragQ<PREC> t;
-#pragma unroll
-        for (int qq = 0; qq < NQ; ++qq) t.q[qq] = sb[((c * NQ + qq) * 4 + g) * TBp + row];
-        f = t.f;
-    };
-
-    int chunk = 0;
-    if (nst > 0) {
-        load(0);
-        store(0);
-    }
-    __syncthreads();
-    for (int st = 0; st < nst; ++st) {
-        if (st + 1 < nst) load(st + 1);
-        const uint4 *sb = s_sk + (size_t)(st & 1) * stage_q;
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-#pragma unroll
-            for (int m = 0; m < SK_MS; ++m) {
-                if (sbi[m] < 0) continue;   // uniform within the wave
-                Frag<PREC> fa[2], fb[2];
-#pragma unroll
-                for (int x = 0; x < 2; ++x) frag(sb, c, 32 * sbi[m] + 16 * x + (lane & 15), fa[x]);
-                if (sbi[m] != sbj[m]) {
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) frag(sb, c, 32 * sbj[m] + 16 * y + (lane & 15), fb[y]);
-                } else {
-                    fb[0] = fa[0];
-                    fb[1] = fa[1];
-                }
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) mma_frag(fa[x], fb[y], acc[m][x][y]);
-            }
-            ++chunk;
-            if (!F64ACC && chunk % GRAM_FLUSH == 0) {
-#pragma unroll
-                for (int m = 0; m < SK_MS; ++m)
-#pragma unroll
-                    for (int x = 0; x < 2; ++x)
-#pragma unroll
-                        for (int y = 0; y < 2; ++y) {
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) acc64[m][x][y][v] += (double)acc[m][x][y][v];
-                            acc[m][x][y] = AccT{0, 0, 0, 0};
-                        }
-            }
-        }
-        if (st + 1 < nst) store((st + 1) & 1);
-        __syncthreads();
-    }
-    // partial super tiles: element (il, jl) of super tile q at [(kc NSS + q) 1024 + il + 32 jl]
-#pragma unroll
-    for (int m = 0; m < SK_MS; ++m) {
-        if (sbi[m] < 0) continue;
-        const int q = wave + SK_W * m;
-        double *dst = partials + ((int64_t)kc * NSS + q) * 1024;
-#pragma unroll
-        for (int x = 0; x < 2; ++x)
-#pragma unroll
-            for (int y = 0; y < 2; ++y)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const double val = F64ACC ? (double)acc[m][x][y][v] : acc64[m][x][y][v] + (double)acc[m][x][y][v];
-                    dst[(16 * x + drow<PREC>(g, v)) + 32 * (16 * y + (lane & 15))] = val;
-                }
-    }
+    gram_skinny_body<PREC, CH, V4>(Y, I, P, nkc, blockIdx.x, partials);
 }
 
 // Sums the partial blocks over the row ranges and writes the IA x IB result

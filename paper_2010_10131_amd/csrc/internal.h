@@ -90,7 +90,7 @@ struct BatchLaunch {
     const int64_t *pref;  // device: prefix sums of the work units (len + 1)
     int len;
     int64_t total;
-    int cls;  // tile class (Gram: WT; TTM: r-tiles per workgroup)
+    int cls;  // tile class (Gram: WT, or BATCH_SKINNY; TTM: r-tiles per workgroup)
     int l1;   // Gram: every tensor of the list has L = 1
 };
 struct BatchTables {
@@ -103,6 +103,11 @@ struct BatchStepPlan {
     std::vector<BatchLaunch> gram, reduce, ttm;
     BatchLaunch prep;
 };
+// Gram class of the skinny path (L = 1, I <= 160): whole triangles per workgroup
+constexpr int BATCH_SKINNY = 8;
+// true when the step's Gram takes the skinny class: ns = super tiles per side,
+// nkc = its workgroups
+bool batch_gram_skinny(int64_t L, int64_t I, int64_t P, int64_t target, int *ns, int *nkc);
 size_t batch_gram_lds(int prec, int wt);
 // subspace block of a batched eigensolve (0: the direct solver)
 int64_t batch_si_block(int64_t n, int64_t R, int64_t rank_bound);

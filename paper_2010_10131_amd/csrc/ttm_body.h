@@ -37,7 +37,9 @@ __device__ __forceinline__ void ttm_load_chunk(const T *__restrict__ Y, int64_t 
 // Body of the TTM for one workgroup: wg of nwg workgroups sharing the row
 // blocks of this tensor, r-block rb.  Also used by the batched kernels.
 // PF = chunks of Y in flight per wave (1 or 2).
-template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES, int PF = 1>
+// ZT (with CONTIG): the output is stored transposed, Z(r, p) at p + P r, which
+// puts the next mode first in the batched path's rotated layout.
+template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES, int PF = 1, bool ZT = false>
 __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *__restrict__ Uq,
                                          T *__restrict__ Z, int64_t L, int64_t K, int64_t Rout,
                                          int64_t P, int nchunks, int ntiles, int64_t nrowblocks,
@@ -168,9 +170,21 @@ __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *_
         }
 
         // D[r][p]: lane holds r = 16*rt + drow(g, v), p = 16*nt + lane%16
+        static_assert(!ZT || CONTIG, "the transposed output is the L = 1 view's");
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (!pvalid[nt]) continue;
+            if constexpr (ZT) {
+                const int64_t p = p0 + 16 * nt + (lane & 15);
+#pragma unroll
+                for (int rt = 0; rt < RTB; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t r = (int64_t)(rt0 + rt) * 16 + drow<PREC>(g, v);
+                        if (r < Rout) Z[p + P * r] = (T)acc[nt][rt][v];
+                    }
+                continue;
+            }
 #pragma unroll
             for (int rt = 0; rt < RTB; ++rt) {
                 const int64_t rbase = (int64_t)(rt0 + rt) * 16;
