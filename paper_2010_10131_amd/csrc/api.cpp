@@ -1109,7 +1109,7 @@ extern "C" sth_status sthosvd_plan_batched_tiles(const sth_desc *descs, int32_t 
             if (s < N - 1) (s % 2 == 0 ? maxA : maxB) = std::max(s % 2 == 0 ? maxA : maxB, out);
             int wt, nbi, nbj, nblocks, nkc, ns;
             int64_t kper;
-            if (batch_gram_skinny(b.L, b.I, P, target, &ns, &nkc)) {
+            if (batch_gram_skinny(d0.gram_prec, b.L, b.I, P, target, &ns, &nkc)) {
                 // whole lower triangles in 32 x 32 super tiles, one workgroup each
                 b.wt = BATCH_SKINNY;
                 b.nbi = ns;

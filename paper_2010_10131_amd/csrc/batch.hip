@@ -113,7 +113,13 @@ __global__ __launch_bounds__(512) void batch_gram_l1w_kernel(const BatchStep *__
 // tensor takes the whole lower triangle of its Gram in 32 x 32 super tiles
 // over round-robin column blocks (the single-tensor skinny body), so no
 // output tile is padded beyond 32 rows and the tensor is read once.
-constexpr int BSK_CH = 2;   // 32-column chunks per stage: 2 TBp loader tasks, one per thread
+// 32-column chunks per stage: TBp * CH loader tasks, one per thread; CH = 4
+// (twice the bytes in flight per stage) where 32 * ceil(I / 32) <= 128 and the
+// two stages fit the LDS (fragments of at most two bf16 parts)
+constexpr int BSK_CH = 2, BSK_CH4_MAXI = 128;
+__host__ __device__ inline int bsk_ch(int prec, int64_t I) {
+    return (I <= BSK_CH4_MAXI && (prec == P_FP32 || prec == P_BF16X3)) ? 4 : BSK_CH;
+}
 template <int PREC>
 __global__ __launch_bounds__(SK_T) void batch_gram_skinny_kernel(const BatchStep *__restrict__ descs,
                                                                 const int32_t *__restrict__ list,
@@ -125,8 +131,12 @@ __global__ __launch_bounds__(SK_T) void batch_gram_skinny_kernel(const BatchStep
     if (lid >= total) return;
     const int k = find_segment(pref, len, lid);
     const BatchStep &d = descs[list[k]];
-    gram_skinny_body<PREC, BSK_CH, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
-                                         (double *)(ws + d.part_off));
+    if (bsk_ch(PREC, d.I) == 4)
+        gram_skinny_body<PREC, 4, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
+                                        (double *)(ws + d.part_off));
+    else
+        gram_skinny_body<PREC, BSK_CH, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
+                                             (double *)(ws + d.part_off));
 }
 
 template <int TB>
@@ -556,17 +566,21 @@ __global__ __launch_bounds__(64 * BT_WAVES) void batch_ttm_kernel(
 
 // ---------------------------------------------------------------- host
 
-bool batch_gram_skinny(int64_t L, int64_t I, int64_t P, int64_t target, int *ns, int *nkc) {
+bool batch_gram_skinny(int prec, int64_t L, int64_t I, int64_t P, int64_t target, int *ns, int *nkc) {
     if (L != 1 || I > SK_MAXI) return false;
     *ns = sk_ns(I);
-    const int64_t nblk = (P + 32 * BSK_CH - 1) / (32 * BSK_CH);
-    // about `target` workgroups, each at least four stages
-    *nkc = (int)std::max<int64_t>(1, std::min<int64_t>(target, nblk / 4));
+    const int ch = bsk_ch(prec, I);
+    const int64_t nblk = (P + 32 * ch - 1) / (32 * ch);
+    // about `target` workgroups, each at least eight stages (the partial
+    // triangles a workgroup writes stay well below what it reads)
+    *nkc = (int)std::max<int64_t>(1, std::min<int64_t>(target, nblk / 8));
     return true;
 }
 
 size_t batch_gram_lds(int prec, int wt) {
-    if (wt == BATCH_SKINNY) return (size_t)2 * BSK_CH * prec_nq(prec) * 4 * 32 * sk_ns(SK_MAXI) * 16;
+    if (wt == BATCH_SKINNY)   // the larger of the two stage shapes
+        return std::max((size_t)2 * BSK_CH * prec_nq(prec) * 4 * 32 * sk_ns(SK_MAXI) * 16,
+                        (size_t)2 * bsk_ch(prec, BSK_CH4_MAXI) * prec_nq(prec) * 4 * BSK_CH4_MAXI * 16);
     const int tb = 32 * wt, nq = prec_nq(prec);
     const size_t l1 = (size_t)2 * 2 * nq * 4 * tb * 16;
     const size_t gen = (size_t)2 * nq * tb * 4 * 16;

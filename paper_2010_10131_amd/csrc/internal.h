@@ -107,7 +107,7 @@ struct BatchStepPlan {
 constexpr int BATCH_SKINNY = 8;
 // true when the step's Gram takes the skinny class: ns = super tiles per side,
 // nkc = its workgroups
-bool batch_gram_skinny(int64_t L, int64_t I, int64_t P, int64_t target, int *ns, int *nkc);
+bool batch_gram_skinny(int prec, int64_t L, int64_t I, int64_t P, int64_t target, int *ns, int *nkc);
 size_t batch_gram_lds(int prec, int wt);
 // subspace block of a batched eigensolve (0: the direct solver)
 int64_t batch_si_block(int64_t n, int64_t R, int64_t rank_bound);
