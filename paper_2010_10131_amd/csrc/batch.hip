@@ -132,10 +132,10 @@ __global__ __launch_bounds__(SK_T) void batch_gram_skinny_kernel(const BatchStep
     const int k = find_segment(pref, len, lid);
     const BatchStep &d = descs[list[k]];
     if (bsk_ch(PREC, d.I) == 4)
-        gram_skinny_body<PREC, 4, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
+        gram_skinny_body<PREC, 4, true, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
                                         (double *)(ws + d.part_off));
     else
-        gram_skinny_body<PREC, BSK_CH, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
+        gram_skinny_body<PREC, BSK_CH, true, true>(bsrc(d, ws, Xp), (int)d.I, d.L * d.M, d.nkc, (int)(lid - pref[k]),
                                              (double *)(ws + d.part_off));
 }
 

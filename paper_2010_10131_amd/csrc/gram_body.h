@@ -599,7 +599,9 @@ constexpr int SK_TASKS = 4;   // loader tasks per thread and stage
 
 __host__ __device__ inline int sk_ns(int64_t I) { return (int)(((I + 15) / 16 + 1) / 2); }
 
-template <int PREC, int CH, bool V4>
+// ANYI (with V4): I need not be a multiple of 4 (the batched class); the
+// quad across row I - 1 is then read value by value.
+template <int PREC, int CH, bool V4, bool ANYI = false>
 __device__ __forceinline__ void gram_skinny_body(const float *__restrict__ Y, int I, int64_t P, int nkc, int kc,
                                                  double *__restrict__ partials) {
     constexpr int NQ = Frag<PREC>::NQ;
@@ -637,10 +639,10 @@ __device__ __forceinline__ void gram_skinny_body(const float *__restrict__ Y, in
                 acc64[m][x][y] = f64x4{0, 0, 0, 0};
             }
 
-    // V4 (rows 4-byte aligned, any I): task (row quad iq, group g, chunk c)
+    // V4 (I % 4 == 0, or any I with ANYI): task (row quad iq, group g, chunk c)
     // loads the 4 x 8 block Y(4 iq .. 4 iq + 3, p0 + 32 c + 8 g + j) with eight
-    // 16-byte loads (consecutive lanes on consecutive row quads; the quad
-    // across row I - 1 value by value) and builds the four rows' fragments.  Otherwise task (row i, group g, chunk c)
+    // 16-byte loads (consecutive lanes on consecutive row quads) and builds
+    // the four rows' fragments.  Otherwise task (row i, group g, chunk c)
     // loads the 8 values of one row with 4-byte loads.
     constexpr int RPT = V4 ? 4 : 1;                 // rows per task
     constexpr int NTK = V4 ? 1 : SK_TASKS;          // tasks per thread
@@ -654,7 +656,21 @@ __device__ __forceinline__ void gram_skinny_body(const float *__restrict__ Y, in
             const int t = tid + SK_T * u;
             const int iq = t % TQ, rest = t / TQ, gg = rest & 3, c = rest >> 2;
             const bool ok = t < ntask && RPT * iq < I;
-            const bool full = RPT * iq + RPT <= I;   // V4: the quad lies inside the column
+            if (ANYI && RPT * iq + RPT > I) {
+                // the quad across row I - 1: its rows below I one at a time
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int64_t pp = p0 + 32 * c + 8 * gg + j;
+                    const bool in = ok && pp < P;
+                    const int64_t a = (int64_t)(ok ? RPT * iq : 0) + (int64_t)I * (in ? pp : p0);
+#pragma unroll
+                    for (int rr = 0; rr < RPT; ++rr) {
+                        const bool rin = in && RPT * iq + rr < I;
+                        raw[u][rr][j] = rin ? Y[a + (rin ? rr : 0)] : 0.f;
+                    }
+                }
+                continue;
+            }
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int64_t pp = p0 + 32 * c + 8 * gg + j;
@@ -662,20 +678,12 @@ __device__ __forceinline__ void gram_skinny_body(const float *__restrict__ Y, in
                 const int64_t pc = in ? pp : p0;
                 const int64_t a = (int64_t)(ok ? RPT * iq : 0) + (int64_t)I * pc;
                 if constexpr (V4) {
-                    if (full) {
-                        const f32x4u v = *reinterpret_cast<const f32x4u *>(Y + a);
-                        raw[u][0][j] = in ? v.x : 0.f;
-                        raw[u][1][j] = in ? v.y : 0.f;
-                        raw[u][2][j] = in ? v.z : 0.f;
-                        raw[u][3][j] = in ? v.w : 0.f;
-                    } else {
-                        // the quad across row I - 1: its rows below I one at a time
-#pragma unroll
-                        for (int rr = 0; rr < 4; ++rr) {
-                            const bool rin = in && RPT * iq + rr < I;
-                            raw[u][rr][j] = rin ? Y[a + (rin ? rr : 0)] : 0.f;
-                        }
-                    }
+                    // 4-byte alignment suffices (ANYI: rows of any length)
+                    const f32x4u v = *reinterpret_cast<const f32x4u *>(Y + a);
+                    raw[u][0][j] = in ? v.x : 0.f;
+                    raw[u][1][j] = in ? v.y : 0.f;
+                    raw[u][2][j] = in ? v.z : 0.f;
+                    raw[u][3][j] = in ? v.w : 0.f;
                 } else {
                     const float v = Y[a];
                     raw[u][0][j] = in ? v : 0.f;
