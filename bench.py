@@ -84,6 +84,13 @@ def main():
     ap.add_argument("--kernels-only", action="store_true",
                     help="run only the dominant kernels a few times (for rocprofv3 counter passes): "
                          "512^3 mode-1 TTM and Gram, a 512 MiB copy, the skinny mode-1 Grams of 160^4 and 48^5")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="run only the batched workload with the tiles of --batch-tiles, --batch-reps "
+                         "times (no autotuning, graph or one-by-one runs; for rocprofv3 passes)")
+    ap.add_argument("--batch-tiles", default="64,4,1",
+                    help="Gram workgroups per CU, Gram tile cap, TTM rows per wave for --batch-only")
+    ap.add_argument("--batch-recipe", default="bf16x6,bf16x3",
+                    help="Gram and TTM precisions for --batch-only (the default run's headline recipe)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the multi-GPU "
@@ -96,6 +103,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.kernels_only:
         kernels_only(api, torch, dev)
+        return
+    if args.batch_only:
+        batch_only(args, api, torch, dev)
         return
     w = wl.C2
     t0 = time.time()
@@ -678,6 +688,26 @@ def kernels_only(api, torch, dev, reps=5):
         del Xs
     torch.cuda.synchronize()
     log("[bench] kernels-only pass done")
+
+
+def batch_only(args, api, torch, dev):
+    """The 256-tensor batch alone under fixed tiles, --batch-reps runs, each
+    checked (for rocprofv3 trace and counter passes)."""
+    tiles = tuple(int(v) for v in args.batch_tiles.split(","))
+    shapes, xs = wl.batch_tensors(args.batch, workers=min(16, os.cpu_count() or 1))
+    xd = [api.to_device(x, dev) for x in xs]
+    del xs
+    xp = torch.tensor([x.data_ptr() for x in xd], dtype=torch.int64, device=dev)
+    gp, tp = args.batch_recipe.split(",")
+    plan = api.BatchPlan(shapes, gp, tp, tiles=tiles)
+    G, U, cp, up = plan.outputs(dev)
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    for k in range(args.batch_reps):
+        t = time.perf_counter()
+        plan.run(xp, cp, up, ws)
+        torch.cuda.synchronize()
+        plan.check(ws)
+        log(f"[bench] batch-only run {k}: {(time.perf_counter() - t) * 1e3:.2f} ms (tiles {tiles}, {gp}/{tp})")
 
 
 if __name__ == "__main__":
