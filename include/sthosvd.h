@@ -375,6 +375,33 @@ sth_status sthosvd_mode_step(int32_t order, const int64_t *dims, int32_t n, int6
                              sth_stream_t stream);
 
 /* ---------------------------------------------------------------------------
+ * Exhaustive solver selection (Sec. IV-B: timing both solvers per mode, the
+ * choice the learned selector and the decision tree stand in for).  For
+ * n = 1..N on the working tensor (X, then the kept step's output), the EIG
+ * and the ALS step of the mode (sthosvd_mode_step, ALS only where it can run)
+ * are each run once untimed and once timed with HIP events on the stream;
+ * a step that raises the numerical flag does not count; the faster step is
+ * kept and its output is the next mode's input.  dims/ranks: host, order
+ * entries; X: device, column-major, dtype; gram_prec, ttm_prec, als_iters
+ * as in sthosvd_desc.  solvers_out: host, order entries (STH_SOLVER_EIG or
+ * STH_SOLVER_ALS), usable as sthosvd_desc.per_mode; ms_out: host, 2 * order
+ * floats (EIG, ALS time per mode; -1 where the step did not count) or NULL.
+ * workspace: device, >= sthosvd_choose_exhaustive_workspace(...) bytes (0
+ * for invalid arguments); X is not modified.  Synchronizes the stream (it
+ * reads the timings), so it is a planning call, not part of a captured run.
+ * Errors: STH_ERR_INVALID, STH_ERR_UNSUPPORTED (no EIG step for a mode),
+ * STH_ERR_NOMEM, STH_ERR_NUMERIC (the EIG step raised the flag), STH_ERR_HIP.
+ * ------------------------------------------------------------------------- */
+size_t sthosvd_choose_exhaustive_workspace(int32_t order, const int64_t *dims, const int64_t *ranks,
+                                           int32_t dtype, int32_t gram_prec, int32_t ttm_prec,
+                                           int32_t als_iters);
+sth_status sthosvd_choose_exhaustive(int32_t order, const int64_t *dims, const int64_t *ranks,
+                                     int32_t dtype, int32_t gram_prec, int32_t ttm_prec,
+                                     int32_t als_iters, const void *X, int32_t *solvers_out,
+                                     float *ms_out, void *workspace, size_t workspace_bytes,
+                                     sth_stream_t stream);
+
+/* ---------------------------------------------------------------------------
  * Learned solver selector (the role of the Sec. IV decision tree, with a
  * small MLP cost model).  Features are the ten Table I quantities of a mode
  * (I_n, R_n, J_n, I_n^2, R_n^2, I_n R_n, R_n^2/I_n, R_n^2/J_n, I_n/J_n,

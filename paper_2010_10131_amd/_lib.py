@@ -95,6 +95,9 @@ SIGNATURES = {
     "sthosvd_mode_step_workspace": (_sz, [_i32, _i64p, _i32, _i64, _i32, _i32, _i32, _i32, _i32]),
     "sthosvd_mode_step": (ctypes.c_int, [_i32, _i64p, _i32, _i64, _i32, _i32, _i32, _i32, _i32, _vp, _vp,
                                          _vp, _vp, _vp, ctypes.c_uint64, _vp, _sz, _vp]),
+    "sthosvd_choose_exhaustive_workspace": (_sz, [_i32, _i64p, _i64p, _i32, _i32, _i32, _i32]),
+    "sthosvd_choose_exhaustive": (ctypes.c_int, [_i32, _i64p, _i64p, _i32, _i32, _i32, _i32, _vp, _i32p,
+                                                 ctypes.POINTER(ctypes.c_float), _vp, _sz, _vp]),
     "sthosvd_plan_batched": (ctypes.c_int, [ctypes.POINTER(sth_desc), _i32, ctypes.POINTER(_vp),
                                             ctypes.POINTER(_sz)]),
     "sthosvd_plan_batched_tiles": (ctypes.c_int, [ctypes.POINTER(sth_desc), _i32,

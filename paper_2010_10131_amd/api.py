@@ -415,6 +415,31 @@ def mode_step(Y: torch.Tensor, n: int, R: int, solver="eig", gram_prec="fp32", t
     return Z, U, ev, ws
 
 
+def choose_exhaustive(X: torch.Tensor, ranks: Sequence[int], gram_prec="fp32", ttm_prec="fp32",
+                      als_iters: int = 5):
+    """sthosvd_choose_exhaustive: the per-mode solver by timing both steps on
+    X (Sec. IV-B).  Returns (["eig" | "als"] per mode, [(eig_ms, als_ms)]
+    per mode, -1 where a step did not count).  Synchronizes the stream."""
+    _need(X, "X")
+    L = _lib.load()
+    N = X.dim()
+    dims, rk = i64arr(X.shape), i64arr(ranks)
+    dt = _dtype_code(X)
+    gp, tp = _prec(gram_prec), _prec(ttm_prec)
+    if dt == _lib.STH_F64:
+        gp = tp = PREC["fp64"]
+    nb = L.sthosvd_choose_exhaustive_workspace(N, dims, rk, dt, gp, tp, als_iters)
+    if nb == 0:
+        raise _lib.SthError(_lib.STH_ERR_INVALID, L.sth_last_error().decode())
+    ws = _ws(nb, X.device)
+    out = (ctypes.c_int32 * N)()
+    ms = (ctypes.c_float * (2 * N))()
+    check(L.sthosvd_choose_exhaustive(N, dims, rk, dt, gp, tp, als_iters, ctypes.c_void_p(X.data_ptr()), out,
+                                      ms, ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream()))
+    names = ["eig", "als"]
+    return [names[v] for v in out], [(ms[2 * n], ms[2 * n + 1]) for n in range(N)]
+
+
 # -------------------------------------------------- learned selector ----
 
 def selector_num_params() -> int:

@@ -929,6 +929,149 @@ extern "C" sth_status sthosvd_mode_step(int32_t order, const int64_t *dims, int3
     return exec_step(*pl, pl->steps[0], Y, Z, U, eigvals, als_init, seed, w, s);
 }
 
+// ------------------------------------------------- exhaustive selection ----
+
+namespace {
+struct ExhLayout {
+    size_t step, zbuf, u, ev, total;
+};
+// [step workspace][three tensor buffers: the working tensor and the two
+// steps' outputs][U][eigvals]
+sth_status exh_layout(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype,
+                      int32_t gram_prec, int32_t ttm_prec, int32_t als_iters, ExhLayout *L) {
+    sth_status st;
+    if ((st = check_shape(order, dims))) return st;
+    if (!ranks) return fail(STH_ERR_INVALID, "ranks is NULL");
+    const size_t esz = dtype == STH_F64 ? 8 : 4;
+    std::vector<int64_t> cur(dims, dims + order);
+    size_t step = 0, zmax = 0, umax = 0, rmax = 0;
+    for (int n = 0; n < order; ++n) {
+        if (ranks[n] < 1 || ranks[n] > cur[n]) return fail(STH_ERR_INVALID, "ranks[%d] out of range", n);
+        const size_t be = sthosvd_mode_step_workspace(order, cur.data(), n, ranks[n], dtype, gram_prec, ttm_prec,
+                                                      STH_SOLVER_EIG, als_iters);
+        if (be == 0) {
+            const std::string why = sth_last_error();
+            return fail(STH_ERR_UNSUPPORTED, "mode %d: no EIG step (%s)", n, why.c_str());
+        }
+        const size_t ba = sthosvd_mode_step_workspace(order, cur.data(), n, ranks[n], dtype, gram_prec, ttm_prec,
+                                                      STH_SOLVER_ALS, als_iters);
+        step = std::max(step, std::max(be, ba));
+        umax = std::max(umax, (size_t)(cur[n] * ranks[n]) * 8);
+        rmax = std::max(rmax, (size_t)ranks[n] * 8);
+        cur[n] = ranks[n];
+        size_t z = esz;
+        for (int k = 0; k < order; ++k) z *= (size_t)cur[k];
+        zmax = std::max(zmax, z);
+    }
+    L->step = align_up(step);
+    L->zbuf = align_up(zmax);
+    L->u = align_up(umax);
+    L->ev = align_up(rmax);
+    L->total = L->step + 3 * L->zbuf + L->u + L->ev;
+    return STH_OK;
+}
+}  // namespace
+
+extern "C" size_t sthosvd_choose_exhaustive_workspace(int32_t order, const int64_t *dims, const int64_t *ranks,
+                                                      int32_t dtype, int32_t gram_prec, int32_t ttm_prec,
+                                                      int32_t als_iters) {
+    ExhLayout L;
+    if (exh_layout(order, dims, ranks, dtype, gram_prec, ttm_prec, als_iters, &L)) return 0;
+    return L.total;
+}
+
+extern "C" sth_status sthosvd_choose_exhaustive(int32_t order, const int64_t *dims, const int64_t *ranks,
+                                                int32_t dtype, int32_t gram_prec, int32_t ttm_prec,
+                                                int32_t als_iters, const void *X, int32_t *solvers_out,
+                                                float *ms_out, void *ws, size_t ws_bytes,
+                                                sth_stream_t stream) {
+    ExhLayout L;
+    sth_status st = exh_layout(order, dims, ranks, dtype, gram_prec, ttm_prec, als_iters, &L);
+    if (st) return st;
+    if ((st = check_ptr(X, "X")) || (st = check_ptr(ws, "ws"))) return st;
+    if (!solvers_out) return fail(STH_ERR_INVALID, "solvers_out is NULL");
+    if (ws_bytes < L.total) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, L.total);
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    char *const zb[3] = {w + L.step, w + L.step + L.zbuf, w + L.step + 2 * L.zbuf};
+    double *const U = (double *)(w + L.step + 3 * L.zbuf);
+    double *const ev = (double *)(w + L.step + 3 * L.zbuf + L.u);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0), "event");
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(STH_ERR_HIP, "event");
+    }
+    std::vector<int64_t> cur(dims, dims + order);
+    const void *Y = X;
+    int yi = -1;   // buffer holding the working tensor (-1: X)
+    st = STH_OK;
+    for (int n = 0; n < order && st == STH_OK; ++n) {
+        float ms[2] = {-1.f, -1.f};
+        int ob[2], m = 0;   // the two steps' outputs: the buffers other than the input
+        for (int b = 0; b < 3 && m < 2; ++b)
+            if (b != yi) ob[m++] = b;
+        for (int sv = 0; sv < 2; ++sv) {
+            const int32_t solver = sv == 0 ? STH_SOLVER_EIG : STH_SOLVER_ALS;
+            // one untimed run (first-touch and code loading), then one timed
+            sth_status r = sthosvd_mode_step(order, cur.data(), n, ranks[n], dtype, gram_prec, ttm_prec, solver,
+                                             als_iters, Y, zb[ob[sv]], U, sv == 0 ? ev : nullptr, nullptr, 0, w,
+                                             L.step, stream);
+            if (r == STH_OK) {
+                hipEventRecord(e0, s);
+                r = sthosvd_mode_step(order, cur.data(), n, ranks[n], dtype, gram_prec, ttm_prec, solver, als_iters,
+                                      Y, zb[ob[sv]], U, sv == 0 ? ev : nullptr, nullptr, 0, w, L.step, stream);
+                hipEventRecord(e1, s);
+            }
+            if (r != STH_OK) {
+                if (sv == 0) {   // the EIG step must run
+                    st = r;
+                    break;
+                }
+                continue;        // ALS cannot run this mode
+            }
+            if (hipEventSynchronize(e1) != hipSuccess) {
+                st = fail(STH_ERR_HIP, "event sync");
+                break;
+            }
+            // a step that raised the numerical flag (e.g. a broken-down ALS
+            // basis) does not count
+            sth_plan *pl = nullptr;
+            size_t need = 0;
+            int64_t flag = 0;
+            if (mode_step_plan(order, cur.data(), n, ranks[n], dtype, gram_prec, ttm_prec, solver, als_iters, &pl,
+                               &need) == STH_OK) {
+                const size_t off = pl->o_flag;
+                delete pl;
+                if (hipMemcpy(&flag, w + off, sizeof(flag), hipMemcpyDeviceToHost) != hipSuccess) {
+                    st = fail(STH_ERR_HIP, "flag read");
+                    break;
+                }
+            }
+            float t = 0.f;
+            hipEventElapsedTime(&t, e0, e1);
+            if (flag == 0) ms[sv] = t;
+            else if (sv == 0) {
+                st = fail(STH_ERR_NUMERIC, "mode %d: the EIG step raised numeric flag %lld", n, (long long)flag);
+                break;
+            }
+        }
+        if (st != STH_OK) break;
+        const int pick = (ms[1] >= 0.f && ms[1] < ms[0]) ? 1 : 0;
+        solvers_out[n] = pick == 0 ? STH_SOLVER_EIG : STH_SOLVER_ALS;
+        if (ms_out) {
+            ms_out[2 * n] = ms[0];
+            ms_out[2 * n + 1] = ms[1];
+        }
+        yi = ob[pick];
+        Y = zb[yi];
+        cur[n] = ranks[n];
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return st;
+}
+
 // ----------------------------------------------------- learned selector ----
 
 extern "C" int32_t sth_selector_num_params(void) { return SEL_NPARAM; }

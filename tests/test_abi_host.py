@@ -248,3 +248,19 @@ def test_hooi_rejects_bad_arguments_before_launch(lib):
     assert lib.sth_hooi(3, dims, ranks, 0, 1, 1, *args, 1, vp(0x6000), need, None) == _lib.STH_ERR_INVALID
     assert lib.sth_hooi(3, dims, ranks, 1, 1, 1, vp(0x4000), None, vp(0x5000), 1, vp(0x6000), need,
                         None) == _lib.STH_ERR_INVALID
+
+
+def test_exhaustive_selection_validates_before_launch(lib):
+    from paper_2010_10131_amd import _lib
+    dims, ranks = _lib.i64arr([64, 32, 16]), _lib.i64arr([8, 4, 4])
+    nb = lib.sthosvd_choose_exhaustive_workspace(3, dims, ranks, _lib.STH_F32, 1, 1, 5)
+    # at least the three tensor buffers of the largest intermediate (64 x 32 x 16 -> 8 x 32 x 16)
+    assert nb >= 3 * 8 * 32 * 16 * 4
+    assert lib.sthosvd_choose_exhaustive_workspace(3, dims, _lib.i64arr([65, 4, 4]), _lib.STH_F32, 1, 1, 5) == 0
+    assert lib.sthosvd_choose_exhaustive_workspace(3, dims, None, _lib.STH_F32, 1, 1, 5) == 0
+    out = (ctypes.c_int32 * 3)()
+    assert lib.sthosvd_choose_exhaustive(3, dims, ranks, _lib.STH_F32, 1, 1, 5, None, out, None, None, 0,
+                                         None) == _lib.STH_ERR_INVALID
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: the size check fails first
+    assert lib.sthosvd_choose_exhaustive(3, dims, ranks, _lib.STH_F32, 1, 1, 5, fake, out, None, fake, nb - 1,
+                                         None) == _lib.STH_ERR_NOMEM

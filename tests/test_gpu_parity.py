@@ -526,6 +526,30 @@ def test_als_fp64_matches_oracle(api, variant_dims, ranks, per_mode):
         np.testing.assert_allclose(Un[n] @ Un[n].T, Uo[n] @ Uo[n].T, atol=1e-9)
 
 
+def test_exhaustive_selection_keeps_the_faster_step_and_matches_oracle(api):
+    """sthosvd_choose_exhaustive (Sec. IV-B): every mode's choice is the
+    faster of the two timed steps that counted, X is left untouched, and the
+    decomposition planned with those choices matches the oracle run with the
+    same per-mode methods and ALS initial guesses."""
+    import torch
+    dims, ranks = (40, 36, 30, 24), (6, 5, 4, 3)
+    X = wl.lowrank_plus_noise(dims, ranks, "none", 1e-3, 91, "float64")
+    Xd = api.to_device(X)
+    X0 = Xd.clone()
+    choice, ms = api.choose_exhaustive(Xd, ranks, "fp64", "fp64")
+    assert torch.equal(Xd, X0)
+    assert len(choice) == len(dims)
+    for c, (te, ta) in zip(choice, ms):
+        assert te > 0
+        assert c == ("als" if 0 <= ta < te else "eig"), (choice, ms)
+    L0 = [wl.gaussian_init(d, r, 9, n) for n, (d, r) in enumerate(zip(dims, ranks))]
+    G, U, _ = api.sthosvd(Xd, ranks, "fp64", "fp64", per_mode=choice, als_init=L0)
+    Go, Uo, _ = oracle.sthosvd(X, ranks, methods=[0 if c == "eig" else 1 for c in choice], L0=L0,
+                               als_variant=1)
+    t1, t2, _, Un = t1_t2(api, X, G, U, Go, Uo)
+    assert t1 <= 1e-10 and t2 <= 1e-10, (t1, t2)
+
+
 def test_large_first_mode_takes_als_and_matches_oracle(api):
     """An Air-Quality-like first mode (I_1 = 30648, beyond the eigensolver's
     512): the plan takes ALS there under either selector and EIG for the
