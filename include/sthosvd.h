@@ -346,9 +346,12 @@ sth_status tucker_reconstruct(int32_t order, const int64_t *dims, const int64_t 
 
 /* Relative-error terms of a decomposition (Sec. VI-B metric): writes
  * out[0] = ||X - X^||_F^2 and out[1] = ||X||_F^2 (device, 2 FP64), both
- * accumulated in FP64, with X^ the reconstruction of (G, U).  The
- * reconstruction is formed in ws (tucker_reconstruct_workspace bytes plus
- * prod dims elements of dtype). */
+ * accumulated in FP64 in a fixed order, with X^ the reconstruction of
+ * (G, U) (each value rounded to dtype, as tucker_reconstruct stores it).
+ * The expansions of modes 1 .. N-1 run as in tucker_reconstruct; the last
+ * one is fused with the sums, so X^ is never stored and X is read once.
+ * ws: tucker_reconstruct_workspace bytes plus the fused step's partial sums
+ * (tucker_error_workspace). */
 size_t tucker_error_workspace(int32_t order, const int64_t *dims, const int64_t *ranks,
                               int32_t dtype);
 sth_status tucker_error(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype,

@@ -830,10 +830,10 @@ extern "C" sth_status tucker_reconstruct(int32_t order, const int64_t *dims, con
 
 extern "C" size_t tucker_error_workspace(int32_t order, const int64_t *dims, const int64_t *ranks, int32_t dtype) {
     if (check_shape(order, dims) || !ranks) return 0;
-    size_t numel = 1;
-    for (int k = 0; k < order; ++k) numel *= (size_t)dims[k];
-    return tucker_reconstruct_workspace(order, dims, ranks, dtype) + align_up(numel * esize(dtype)) +
-           align_up(SUMSQ_BLOCKS * sizeof(double));
+    // the reconstruction's intermediates and factor split, then the fused
+    // last expansion's partial sums (X^ itself is never stored)
+    return tucker_reconstruct_workspace(order, dims, ranks, dtype) +
+           align_up(ttm_err_part_doubles(dims[order - 1]) * sizeof(double));
 }
 
 extern "C" sth_status tucker_error(int32_t order, const int64_t *dims, const int64_t *ranks,
@@ -846,15 +846,37 @@ extern "C" sth_status tucker_error(int32_t order, const int64_t *dims, const int
     if ((st = check_ptr(X, "X")) || (st = check_ptr(out, "out"))) return st;
     size_t need = tucker_error_workspace(order, dims, ranks, dtype);
     if (ws_bytes < need) return fail(STH_ERR_NOMEM, "workspace %zu < %zu", ws_bytes, need);
-    size_t rw = tucker_reconstruct_workspace(order, dims, ranks, dtype);
-    size_t numel = 1;
-    for (int k = 0; k < order; ++k) numel *= (size_t)dims[k];
-    char *xh = (char *)ws + rw;
-    double *part = (double *)(xh + align_up(numel * esize(dtype)));
-    if ((st = tucker_reconstruct(order, dims, ranks, dtype, prec, G, U, xh, ws, rw, stream))) return st;
+    if (!U) return fail(STH_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < order; ++k) {
+        if (ranks[k] < 1 || ranks[k] > dims[k]) return fail(STH_ERR_INVALID, "ranks[%d] out of range", k);
+        if ((st = check_ptr(U[k], "U[n]"))) return st;
+    }
+    if ((st = check_dtype_prec(dtype, prec, "prec")) || (st = check_ptr(G, "G")) || (st = check_ptr(ws, "ws")))
+        return st;
+    // the expansions of modes 1 .. N-1 as tucker_reconstruct runs them, the
+    // last one fused with the sums: X^ is never written
+    const size_t rw = tucker_reconstruct_workspace(order, dims, ranks, dtype);
+    double *part = (double *)((char *)ws + rw);
+    size_t a, b;
+    recon_sizes(order, dims, ranks, a, b);
+    char *bufA = (char *)ws, *bufB = bufA + align_up(a * esize(dtype));
+    void *uq = bufB + align_up(b * esize(dtype));
     hipStream_t s = (hipStream_t)stream;
-    HIPCHK(sumsq_launch(dtype, X, xh, (int64_t)numel, out, part, nullptr, s), "diff");
-    HIPCHK(sumsq_launch(dtype, X, nullptr, (int64_t)numel, out + 1, part, nullptr, s), "norm");
+    std::vector<int64_t> cur(ranks, ranks + order);
+    const void *src = G;
+    for (int n = 0; n < order; ++n) {
+        int64_t L, I, M;
+        lim(order, cur.data(), n, L, I, M);
+        HIPCHK(ttm_prep_u(U[n], ranks[n], dims[n], 1, prec, uq, s), "error prep");
+        if (n == order - 1) {
+            HIPCHK(ttm_err_launch(dtype, prec, src, uq, X, L, ranks[n], dims[n], M, part, out, s), "error ttm");
+            break;
+        }
+        void *dst = n % 2 == 0 ? (void *)bufA : (void *)bufB;
+        HIPCHK(ttm_launch(dtype, prec, src, uq, dst, L, ranks[n], dims[n], M, s), "error expand");
+        cur[n] = dims[n];
+        src = dst;
+    }
     return STH_OK;
 }
 

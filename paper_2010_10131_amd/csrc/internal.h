@@ -21,6 +21,12 @@ int device_cu_count();
 size_t ttm_prep_bytes(int64_t K, int64_t Rout, int prec);
 hipError_t ttm_prep_u(const double *U, int64_t K, int64_t Rout, int transpose, int prec, void *out,
                       hipStream_t s);
+// The TTM of a reconstruction's last expansion fused with its error sums:
+// out[0] = sum (X - Z)^2, out[1] = sum X^2 (FP64, device) with Z never stored;
+// part: device, ttm_err_part_doubles(Rout) doubles.
+size_t ttm_err_part_doubles(int64_t Rout);
+hipError_t ttm_err_launch(int dtype, int prec, const void *Y, const void *Uq, const void *X, int64_t L, int64_t K,
+                          int64_t Rout, int64_t M, double *part, double *out, hipStream_t s);
 hipError_t ttm_launch(int dtype, int prec, const void *Y, const void *Uq, void *Z, int64_t L,
                       int64_t K, int64_t Rout, int64_t M, hipStream_t s);
 // the library-held scratch of ttm_mode_n_noalloc (its size, and its address on

@@ -72,6 +72,43 @@ __global__ __launch_bounds__(64 * WAVES) void ttm_kernel(
                                                     nrowblocks, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
+// The TTM fused with the error sums of a reconstruction (nothing stored):
+// per-workgroup sums of (X - Z)^2 and X^2 into epart.
+template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void ttm_err_kernel(
+    const T *__restrict__ Y, const uint4 *__restrict__ Uq, const T *__restrict__ X, int64_t L, int64_t K,
+    int64_t Rout, int64_t P, int nchunks, int ntiles, int64_t nrowblocks, double *__restrict__ epart) {
+    ttm_body<T, PREC, NT, RTB, CONTIG, ULDS, WAVES, 1, false, true>(Y, Uq, nullptr, L, K, Rout, P, nchunks, ntiles,
+                                                                   nrowblocks, blockIdx.x, gridDim.x, blockIdx.y,
+                                                                   X, epart);
+}
+
+// out[0], out[1] = the sums of the n (d, x) pairs: 256 threads each sum a
+// strided subset in order, then a fixed tree
+__global__ __launch_bounds__(256) void sum_pairs_kernel(const double *__restrict__ part, int64_t n,
+                                                        double *__restrict__ out) {
+    __shared__ double sa[256], sb[256];
+    double a = 0.0, b = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        a += part[2 * i];
+        b += part[2 * i + 1];
+    }
+    sa[threadIdx.x] = a;
+    sb[threadIdx.x] = b;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            sa[threadIdx.x] += sa[threadIdx.x + o];
+            sb[threadIdx.x] += sb[threadIdx.x + o];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sa[0];
+        out[1] = sb[0];
+    }
+}
+
 template <int PREC, int NT, int CPW, bool FULL>
 __global__ __launch_bounds__(64 * KS_WAVES) void ttm_ks_kernel(
     const float *__restrict__ Y, const uint4 *__restrict__ Uq, float *__restrict__ Z, int64_t K,
@@ -220,7 +257,81 @@ hipError_t launch_ttm_p(const T *Y, const uint4 *Uq, T *Z, int64_t L, int64_t K,
     return launch_ttm_r<T, PREC, 4>(Y, Uq, Z, L, K, Rout, M, s);
 }
 
+// ---- the TTM fused with the reconstruction error ----
+constexpr int64_t TTM_ERR_WGS = 1024;   // workgroups per r-block at most (partial sums stay small)
+
+int ttm_err_rtb(int64_t Rout) {
+    const int64_t ntiles = (Rout + 15) / 16;
+    return ntiles <= 1 ? 1 : (ntiles <= 2 ? 2 : 4);
+}
+
+template <typename T, int PREC, int RTB>
+hipError_t launch_ttm_err_r(const T *Y, const uint4 *Uq, const T *X, int64_t L, int64_t K, int64_t Rout,
+                            int64_t M, double *part, double *out, hipStream_t s) {
+    constexpr int NT = (PREC == P_FP64) ? (RTB == 1 ? 2 : 1) : (RTB == 1 ? 4 : 2);
+    const int64_t P = L * M;
+    const int nchunks = (int)((K + KC - 1) / KC);
+    const int ntiles = (int)((Rout + 15) / 16);
+    const int nrb = (ntiles + RTB - 1) / RTB;
+    const int64_t nrowblocks = (P + 16 * NT - 1) / (16 * NT);
+    const size_t lds = (size_t)nchunks * RTB * Frag<PREC>::NQ * 64 * 16;
+    const bool ulds = lds <= TTM_LDS_MAX;
+    int64_t wgs = std::min<int64_t>(TTM_ERR_WGS, (nrowblocks + TTM_WAVES - 1) / TTM_WAVES);
+    if (ulds) {
+        const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(2, (160 * 1024) / std::max<size_t>(lds, 1)));
+        wgs = std::min<int64_t>(wgs, (int64_t)device_cu_count() * per_cu);
+    }
+    if (wgs < 1) wgs = 1;
+    const bool contig = L == 1;
+    hipError_t e;
+    auto go = [&](auto kern, size_t lb) -> hipError_t {
+        if (lb > 64 * 1024) {
+            hipError_t r = hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lb);
+            if (r != hipSuccess) return r;
+        }
+        hipLaunchKernelGGL(kern, dim3((unsigned)wgs, (unsigned)nrb), dim3(64 * TTM_WAVES), lb, s, Y, Uq, X, L, K,
+                           Rout, P, nchunks, ntiles, nrowblocks, part);
+        return hipGetLastError();
+    };
+    if (ulds) e = contig ? go(ttm_err_kernel<T, PREC, NT, RTB, true, true, TTM_WAVES>, lds)
+                         : go(ttm_err_kernel<T, PREC, NT, RTB, false, true, TTM_WAVES>, lds);
+    else e = contig ? go(ttm_err_kernel<T, PREC, NT, RTB, true, false, TTM_WAVES>, 0)
+                    : go(ttm_err_kernel<T, PREC, NT, RTB, false, false, TTM_WAVES>, 0);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(sum_pairs_kernel, dim3(1), dim3(256), 0, s, part, wgs * nrb, out);
+    return hipGetLastError();
+}
+
+template <typename T, int PREC>
+hipError_t launch_ttm_err_p(const T *Y, const uint4 *Uq, const T *X, int64_t L, int64_t K, int64_t Rout,
+                            int64_t M, double *part, double *out, hipStream_t s) {
+    switch (ttm_err_rtb(Rout)) {
+        case 1: return launch_ttm_err_r<T, PREC, 1>(Y, Uq, X, L, K, Rout, M, part, out, s);
+        case 2: return launch_ttm_err_r<T, PREC, 2>(Y, Uq, X, L, K, Rout, M, part, out, s);
+        default: return launch_ttm_err_r<T, PREC, 4>(Y, Uq, X, L, K, Rout, M, part, out, s);
+    }
+}
+
 }  // namespace
+
+size_t ttm_err_part_doubles(int64_t Rout) {
+    const int64_t ntiles = (Rout + 15) / 16, rtb = ttm_err_rtb(Rout);
+    return (size_t)(2 * TTM_ERR_WGS * ((ntiles + rtb - 1) / rtb));
+}
+
+hipError_t ttm_err_launch(int dtype, int prec, const void *Y, const void *Uq, const void *X, int64_t L, int64_t K,
+                          int64_t Rout, int64_t M, double *part, double *out, hipStream_t s) {
+    const uint4 *uq = (const uint4 *)Uq;
+    if (dtype == DT_F64)
+        return launch_ttm_err_p<double, P_FP64>((const double *)Y, uq, (const double *)X, L, K, Rout, M, part, out, s);
+    const float *y = (const float *)Y, *x = (const float *)X;
+    switch (prec) {
+        case P_FP64: return launch_ttm_err_p<float, P_FP64>(y, uq, x, L, K, Rout, M, part, out, s);
+        case P_FP32: return launch_ttm_err_p<float, P_FP32>(y, uq, x, L, K, Rout, M, part, out, s);
+        case P_BF16X3: return launch_ttm_err_p<float, P_BF16X3>(y, uq, x, L, K, Rout, M, part, out, s);
+        default: return launch_ttm_err_p<float, P_BF16X6>(y, uq, x, L, K, Rout, M, part, out, s);
+    }
+}
 
 hipError_t ttm_launch(int dtype, int prec, const void *Y, const void *Uq, void *Z, int64_t L,
                       int64_t K, int64_t Rout, int64_t M, hipStream_t s) {

@@ -39,11 +39,17 @@ __device__ __forceinline__ void ttm_load_chunk(const T *__restrict__ Y, int64_t 
 // PF = chunks of Y in flight per wave (1 or 2).
 // ZT (with CONTIG): the output is stored transposed, Z(r, p) at p + P r, which
 // puts the next mode first in the batched path's rotated layout.
-template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES, int PF = 1, bool ZT = false>
+// ERR: nothing is stored; each output value z (rounded to T, as a store
+// would) is compared with Xe at the address it would have been stored to, and
+// the workgroup's sums of (Xe - z)^2 and Xe^2 (FP64) go to epart[2 wg_id],
+// epart[2 wg_id + 1] (wg_id = blockIdx.y * gridDim.x + blockIdx.x).
+template <typename T, int PREC, int NT, int RTB, bool CONTIG, bool ULDS, int WAVES, int PF = 1, bool ZT = false,
+          bool ERR = false>
 __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *__restrict__ Uq,
                                          T *__restrict__ Z, int64_t L, int64_t K, int64_t Rout,
                                          int64_t P, int nchunks, int ntiles, int64_t nrowblocks,
-                                         int64_t wg, int64_t nwg, int rb) {
+                                         int64_t wg, int64_t nwg, int rb, const T *__restrict__ Xe = nullptr,
+                                         double *__restrict__ epart = nullptr) {
     if (CONTIG) L = 1;  // the contiguous variant is the L = 1 view; a constant for the compiler
     constexpr int NQ = Frag<PREC>::NQ;
     typedef typename Acc<PREC>::type AccT;
@@ -70,6 +76,7 @@ __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *_
         __syncthreads();
     }
 
+    double esq_d = 0.0, esq_x = 0.0;   // ERR: this lane's sums
     const int64_t wstride = nwg * WAVES;
     for (int64_t wb = wg * WAVES + wave; wb < nrowblocks; wb += wstride) {
         const int64_t p0 = wb * (16 * NT);
@@ -174,6 +181,21 @@ __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *_
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if (!pvalid[nt]) continue;
+            if constexpr (ERR) {
+#pragma unroll
+                for (int rt = 0; rt < RTB; ++rt)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int64_t r = (int64_t)(rt0 + rt) * 16 + drow<PREC>(g, v);
+                        if (r < Rout) {
+                            const double x = (double)Xe[zoff[nt] + L * r];
+                            const double d = x - (double)(T)acc[nt][rt][v];
+                            esq_d += d * d;
+                            esq_x += x * x;
+                        }
+                    }
+                continue;
+            }
             if constexpr (ZT) {
                 const int64_t p = p0 + 16 * nt + (lane & 15);
 #pragma unroll
@@ -203,7 +225,31 @@ __device__ __forceinline__ void ttm_body(const T *__restrict__ Y, const uint4 *_
             }
         }
     }
+    if constexpr (ERR) {
+        // fixed-order workgroup sums: lanes by xor shuffles, then waves in order
+        __shared__ double s_err[2][WAVES];
+        for (int o = 32; o > 0; o >>= 1) {
+            esq_d += __shfl_xor(esq_d, o);
+            esq_x += __shfl_xor(esq_x, o);
+        }
+        if (lane == 0) {
+            s_err[0][wave] = esq_d;
+            s_err[1][wave] = esq_x;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0, b = 0.0;
+            for (int w = 0; w < WAVES; ++w) {
+                a += s_err[0][w];
+                b += s_err[1][w];
+            }
+            const int64_t id = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+            epart[2 * id] = a;
+            epart[2 * id + 1] = b;
+        }
+    }
 }
+
 
 }  // namespace sth
 

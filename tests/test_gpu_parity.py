@@ -592,9 +592,13 @@ def test_fp32_data_recipes(api, gp, tp, t2max):
 # -------------------------------------------------------- reconstruction ----
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_reconstruct_and_error(api, prec):
+@pytest.mark.parametrize("dims,ranks", [((20, 14, 9), (5, 4, 3)), ((70, 45, 37), (9, 7, 5)),
+                                        ((24, 18, 12, 40), (4, 3, 5, 6))])
+def test_reconstruct_and_error(api, prec, dims, ranks):
+    """tucker_reconstruct against the oracle's reconstruction; tucker_error
+    (the last expansion fused with the sums, X^ never stored) against the
+    sums over the oracle's X^: several workgroups and r-blocks, ragged I_N."""
     dtype = "float64" if prec == "fp64" else "float32"
-    dims, ranks = (20, 14, 9), (5, 4, 3)
     G = randn(ranks, 1, dtype)
     U = [randn((d, r), 2 + d, "float64") for d, r in zip(dims, ranks)]
     Xh = api.to_numpy(api.tucker_reconstruct(api.to_device(G), [api.to_device(u) for u in U], prec))
