@@ -1,7 +1,12 @@
 // Batched st-HOSVD: many independent tensors decomposed together, one
-// launch per phase of a mode step for the whole batch:
-//   grouped Gram      every (tensor, row range, output block) workgroup of
-//                     one tile class in one grid, XCD-aware ids;
+// launch per phase of a mode step for the whole batch.  Every intermediate
+// is stored rotated (the TTM writes its output transposed), so the mode a
+// step contracts is always first and every step is the contiguous L = 1
+// view; after the last mode the core is in natural order.
+//   grouped Gram      per tile class one grid: the skinny class (I <= 160,
+//                     whole triangles per workgroup over column ranges) or
+//                     every (tensor, row range, output block) workgroup,
+//                     XCD-aware ids;
 //   grouped reduce    the FP64 partial blocks of every tensor;
 //   batched eigen     one workgroup per tensor: up to order 128 the direct
 //                     solver of teig_body.h (tridiagonalization, bisection,

@@ -88,7 +88,7 @@ struct BatchStep {
     int64_t part_off, S_off, uq_off, eig_off;
     int64_t kper, gram_wg;
     int32_t nkc, nbi, nblocks, wt;
-    int32_t nchunks, ntiles, rtb, contig;
+    int32_t nchunks, ntiles, rtb, contig;   // contig: 1 (every batched step is the L = 1 view)
     int32_t tensor, sib;   // sib: subspace block of the eigensolve (0: the direct solver)
 };
 struct BatchLaunch {
