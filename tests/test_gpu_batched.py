@@ -216,3 +216,37 @@ def test_batched_full_range_tensors_match_oracle(api):
         for n in range(3):
             u = api.to_numpy(U[t][n])
             np.testing.assert_allclose(u.T @ u, np.eye(r[n]), atol=1e-10)
+
+
+@pytest.mark.parametrize("shapes", [
+    [((150, 90), (12, 8)), ((33, 200), (5, 20)), ((64, 64), (8, 8))],
+    [((24, 30, 18, 20), (4, 5, 3, 4)), ((40, 12, 9, 33), (6, 3, 2, 5)), ((150, 10, 8, 6), (15, 3, 2, 2))],
+    [((12, 10, 9, 8, 11), (3, 2, 3, 2, 3)), ((20, 6, 7, 5, 9), (4, 2, 2, 2, 3))],
+])
+def test_batched_orders_2_4_5_match_oracle(api, shapes):
+    """The rotated layout for orders other than 3: each step contracts the
+    tensor's first index and writes its output transposed, so the core must
+    come out in natural order and every factor must belong to its mode;
+    checked against the oracle (reconstruction, core norm, and each factor's
+    subspace)."""
+    import torch
+    xs, xd, xp = make_batch(api, shapes, seed=33)
+    plan = api.BatchPlan(shapes, "fp64", "fp32")
+    G, U, cp, up = plan.outputs()
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+    plan.run(xp, cp, up, ws)
+    plan.check(ws)
+    for t, (d, r) in enumerate(shapes):
+        Go, Uo, _ = oracle.sthosvd(xs[t], r)
+        xn = np.linalg.norm(xs[t].astype(np.float64))
+        t2 = np.linalg.norm(recon(api, G[t], U[t]) - oracle.reconstruct(Go, Uo)) / xn
+        t1 = abs(np.linalg.norm(api.to_numpy(G[t])) - np.linalg.norm(Go)) / np.linalg.norm(Go)
+        assert t2 <= 1e-5 and t1 <= 1e-5, (t, d, r, t2, t1)
+        for n in range(len(d)):
+            u = api.to_numpy(U[t][n])
+            assert u.shape == (d[n], r[n])
+            np.testing.assert_allclose(u.T @ u, np.eye(r[n]), atol=1e-10)
+            # the leading vectors are unique up to sign only within the rank
+            # of the mode-n unfolding (earlier modes already truncated)
+            k = min(r[n], int(np.prod(r[:n])) * int(np.prod(d[n + 1:])))
+            np.testing.assert_allclose(u[:, :k] @ u[:, :k].T, Uo[n][:, :k] @ Uo[n][:, :k].T, atol=1e-5)
