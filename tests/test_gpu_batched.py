@@ -250,3 +250,23 @@ def test_batched_orders_2_4_5_match_oracle(api, shapes):
             # of the mode-n unfolding (earlier modes already truncated)
             k = min(r[n], int(np.prod(r[:n])) * int(np.prod(d[n + 1:])))
             np.testing.assert_allclose(u[:, :k] @ u[:, :k].T, Uo[n][:, :k] @ Uo[n][:, :k].T, atol=1e-5)
+
+
+def test_batched_tiny_sides_match_oracle(api):
+    """Sides of 1 to 3 (every loader's quad crosses the last row, skinny
+    triangles of one super tile, rank-1 modes) and a long last mode."""
+    import torch
+    shapes = [((2, 50, 40), (1, 5, 4)), ((64, 3, 1), (6, 2, 1)), ((3, 3, 300), (2, 2, 3)),
+              ((1, 70, 33), (1, 7, 4)), ((5, 7, 6), (2, 3, 2))]
+    xs, xd, xp = make_batch(api, shapes, seed=61)
+    for gp, tp in (("fp64", "fp32"), ("bf16x6", "bf16x3")):
+        plan = api.BatchPlan(shapes, gp, tp)
+        G, U, cp, up = plan.outputs()
+        ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device="cuda")
+        plan.run(xp, cp, up, ws)
+        plan.check(ws)
+        for t, (d, r) in enumerate(shapes):
+            Go, Uo, _ = oracle.sthosvd(xs[t], r)
+            xn = np.linalg.norm(xs[t].astype(np.float64))
+            t2 = np.linalg.norm(recon(api, G[t], U[t]) - oracle.reconstruct(Go, Uo)) / xn
+            assert t2 <= 1e-5, (gp, t, d, r, t2)
