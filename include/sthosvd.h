@@ -195,8 +195,13 @@ sth_status sthosvd_plan_batched(const sth_desc *descs, int32_t count, sth_batch_
 
 /* Tile choices of the batched kernels; a zero field takes its default.  They
  * change the work split only: the TTM results are bit-identical for every
- * choice, the Gram's split-K depth changes the order of its FP64 partial
- * sums (results agree to rounding).
+ * choice; the Gram's split (workgroups per CU, tile width) changes which
+ * products each FP32 accumulator sums before its FP64 flush and the order of
+ * the FP64 partial sums, so Grams agree to the rounding of the product
+ * precision and decompositions within its tolerance (reconstructions within
+ * 1e-5 of each other and of the FP64 oracle for split-bf16 recipes).  Modes
+ * with I_n <= 160 always take the skinny class (whole triangles per
+ * workgroup), whatever gram_wt_max says.
  *   gram_wg_per_cu    Gram workgroups aimed at per compute unit over the
  *                     whole batch (split-K depth), 1..64, default 4
  *   gram_wt_max       largest Gram output tile, in units of 32 rows: 1, 2
