@@ -365,3 +365,42 @@ def test_mlp_gradients_against_finite_differences(orc):
     b1 = [np.zeros(2)]
     _, g1, gb1 = orc.mlp_loss_grad(W1, b1, X, T)
     np.testing.assert_allclose(g1[0], (W1[0] @ X - T) @ X.T / 7, rtol=1e-12, atol=1e-14)
+
+
+def test_mlp_forward_tanh_pins(orc):
+    """The hidden activation pinned by properties of tanh itself, independent
+    of the oracle's backward pass: (1) saturation: pre-activations of size
+    >= 40 give exactly +-1, so a two-hidden-layer net reduces to
+    W3 sign(W2 sign(W1 X + b1) + b2) + b3; (2) small signal: tanh z = z - z^3/3
+    + O(z^5), so with inputs of size 1e-3 the net's deviation from the
+    linear map W2 W1 X + b2 is -W2 (W1 X)^3 / 3 to relative O(z^2) (a sigmoid,
+    ReLU or sine hidden layer fails one of the two)."""
+    rng = np.random.default_rng(17)
+    # (1) saturation through two hidden layers
+    W1 = rng.choice([-1.0, 1.0], size=(6, 4)) * 50.0
+    b1 = np.zeros(6)
+    W2 = rng.choice([-1.0, 1.0], size=(5, 6)) * 50.0
+    b2 = np.full(5, 25.0)                        # z2 = 50 * (odd count of +-1) + 25: |z2| >= 25
+    W3 = rng.standard_normal((2, 5))
+    b3 = rng.standard_normal(2)
+    X = rng.choice([-1.0, 1.0], size=(4, 9)) * rng.uniform(1.0, 2.0, size=(4, 9))
+    X[:, 0] = [1.0, 1.0, 1.0, 1.0]
+    z1 = W1 @ X
+    keep = np.all(np.abs(z1) >= 40.0, axis=0)    # columns whose every pre-activation saturates
+    assert keep.sum() >= 1
+    X = X[:, keep]
+    h1 = np.sign(W1 @ X)
+    h2 = np.sign(W2 @ h1 + b2[:, None])
+    assert np.all(np.abs(W2 @ h1 + b2[:, None]) >= 25.0)
+    Y = orc.mlp_forward([W1, W2, W3], [b1, b2, b3], X)
+    np.testing.assert_allclose(Y, W3 @ h2 + b3[:, None], rtol=0, atol=1e-13)
+    # (2) the cubic term of one hidden layer
+    V1 = rng.standard_normal((7, 3))
+    V2 = rng.standard_normal((2, 7))
+    c2 = rng.standard_normal(2)
+    Xs = rng.standard_normal((3, 11)) * 1e-3
+    z = V1 @ Xs
+    Ys = orc.mlp_forward([V1, V2], [np.zeros(7), c2], Xs)
+    dev = Ys - (V2 @ z + c2[:, None])
+    cubic = -V2 @ (z ** 3) / 3.0
+    assert np.max(np.abs(dev - cubic)) <= 1e-4 * np.max(np.abs(cubic)), (dev, cubic)
